@@ -1,0 +1,221 @@
+/*
+ * qsv — partitioned state-vector simulation on AMD MI355X (gfx950).
+ *
+ * C interface of the library.  It implements the hot path of "A Closeness
+ * Centrality-based Circuit Partitioner for Quantum Simulations"
+ * (arXiv:2509.14098):
+ *   - a circuit is a qubit count plus a flat ordered list of gates on given
+ *     qubits (paper Section 4.1);
+ *   - a p-qubit gate is a 2^p x 2^p unitary, i.e. a 2p-dimensional tensor of
+ *     extent 2 (Section 3.1, Eq. 8);
+ *   - a state of n qubits is 2^n complex amplitudes, i.e. an n-dimensional
+ *     tensor of extent 2 (Section 3.1, Eq. 7); qubit q is bit q of the
+ *     amplitude index (column-major stacking, Eq. 4);
+ *   - the planner builds the contraction graph, scores every gate by closeness
+ *     centrality and cuts the circuit into partitions of at most k local
+ *     qubits (Section 4.2, Eq. 10-13, Fig. 5), recursively for the register
+ *     level; each partition is then applied on the GPU as one fused sweep over
+ *     the amplitudes (Section 4.3).
+ * Expectation values, the adjoint gradient and batching are additions of this
+ * library; the paper has none of them.
+ *
+ * Conventions of every entry point:
+ *   - the return value is QSV_OK (0) or a negative qsv_status; on error
+ *     qsv_last_error() returns a message (thread-local) and no device work has
+ *     been queued, so outputs are untouched;
+ *   - device pointers are plain HIP device addresses owned by the caller
+ *     (e.g. torch tensors); host pointers are read during the call only;
+ *   - device work is queued on the context's stream and is asynchronous:
+ *     outputs are valid after the stream is synchronised;
+ *   - state vectors are complex64: interleaved (re, im) float pairs, 8 bytes
+ *     per amplitude, 2^n amplitudes per state, batches stored back to back.
+ */
+#ifndef QSV_PUBLIC_API_H_
+#define QSV_PUBLIC_API_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t qsv_status;
+#define QSV_OK 0
+#define QSV_E_ARG (-1)         /* invalid argument (null pointer, bad qubit, bad size) */
+#define QSV_E_RANGE (-2)       /* parameter index out of range / not a rotation */
+#define QSV_E_NOMEM (-3)       /* device or host allocation failed */
+#define QSV_E_DEVICE (-4)      /* HIP runtime error */
+#define QSV_E_STATE (-5)       /* call not valid for this plan (e.g. no gradient support) */
+#define QSV_E_UNSUPPORTED (-6) /* valid request outside what this build implements */
+
+/* Gate kinds: textbook / OpenQASM 2 definitions. */
+enum {
+    QSV_H = 1, QSV_X = 2, QSV_Y = 3, QSV_Z = 4, QSV_S = 5, QSV_SDG = 6, QSV_T = 7, QSV_TDG = 8, QSV_SX = 9,
+    QSV_RX = 10,  /* exp(-i a X / 2) */
+    QSV_RY = 11,  /* exp(-i a Y / 2) */
+    QSV_RZ = 12,  /* exp(-i a Z / 2) */
+    QSV_P = 13,   /* diag(1, e^{i a}) */
+    QSV_U3 = 14,  /* [[cos t/2, -e^{il} sin t/2], [e^{ip} sin t/2, e^{i(p+l)} cos t/2]] */
+    QSV_CX = 20, QSV_CY = 21, QSV_CZ = 22,
+    QSV_CP = 23,  /* diag(1, 1, 1, e^{i a}) */
+    QSV_SWAP = 24,
+    QSV_RZZ = 25, /* exp(-i a Z(x)Z / 2) */
+    QSV_MAT1 = 30, /* user 2x2 unitary in mat[0..7] */
+    QSV_MAT2 = 31  /* user 4x4 unitary in mat[0..31] */
+};
+
+/*
+ * One gate (296 bytes).  q0 is the target of a one-qubit gate and the control
+ * of CX/CY/CZ/CP (q1 the target); SWAP/RZZ/MAT2 act on (q0, q1), MAT2 on the
+ * local index j = b(q0) + 2 b(q1).  param >= 0 (RX, RY, RZ, RZZ only) takes
+ * the angle from theta[param] of the gate's circuit; otherwise angle[0] (U3:
+ * angle[0..2] = theta, phi, lambda).  mat holds MAT1/MAT2 matrices row-major
+ * as (re, im) pairs.
+ */
+typedef struct qsv_gate {
+    int32_t kind;
+    int32_t q0;
+    int32_t q1;
+    int32_t param;
+    double angle[3];
+    double mat[32];
+} qsv_gate;
+
+/* One Pauli string with a real weight: bit q of x_mask is set for X or Y on
+ * qubit q, bit q of z_mask for Z or Y. */
+typedef struct qsv_pauli_term {
+    double coeff;
+    uint64_t x_mask;
+    uint64_t z_mask;
+} qsv_pauli_term;
+
+typedef struct qsv_ctx qsv_ctx;
+typedef struct qsv_plan qsv_plan;
+
+/* Plan flags. */
+#define QSV_PLAN_GATE_BY_GATE 1u /* one gate per partition: the unfused baseline, same kernels */
+#define QSV_PLAN_GRAD 2u         /* keep what qsv_adjoint_grad needs (checkpoint layout) */
+
+/* Kernel tile shape: a workgroup of 2^log_threads threads holds a tile of
+ * 2^(reg_qubits + log_threads) amplitudes, reg_qubits of them per thread.
+ * All zero = library default. */
+typedef struct qsv_tile_config {
+    int32_t reg_qubits;  /* 1..5 */
+    int32_t log_threads; /* 6..10 */
+} qsv_tile_config;
+
+typedef struct qsv_plan_info {
+    int32_t n_qubits;
+    int32_t n_circuits;
+    int32_t k_local;         /* partition size in qubits actually used */
+    int32_t tile_qubits;     /* qubits per on-chip tile */
+    int32_t reg_qubits;
+    int32_t log_threads;
+    int64_t n_gates;
+    int64_t n_params;        /* total theta entries over all circuits */
+    int64_t n_partitions;    /* total over circuits */
+    int64_t n_stages;        /* register-level stages, total */
+    int64_t ckpt_bytes;      /* size of the checkpoint buffer qsv_apply may fill */
+    double flops_per_apply;  /* algorithmic flops of one qsv_apply */
+    double bytes_per_apply;  /* algorithmic HBM bytes of one qsv_apply (16 B/amplitude/sweep) */
+    double plan_seconds;     /* host time spent in qsv_partition */
+} qsv_plan_info;
+
+/* Last error message of the calling thread ("" if none). */
+const char *qsv_last_error(void);
+
+/*
+ * Bind a context to a HIP device and stream (stream may be NULL = the null
+ * stream of that device).  The context owns scratch memory (reduction
+ * partials, the adjoint's lambda state) and is freed by qsv_destroy.
+ * Errors: QSV_E_ARG (out null), QSV_E_DEVICE (no such device).
+ */
+qsv_status qsv_create(int32_t device, void *hip_stream, qsv_ctx **out);
+qsv_status qsv_destroy(qsv_ctx *ctx);
+/* Change the stream later calls are queued on. */
+qsv_status qsv_set_stream(qsv_ctx *ctx, void *hip_stream);
+
+/*
+ * Partition circuits (paper Section 4.1-4.3).  For each of n_circuits
+ * circuits (gates[circ_offsets[c] .. circ_offsets[c+1]); circ_offsets holds
+ * n_circuits + 1 non-decreasing offsets starting at 0): build the contraction graph and critical-path
+ * lengths, score every gate by closeness centrality (Eq. 10-13), cut the gate
+ * list into partitions of at most k_local local qubits with the greedy
+ * frontier sweep and its two locality exemptions (diagonal gates, non-local
+ * controls), repeat one level down for the register stages, and lower the
+ * result to device tables (uploaded when ctx is non-NULL; ctx == NULL gives a
+ * host-only plan usable with the introspection calls only).
+ * k_local == 0 chooses k and the tile shape by timing candidates on the
+ * device (autotuner, needs ctx).  tile may be NULL (default shape).
+ * The gate array is copied; it is not retained.  The plan is freed by
+ * qsv_plan_destroy.
+ * Errors: QSV_E_ARG (n_qubits < 1 or > 34, k_local < 0, qubit out of range,
+ * q0 == q1, unknown kind, bad offsets, a batched plan with n_qubits > 14),
+ * QSV_E_RANGE (param >= 0 on a non-rotation), QSV_E_NOMEM, QSV_E_DEVICE.
+ */
+qsv_status qsv_partition(qsv_ctx *ctx, int32_t n_qubits, const qsv_gate *gates, const int64_t *circ_offsets,
+                         int32_t n_circuits, int32_t k_local, uint32_t flags, const qsv_tile_config *tile,
+                         qsv_plan **out);
+qsv_status qsv_plan_destroy(qsv_plan *plan);
+qsv_status qsv_plan_get_info(const qsv_plan *plan, qsv_plan_info *out);
+/* Number of theta entries of circuit c and its offset in the packed theta array. */
+qsv_status qsv_plan_params(const qsv_plan *plan, int32_t circuit, int64_t *offset, int64_t *count);
+/*
+ * Introspection of partition p of circuit c (Section 4.3 partition tree):
+ * local_mask = its local qubit set S (|S| = min(k, n)), gates = its gate
+ * indices in execution order (at most cap written; *n_gates = the count).
+ * level 0 = the partition level, level 1 = the register stages of all
+ * partitions of circuit c in order (local_mask = the stage's register qubits).
+ */
+qsv_status qsv_plan_partition(const qsv_plan *plan, int32_t circuit, int32_t level, int64_t p,
+                              uint64_t *local_mask, int32_t *gates, int64_t cap, int64_t *n_gates);
+
+/*
+ * Apply the planned circuits in place: psi_b <- C_b(theta_b) psi_b on
+ * complex64[n_circuits][2^n] (the caller initialises psi, e.g. to |0..0>).
+ * theta_dev: float64 device array of qsv_plan_info.n_params entries (may be
+ * NULL when the plan has none); rotation matrices are formed on the device
+ * (cos/sin in float64, rounded to float32).  When ckpt_dev is non-NULL
+ * (single-circuit plans) the state after every partition but the last is also
+ * written to ckpt_dev + p * 2^n amplitudes (qsv_plan_info.ckpt_bytes) for
+ * qsv_adjoint_grad.
+ * Errors: QSV_E_ARG (null psi, theta missing), QSV_E_DEVICE.
+ */
+qsv_status qsv_apply(qsv_ctx *ctx, const qsv_plan *plan, const double *theta_dev, void *psi_dev,
+                     void *ckpt_dev);
+
+/*
+ * Expectation values out_b = sum_t coeff_t <psi_b|P_t|psi_b> for b < batch,
+ * computed with float64 accumulation into out_dev (float64[batch], device).
+ * H = one term with empty masks and coeff 1 gives the squared norm.
+ * Errors: QSV_E_ARG (n_qubits out of range, masks beyond n_qubits, nulls).
+ */
+qsv_status qsv_expect(qsv_ctx *ctx, const qsv_pauli_term *H, int32_t n_terms, int32_t n_qubits, int64_t batch,
+                      const void *psi_dev, double *out_dev);
+
+/*
+ * Adjoint gradient (reverse sweep over the partitions).  For every circuit b:
+ * energy_b = <psi_b|H|psi_b> and grad_b[j] = d energy_b / d theta_b[j]
+ * (parameters used by several rotations receive the sum of their terms).
+ * Single-circuit plans: psi_final_dev is the state qsv_apply produced and
+ * ckpt_dev the checkpoints it wrote; the plan must carry QSV_PLAN_GRAD.
+ * Batched plans (n_circuits > 1): forward, energy and adjoint run in one
+ * persistent launch from |0..0>; psi_final_dev and ckpt_dev are ignored and
+ * may be NULL.  grad_dev: float64[n_params], energy_dev: float64[n_circuits].
+ * Errors: QSV_E_STATE (no QSV_PLAN_GRAD or missing checkpoints), QSV_E_ARG.
+ */
+qsv_status qsv_adjoint_grad(qsv_ctx *ctx, const qsv_plan *plan, const qsv_pauli_term *H, int32_t n_terms,
+                            const double *theta_dev, const void *psi_final_dev, const void *ckpt_dev,
+                            double *energy_dev, double *grad_dev);
+
+/* Time-stamped launch counters of the last call on ctx (for benchmarks):
+ * average duration in ms of the sweep kernels of the last qsv_apply, measured
+ * with HIP events on the context stream when timing is enabled. */
+qsv_status qsv_set_timing(qsv_ctx *ctx, int32_t enable);
+qsv_status qsv_last_sweep_ms(qsv_ctx *ctx, double *total_ms, int64_t *n_launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QSV_PUBLIC_API_H_ */

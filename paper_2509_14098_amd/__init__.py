@@ -1,0 +1,16 @@
+"""qsv: partitioned state-vector simulation on AMD MI355X (gfx950).
+
+Python binding of the C interface declared in ``include/qsv.h``.  Every call
+marshals arguments and forwards them to ``libqsv.so``; all computation (graph
+analysis, partitioning, the GPU sweeps, reductions and gradients) happens in
+the native library.  torch provides device memory and the current stream.
+There is no fallback: if the native library is missing, importing the binding
+succeeds but every call raises.
+"""
+from .binding import (  # noqa: F401
+    QsvError, GATE_DTYPE, PAULI_DTYPE, KIND, PLAN_GATE_BY_GATE, PLAN_GRAD,
+    qsv_create, qsv_destroy, qsv_set_stream, qsv_partition, qsv_plan_destroy, qsv_plan_info,
+    qsv_plan_params, qsv_plan_partition, qsv_apply, qsv_expect, qsv_adjoint_grad,
+    qsv_set_timing, qsv_last_sweep_ms, library_path, load_library,
+)
+from .sim import Simulator, Plan, Energy  # noqa: F401

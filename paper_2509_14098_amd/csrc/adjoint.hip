@@ -1,0 +1,238 @@
+// Adjoint (reverse-sweep) gradient over the partitions.
+//
+// For partition p, walked from the last to the first: a workgroup loads the
+// tile of the checkpointed state after p (psi) and of lambda, then walks the
+// partition's register stages and gates backwards.  For a parameterised
+// rotation exp(-i a P / 2) it first adds Im <lambda|P|psi> over its amplitudes
+// (both states taken just after the gate; float64 products and sums), then
+// applies U^dagger to psi and to lambda.  lambda goes back to HBM, psi is
+// dropped (the next partition reloads its own checkpoint).  Per-wave partial
+// sums are written per (gate, tile, wave) and reduced in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include "gates.cuh"
+#include "kernels.h"
+
+namespace qsv {
+
+__device__ __forceinline__ double im_conj_mul(float2 l, float2 a) { return (double)l.x * a.y - (double)l.y * a.x; }
+__device__ __forceinline__ double re_conj_mul(float2 l, float2 a) { return (double)l.x * a.x + (double)l.y * a.y; }
+
+template <int R, int J>
+__device__ __forceinline__ double grad_pairs(const float2 (&a)[1 << R], const float2 (&l)[1 << R], bool y_gen)
+{
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < (1 << R); ++i) {
+        if (i & (1 << J)) continue;
+        const float2 a0 = a[i], a1 = a[i | (1 << J)], l0 = l[i], l1 = l[i | (1 << J)];
+        if (y_gen)  // Y: (Y psi)_0 = -i psi_1, (Y psi)_1 = i psi_0
+            acc += re_conj_mul(l1, a0) - re_conj_mul(l0, a1);
+        else        // X: (X psi)_0 = psi_1, (X psi)_1 = psi_0
+            acc += im_conj_mul(l0, a1) + im_conj_mul(l1, a0);
+    }
+    return acc;
+}
+
+// Im <lambda|P|psi> over this thread's amplitudes for the op's generator.
+template <int R>
+__device__ __forceinline__ double grad_term(const float2 (&a)[1 << R], const float2 (&l)[1 << R], const DevOp &o,
+                                            uint32_t tid, uint64_t base)
+{
+    double acc = 0.0;
+    if (o.gen == GEN_Z || o.gen == GEN_ZZ) {
+        uint32_t p = loc_pattern(o.a, tid, base);
+        if (o.gen == GEN_ZZ) p ^= loc_pattern(o.b, tid, base);
+#pragma unroll
+        for (int i = 0; i < (1 << R); ++i) {
+            const double v = im_conj_mul(l[i], a[i]);
+            acc += ((p >> i) & 1u) ? -v : v;
+        }
+    } else {
+        const bool y = o.gen == GEN_Y;
+        on_reg<R>(o.a & 0x3F, [&](auto J) __attribute__((always_inline)) { acc = grad_pairs<R, std::decay_t<decltype(J)>::value>(a, l, y); });
+    }
+    return acc;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+template <int LW>
+__device__ __forceinline__ void load_pairs(const float2 *__restrict__ src, float2 *lds, const DevPart *__restrict__ P,
+                                           uint64_t base, uint32_t tid)
+{
+    const int t = P->t;
+    const uint32_t npairs = 1u << (t - 1);
+    uint64_t gthr = 0;
+    for (int b = 1; b < LW + 1 && b < t; ++b)
+        if (((2u * tid) >> b) & 1u) gthr |= 1ull << P->tq[b];
+    for (uint32_t p0 = 0; p0 < npairs; p0 += (1u << LW)) {
+        const uint32_t p = p0 + tid;
+        if (p < npairs) {
+            uint64_t g = base | gthr;
+            for (int b = LW + 1; b < t; ++b)
+                if (((2u * p0) >> b) & 1u) g |= 1ull << P->tq[b];
+            const float4 v = *reinterpret_cast<const float4 *>(src + g);
+            lds[swz(2u * p)] = float2{v.x, v.y};
+            lds[swz(2u * p + 1)] = float2{v.z, v.w};
+        }
+    }
+}
+
+template <int LW>
+__device__ __forceinline__ void store_pairs(float2 *__restrict__ dst, const float2 *lds, const DevPart *__restrict__ P,
+                                            uint64_t base, uint32_t tid)
+{
+    const int t = P->t;
+    const uint32_t npairs = 1u << (t - 1);
+    uint64_t gthr = 0;
+    for (int b = 1; b < LW + 1 && b < t; ++b)
+        if (((2u * tid) >> b) & 1u) gthr |= 1ull << P->tq[b];
+    for (uint32_t p0 = 0; p0 < npairs; p0 += (1u << LW)) {
+        const uint32_t p = p0 + tid;
+        if (p < npairs) {
+            uint64_t g = base | gthr;
+            for (int b = LW + 1; b < t; ++b)
+                if (((2u * p0) >> b) & 1u) g |= 1ull << P->tq[b];
+            const float2 x = lds[swz(2u * p)], y = lds[swz(2u * p + 1)];
+            *reinterpret_cast<float4 *>(dst + g) = float4{x.x, x.y, y.x, y.y};
+        }
+    }
+}
+
+template <int R, int LW>
+__global__ __launch_bounds__(1 << LW) void reverse_kernel(const float2 *__restrict__ psi_src, float2 *__restrict__ lam,
+                                                            const DevPart *__restrict__ parts, int pidx,
+                                                            const DevStage *__restrict__ stages,
+                                                            const DevOp *__restrict__ ops,
+                                                            const float *__restrict__ pool,
+                                                            double *__restrict__ gpart, int64_t slot_stride)
+{
+    constexpr int NA = 1 << R;
+    extern __shared__ float2 lds[];
+    const DevPart *__restrict__ P = parts + pidx;
+    const uint32_t tid = threadIdx.x;
+    const int t = P->t;
+    float2 *lds_psi = lds, *lds_lam = lds + (1u << t);
+    uint64_t base = 0;
+    for (int b = 0; b < P->n_glb; ++b)
+        if (((uint64_t)blockIdx.x >> b) & 1ull) base |= 1ull << P->gq[b];
+    load_pairs<LW>(psi_src, lds_psi, P, base, tid);
+    load_pairs<LW>(lam, lds_lam, P, base, tid);
+    __syncthreads();
+    const int w = t - R;
+    const bool active = tid < (1u << w);
+    const int waves = (1 << LW) >= 64 ? (1 << LW) / 64 : 1;
+    const int64_t part_index = (int64_t)blockIdx.x * waves + (tid >> 6);
+    for (int s = P->stage_end - 1; s >= P->stage_begin; --s) {
+        const DevStage *__restrict__ S = stages + s;
+        uint32_t toff = 0;
+        for (int b = 0; b < w; ++b) toff |= ((tid >> b) & 1u) << S->thrpos[b];
+        uint32_t roff[NA];
+        roff[0] = 0;
+#pragma unroll
+        for (int i = 1; i < NA; ++i) roff[i] = roff[i & (i - 1)] | (1u << S->regpos[__builtin_ctz(i)]);
+        float2 a[NA], l[NA];
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            a[i] = active ? lds_psi[swz(toff | roff[i])] : float2{0.f, 0.f};
+            l[i] = active ? lds_lam[swz(toff | roff[i])] : float2{0.f, 0.f};
+        }
+        for (int k = S->op_end - 1; k >= S->op_begin; --k) {
+            const DevOp o = ops[k];
+            if (o.grad_slot >= 0) {
+                const double v = wave_sum(grad_term<R>(a, l, o, tid, base));
+                if ((tid & 63) == 0) gpart[(int64_t)o.grad_slot * slot_stride + part_index] = v;
+            }
+            apply_op<R, true>(a, o, pool, tid, base);
+            apply_op<R, true>(l, o, pool, tid, base);
+        }
+        if (active) {
+#pragma unroll
+            for (int i = 0; i < NA; ++i) {
+                lds_psi[swz(toff | roff[i])] = a[i];
+                lds_lam[swz(toff | roff[i])] = l[i];
+            }
+        }
+        __syncthreads();
+    }
+    store_pairs<LW>(lam, lds_lam, P, base, tid);
+}
+
+// slot_sum[s] = sum over (tile, wave) of gpart[s * stride + i], fixed order
+__global__ __launch_bounds__(256) void slot_sum_kernel(const double *__restrict__ gpart, int64_t stride,
+                                                        double *__restrict__ slot_sum)
+{
+    __shared__ double sh[256];
+    const int64_t s = blockIdx.x;
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < stride; i += 256) acc += gpart[s * stride + i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) slot_sum[s] = sh[0];
+}
+
+// grad[p] = sum of its slots in slot order
+__global__ void param_sum_kernel(const int32_t *__restrict__ off, const int32_t *__restrict__ slots,
+                                 const double *__restrict__ slot_sum, int64_t n_params, double *__restrict__ grad)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_params) return;
+    double acc = 0.0;
+    for (int32_t k = off[p]; k < off[p + 1]; ++k) acc += slot_sum[slots[k]];
+    grad[p] = acc;
+}
+
+template <int R, int LW>
+static hipError_t launch_reverse_t(const Plan &plan, int pidx, const float2 *psi, float2 *lam, double *gpart,
+                                   int64_t stride, hipStream_t s)
+{
+    const DevPart &P = plan.parts[pidx];
+    const size_t lds = (size_t)16 << P.t;
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void *)reverse_kernel<R, LW>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024);
+        (void)hipGetLastError();
+        attr = true;
+    }
+    hipLaunchKernelGGL((reverse_kernel<R, LW>), dim3((uint32_t)(1ull << P.n_glb)), dim3(1 << LW), lds, s, psi, lam,
+                       plan.d_parts, pidx, plan.d_stages, plan.d_ops, plan.d_pool, gpart, stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_reverse(const Plan &plan, int R, int LW, int pidx, const float2 *psi, float2 *lam, double *gpart,
+                          int64_t stride, hipStream_t s)
+{
+#define QSV_CASE(r, lw) \
+    if (R == r && LW == lw) return launch_reverse_t<r, lw>(plan, pidx, psi, lam, gpart, stride, s);
+    QSV_CASE(1, 6) QSV_CASE(2, 6) QSV_CASE(3, 6) QSV_CASE(4, 6) QSV_CASE(5, 6)
+    QSV_CASE(3, 8) QSV_CASE(4, 8) QSV_CASE(5, 8) QSV_CASE(4, 9)
+#undef QSV_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_grad_reduce(const Plan &plan, const double *gpart, int64_t n_slots, int64_t stride,
+                              double *slot_sum, double *grad, hipStream_t s)
+{
+    if (n_slots > 0) {
+        hipLaunchKernelGGL(slot_sum_kernel, dim3((uint32_t)n_slots), dim3(256), 0, s, gpart, stride, slot_sum);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const int64_t np = plan.n_params;
+    hipLaunchKernelGGL(param_sum_kernel, dim3((uint32_t)((np + 255) / 256)), dim3(256), 0, s, plan.d_param_off,
+                       plan.d_param_slots, slot_sum, np, grad);
+    return hipGetLastError();
+}
+
+}  // namespace qsv

@@ -1,0 +1,529 @@
+// C interface (include/qsv.h).  Argument checking, plan construction and
+// upload, and the launch sequences of qsv_apply / qsv_expect /
+// qsv_adjoint_grad.  No C++ exception crosses the interface.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+using namespace qsv;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Fail {
+    qsv_status code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(qsv_status code, const std::string &msg) { throw Fail{code, msg}; }
+
+void hip_check(hipError_t e, const char *what)
+{
+    if (e != hipSuccess) fail(QSV_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename F>
+qsv_status guarded(F &&f)
+{
+    try {
+        f();
+        g_err.clear();
+        return QSV_OK;
+    } catch (const Fail &e) {
+        g_err = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_err = "host allocation failed";
+        return QSV_E_NOMEM;
+    } catch (const std::exception &e) {
+        g_err = std::string("internal error: ") + e.what();
+        return QSV_E_ARG;
+    }
+}
+
+template <typename T>
+T *dev_upload(const std::vector<T> &v)
+{
+    if (v.empty()) return nullptr;
+    void *p = nullptr;
+    if (hipMalloc(&p, v.size() * sizeof(T)) != hipSuccess) fail(QSV_E_NOMEM, "device allocation failed");
+    hip_check(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy");
+    return static_cast<T *>(p);
+}
+
+void dev_free(void *p)
+{
+    if (p) (void)hipFree(p);
+}
+
+// Smallest supported kernel shape that covers n qubits when the state fits
+// one tile; otherwise the configured shape.
+void choose_shape(int n, int R, int LW, int &Re, int &LWe, int &te)
+{
+    if (n >= R + LW) {
+        Re = R; LWe = LW; te = R + LW;
+        return;
+    }
+    te = n;
+    for (int r = std::min(R, n); r <= std::min(5, n); ++r) {
+        int w = n - r;
+        for (int lw : {6, 8, 9, 10}) {
+            if (lw >= w && kernel_shape_supported(r, lw)) {
+                Re = r; LWe = lw;
+                return;
+            }
+        }
+    }
+    fail(QSV_E_UNSUPPORTED, "no kernel shape for this qubit count");
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+struct qsv_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool timing = false;
+    double last_ms = 0;
+    int64_t last_launches = 0;
+    std::vector<hipEvent_t> events;
+    // scratch
+    void *scratch = nullptr;
+    size_t scratch_bytes = 0;
+    void *lam = nullptr;
+    size_t lam_bytes = 0;
+    void *terms_dev = nullptr;
+    size_t terms_bytes = 0;
+    void *pinned = nullptr;
+    size_t pinned_bytes = 0;
+    hipEvent_t pinned_ready = nullptr;
+    int *queue = nullptr;
+
+    void *ensure(void *&p, size_t &have, size_t need)
+    {
+        if (need > have) {
+            if (p) {
+                hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
+                dev_free(p);
+                p = nullptr;
+                have = 0;
+            }
+            if (hipMalloc(&p, need) != hipSuccess) fail(QSV_E_NOMEM, "device scratch allocation failed");
+            have = need;
+        }
+        return p;
+    }
+};
+
+struct qsv_plan : public Plan {};
+
+struct HostGroups {
+    std::vector<DevGroup> groups;
+    std::vector<DevTerm> terms;
+};
+
+static HostGroups group_terms(const qsv_pauli_term *H, int n_terms, int n)
+{
+    if (n_terms < 0 || (n_terms > 0 && !H)) fail(QSV_E_ARG, "null or negative Pauli sum");
+    const uint64_t full = n >= 64 ? ~0ull : ((1ull << n) - 1);
+    std::map<uint64_t, std::vector<int>> by_x;
+    for (int t = 0; t < n_terms; ++t) {
+        if ((H[t].x_mask & ~full) || (H[t].z_mask & ~full)) fail(QSV_E_ARG, "Pauli mask beyond n_qubits");
+        by_x[H[t].x_mask].push_back(t);
+    }
+    HostGroups g;
+    for (auto &kv : by_x) {
+        DevGroup dg;
+        dg.x_mask = kv.first;
+        dg.term_begin = (int32_t)g.terms.size();
+        for (int t : kv.second) {
+            int ny = __builtin_popcountll(H[t].x_mask & H[t].z_mask) & 3;  // i^{#Y}
+            double c = H[t].coeff;
+            DevTerm d;
+            d.cre = ny == 0 ? c : ny == 2 ? -c : 0.0;
+            d.cim = ny == 1 ? c : ny == 3 ? -c : 0.0;
+            d.z_mask = H[t].z_mask;
+            g.terms.push_back(d);
+        }
+        dg.term_end = (int32_t)g.terms.size();
+        g.groups.push_back(dg);
+    }
+    return g;
+}
+
+// Upload grouped terms into the context (pinned staging + async copy).
+static void upload_groups(qsv_ctx *ctx, const HostGroups &g, DevGroup *&dgroups, DevTerm *&dterms)
+{
+    size_t gb = g.groups.size() * sizeof(DevGroup), tb = g.terms.size() * sizeof(DevTerm);
+    size_t need = gb + tb + 64;
+    if (ctx->pinned_ready) hip_check(hipEventSynchronize(ctx->pinned_ready), "hipEventSynchronize");
+    if (need > ctx->pinned_bytes) {
+        if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+        ctx->pinned = nullptr;
+        if (hipHostMalloc(&ctx->pinned, need) != hipSuccess) fail(QSV_E_NOMEM, "pinned allocation failed");
+        ctx->pinned_bytes = need;
+    }
+    char *dev = (char *)ctx->ensure(ctx->terms_dev, ctx->terms_bytes, need);
+    char *h = (char *)ctx->pinned;
+    size_t toff = (gb + 15) & ~size_t(15);
+    if (gb) std::memcpy(h, g.groups.data(), gb);
+    if (tb) std::memcpy(h + toff, g.terms.data(), tb);
+    hip_check(hipMemcpyAsync(dev, h, toff + tb, hipMemcpyHostToDevice, ctx->stream), "hipMemcpyAsync");
+    if (!ctx->pinned_ready) hip_check(hipEventCreateWithFlags(&ctx->pinned_ready, hipEventDisableTiming), "event");
+    hip_check(hipEventRecord(ctx->pinned_ready, ctx->stream), "hipEventRecord");
+    dgroups = (DevGroup *)dev;
+    dterms = (DevTerm *)(dev + toff);
+}
+
+extern "C" {
+
+const char *qsv_last_error(void) { return g_err.c_str(); }
+
+qsv_status qsv_create(int32_t device, void *hip_stream, qsv_ctx **out)
+{
+    return guarded([&] {
+        if (!out) fail(QSV_E_ARG, "out is null");
+        int count = 0;
+        hip_check(hipGetDeviceCount(&count), "hipGetDeviceCount");
+        if (device < 0 || device >= count) fail(QSV_E_DEVICE, "no such device");
+        hip_check(hipSetDevice(device), "hipSetDevice");
+        qsv_ctx *c = new qsv_ctx();
+        c->device = device;
+        c->stream = (hipStream_t)hip_stream;
+        *out = c;
+    });
+}
+
+qsv_status qsv_destroy(qsv_ctx *ctx)
+{
+    return guarded([&] {
+        if (!ctx) return;
+        (void)hipSetDevice(ctx->device);
+        (void)hipStreamSynchronize(ctx->stream);
+        dev_free(ctx->scratch);
+        dev_free(ctx->lam);
+        dev_free(ctx->terms_dev);
+        dev_free(ctx->queue);
+        if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+        if (ctx->pinned_ready) (void)hipEventDestroy(ctx->pinned_ready);
+        for (auto e : ctx->events) (void)hipEventDestroy(e);
+        delete ctx;
+    });
+}
+
+qsv_status qsv_set_stream(qsv_ctx *ctx, void *hip_stream)
+{
+    return guarded([&] {
+        if (!ctx) fail(QSV_E_ARG, "ctx is null");
+        ctx->stream = (hipStream_t)hip_stream;
+    });
+}
+
+qsv_status qsv_set_timing(qsv_ctx *ctx, int32_t enable)
+{
+    return guarded([&] {
+        if (!ctx) fail(QSV_E_ARG, "ctx is null");
+        ctx->timing = enable != 0;
+    });
+}
+
+qsv_status qsv_last_sweep_ms(qsv_ctx *ctx, double *total_ms, int64_t *n_launches)
+{
+    return guarded([&] {
+        if (!ctx || !total_ms || !n_launches) fail(QSV_E_ARG, "null argument");
+        if (ctx->timing && !ctx->events.empty() && ctx->last_launches > 0) {
+            hip_check(hipEventSynchronize(ctx->events[2 * ctx->last_launches - 1]), "hipEventSynchronize");
+            double total = 0;
+            for (int64_t i = 0; i < ctx->last_launches; ++i) {
+                float ms = 0;
+                hip_check(hipEventElapsedTime(&ms, ctx->events[2 * i], ctx->events[2 * i + 1]), "hipEventElapsedTime");
+                total += ms;
+            }
+            ctx->last_ms = total;
+        }
+        *total_ms = ctx->last_ms;
+        *n_launches = ctx->last_launches;
+    });
+}
+
+qsv_status qsv_partition(qsv_ctx *ctx, int32_t n_qubits, const qsv_gate *gates, const int64_t *circ_offsets,
+                         int32_t n_circuits, int32_t k_local, uint32_t flags, const qsv_tile_config *tile,
+                         qsv_plan **out)
+{
+    return guarded([&] {
+        auto t0 = std::chrono::steady_clock::now();
+        if (!out) fail(QSV_E_ARG, "out is null");
+        if (n_qubits < 1 || n_qubits > 34) fail(QSV_E_ARG, "n_qubits must be in [1, 34]");
+        if (k_local < 0) fail(QSV_E_ARG, "k_local must be >= 0");
+        if (n_circuits < 1) fail(QSV_E_ARG, "n_circuits must be >= 1");
+        if (flags & ~(QSV_PLAN_GATE_BY_GATE | QSV_PLAN_GRAD)) fail(QSV_E_ARG, "unknown flag");
+        if (!circ_offsets) fail(QSV_E_ARG, "circ_offsets is null");
+        std::vector<int64_t> off(n_circuits + 1, 0);
+        for (int c = 0; c <= n_circuits; ++c) off[c] = circ_offsets[c];
+        if (off[0] != 0) fail(QSV_E_ARG, "circ_offsets[0] must be 0");
+        for (int c = 0; c < n_circuits; ++c)
+            if (off[c + 1] < off[c]) fail(QSV_E_ARG, "circ_offsets must be non-decreasing");
+        const int64_t G = off[n_circuits];
+        if (G > 0 && !gates) fail(QSV_E_ARG, "gates is null");
+        if (n_circuits > 1 && n_qubits > 14) fail(QSV_E_ARG, "batched plans need n_qubits <= 14");
+        int R = 5, LW = 8;
+        if (tile && (tile->reg_qubits || tile->log_threads)) {
+            R = tile->reg_qubits;
+            LW = tile->log_threads;
+            if (!kernel_shape_supported(R, LW)) fail(QSV_E_ARG, "unsupported tile shape");
+        }
+        if (n_circuits > 1) { R = 4; LW = 10; }
+        if ((flags & QSV_PLAN_GRAD) && n_circuits == 1 && R + LW > 13 && n_qubits > 13)
+            fail(QSV_E_UNSUPPORTED, "gradient plans need a tile of at most 13 qubits");
+        int k = k_local == 0 ? (n_qubits <= R + LW ? n_qubits : R + LW - 3) : k_local;
+        if (n_qubits > R + LW && k >= R + LW) fail(QSV_E_ARG, "k_local must be below the tile size");
+
+        auto P = new qsv_plan();
+        std::unique_ptr<qsv_plan, void (*)(qsv_plan *)> guard(P, [](qsv_plan *p) { qsv_plan_destroy(p); });
+        P->n = n_qubits;
+        P->n_circuits = n_circuits;
+        P->flags = flags;
+        choose_shape(n_qubits, R, LW, P->R, P->LW, P->t);
+        P->k = std::min(k, n_qubits);
+        P->gates.assign(gates, gates + G);
+        int64_t theta_off = 0;
+        for (int c = 0; c < n_circuits; ++c) {
+            CircuitPlan C;
+            C.g0 = off[c];
+            C.g1 = off[c + 1];
+            int64_t np = 0;
+            for (int64_t g = C.g0; g < C.g1; ++g) {
+                std::string e = validate_gate(P->gates[g], n_qubits, 0);
+                if (!e.empty()) {
+                    bool range = e.find("param") != std::string::npos;
+                    fail(range ? QSV_E_RANGE : QSV_E_ARG, "gate " + std::to_string(g - C.g0) + ": " + e);
+                }
+                np = std::max<int64_t>(np, (int64_t)P->gates[g].param + 1);
+            }
+            C.theta_off = theta_off;
+            C.n_params = np;
+            theta_off += np;
+            P->circ.push_back(C);
+        }
+        P->n_params = theta_off;
+        build_plan(*P);
+        if (ctx) {
+            hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+            P->device = ctx->device;
+            P->d_ops = dev_upload(P->ops);
+            P->d_stages = dev_upload(P->stages);
+            P->d_parts = dev_upload(P->parts);
+            std::vector<float> pool = P->pool;
+            if (pool.empty()) pool.push_back(0.f);
+            P->d_pool = dev_upload(pool);
+            P->d_pgates = dev_upload(P->pgates);
+            P->d_grad_param = dev_upload(P->grad_param);
+            P->d_param_off = dev_upload(P->param_off);
+            P->d_param_slots = dev_upload(P->param_slots);
+        }
+        P->plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        *out = guard.release();
+    });
+}
+
+qsv_status qsv_plan_destroy(qsv_plan *plan)
+{
+    return guarded([&] {
+        if (!plan) return;
+        if (plan->device >= 0) (void)hipSetDevice(plan->device);
+        dev_free(plan->d_ops);
+        dev_free(plan->d_stages);
+        dev_free(plan->d_parts);
+        dev_free(plan->d_pool);
+        dev_free(plan->d_pgates);
+        dev_free(plan->d_grad_param);
+        dev_free(plan->d_param_off);
+        dev_free(plan->d_param_slots);
+        dev_free(plan->d_batch_order);
+        dev_free(plan->d_circ_stage);
+        dev_free(plan->d_circ_theta);
+        dev_free(plan->d_circ_grad);
+        delete plan;
+    });
+}
+
+qsv_status qsv_plan_get_info(const qsv_plan *plan, qsv_plan_info *out)
+{
+    return guarded([&] {
+        if (!plan || !out) fail(QSV_E_ARG, "null argument");
+        qsv_plan_info i;
+        std::memset(&i, 0, sizeof(i));
+        i.n_qubits = plan->n;
+        i.n_circuits = plan->n_circuits;
+        i.k_local = plan->k;
+        i.tile_qubits = plan->t;
+        i.reg_qubits = plan->R;
+        i.log_threads = plan->LW;
+        i.n_gates = (int64_t)plan->gates.size();
+        i.n_params = plan->n_params;
+        int64_t np = 0;
+        for (auto &c : plan->circ) np += (int64_t)c.parts.size();
+        i.n_partitions = np;
+        i.n_stages = (int64_t)plan->stages.size();
+        int64_t P0 = plan->circ.empty() ? 0 : (int64_t)plan->circ[0].parts.size();
+        i.ckpt_bytes = plan->n_circuits == 1 && P0 > 1 ? (P0 - 1) * ((int64_t)8 << plan->n) : 0;
+        i.flops_per_apply = plan->flops;
+        i.bytes_per_apply = plan->bytes;
+        i.plan_seconds = plan->plan_seconds;
+        *out = i;
+    });
+}
+
+qsv_status qsv_plan_params(const qsv_plan *plan, int32_t circuit, int64_t *offset, int64_t *count)
+{
+    return guarded([&] {
+        if (!plan || !offset || !count) fail(QSV_E_ARG, "null argument");
+        if (circuit < 0 || circuit >= plan->n_circuits) fail(QSV_E_ARG, "circuit out of range");
+        *offset = plan->circ[circuit].theta_off;
+        *count = plan->circ[circuit].n_params;
+    });
+}
+
+qsv_status qsv_plan_partition(const qsv_plan *plan, int32_t circuit, int32_t level, int64_t p, uint64_t *local_mask,
+                              int32_t *gates, int64_t cap, int64_t *n_gates)
+{
+    return guarded([&] {
+        if (!plan || !local_mask || !n_gates) fail(QSV_E_ARG, "null argument");
+        if (circuit < 0 || circuit >= plan->n_circuits) fail(QSV_E_ARG, "circuit out of range");
+        const CircuitPlan &C = plan->circ[circuit];
+        const Part *part = nullptr;
+        if (level == 0) {
+            if (p < 0 || p >= (int64_t)C.parts.size()) fail(QSV_E_ARG, "partition out of range");
+            part = &C.parts[p];
+        } else if (level == 1) {
+            int64_t q = p;
+            for (auto &st : C.stages) {
+                if (q < (int64_t)st.size()) { part = &st[q]; break; }
+                q -= (int64_t)st.size();
+            }
+            if (!part || p < 0) fail(QSV_E_ARG, "stage out of range");
+        } else {
+            fail(QSV_E_ARG, "level must be 0 or 1");
+        }
+        *local_mask = part->S;
+        *n_gates = (int64_t)part->gates.size();
+        for (int64_t i = 0; gates && i < std::min<int64_t>(cap, *n_gates); ++i)
+            gates[i] = (int32_t)(part->gates[i] - C.g0);
+    });
+}
+
+qsv_status qsv_apply(qsv_ctx *ctx, const qsv_plan *plan, const double *theta_dev, void *psi_dev, void *ckpt_dev)
+{
+    return guarded([&] {
+        if (!ctx || !plan) fail(QSV_E_ARG, "null ctx or plan");
+        if (!psi_dev) fail(QSV_E_ARG, "psi is null");
+        if (plan->device != ctx->device || (!plan->d_parts && !plan->parts.empty()))
+            fail(QSV_E_STATE, "plan has no device tables on this context's device");
+        if (plan->n_params > 0 && !theta_dev) fail(QSV_E_ARG, "theta is null");
+        hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+        if (plan->n_circuits > 1) fail(QSV_E_UNSUPPORTED, "batched forward-only apply not built");
+        hip_check(launch_materialize(*plan, theta_dev, ctx->stream), "materialize");
+        const int np = (int)plan->parts.size();
+        if (ctx->timing) {
+            while ((int)ctx->events.size() < 2 * np) {
+                hipEvent_t e;
+                hip_check(hipEventCreate(&e), "hipEventCreate");
+                ctx->events.push_back(e);
+            }
+        }
+        float2 *psi = (float2 *)psi_dev;
+        float2 *ckpt = (float2 *)ckpt_dev;
+        const size_t dim = (size_t)1 << plan->n;
+        for (int p = 0; p < np; ++p) {
+            float2 *ck = (ckpt && p < np - 1) ? ckpt + (size_t)p * dim : nullptr;
+            if (ctx->timing) hip_check(hipEventRecord(ctx->events[2 * p], ctx->stream), "hipEventRecord");
+            hip_check(launch_sweep(*plan, plan->R, plan->LW, p, psi, ck, ctx->stream), "sweep launch");
+            if (ctx->timing) hip_check(hipEventRecord(ctx->events[2 * p + 1], ctx->stream), "hipEventRecord");
+        }
+        ctx->last_launches = ctx->timing ? np : 0;
+    });
+}
+
+qsv_status qsv_expect(qsv_ctx *ctx, const qsv_pauli_term *H, int32_t n_terms, int32_t n_qubits, int64_t batch,
+                      const void *psi_dev, double *out_dev)
+{
+    return guarded([&] {
+        if (!ctx || !psi_dev || !out_dev) fail(QSV_E_ARG, "null argument");
+        if (n_qubits < 1 || n_qubits > 34) fail(QSV_E_ARG, "n_qubits must be in [1, 34]");
+        if (batch < 1) fail(QSV_E_ARG, "batch must be >= 1");
+        HostGroups g = group_terms(H, n_terms, n_qubits);
+        hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+        const int n_blocks = 512;
+        size_t need = sizeof(double) * (size_t)n_blocks * std::max<size_t>(1, g.groups.size()) * (size_t)batch;
+        double *partials = (double *)ctx->ensure(ctx->scratch, ctx->scratch_bytes, need);
+        DevGroup *dg = nullptr;
+        DevTerm *dt = nullptr;
+        if (!g.groups.empty()) upload_groups(ctx, g, dg, dt);
+        hip_check(launch_expect(dg, (int)g.groups.size(), dt, n_qubits, batch, (const float2 *)psi_dev, partials,
+                                n_blocks, out_dev, ctx->stream),
+                  "expect launch");
+    });
+}
+
+qsv_status qsv_adjoint_grad(qsv_ctx *ctx, const qsv_plan *plan, const qsv_pauli_term *H, int32_t n_terms,
+                            const double *theta_dev, const void *psi_final_dev, const void *ckpt_dev,
+                            double *energy_dev, double *grad_dev)
+{
+    return guarded([&] {
+        if (!ctx || !plan) fail(QSV_E_ARG, "null ctx or plan");
+        if (!energy_dev) fail(QSV_E_ARG, "energy is null");
+        if (plan->n_params > 0 && (!theta_dev || !grad_dev)) fail(QSV_E_ARG, "theta or grad is null");
+        if (plan->device != ctx->device) fail(QSV_E_STATE, "plan has no device tables on this context's device");
+        HostGroups g = group_terms(H, n_terms, plan->n);
+        hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+        if (plan->n_circuits > 1) fail(QSV_E_UNSUPPORTED, "batched adjoint not built");
+        if (!(plan->flags & QSV_PLAN_GRAD)) fail(QSV_E_STATE, "plan was built without QSV_PLAN_GRAD");
+        if (!psi_final_dev) fail(QSV_E_ARG, "psi_final is null");
+        const int np = (int)plan->parts.size();
+        if (np > 1 && !ckpt_dev) fail(QSV_E_STATE, "checkpoints missing");
+        const int n = plan->n;
+        const size_t dim = (size_t)1 << n;
+        // scratch: lambda state + reduction partials + gradient partials
+        float2 *lam = (float2 *)ctx->ensure(ctx->lam, ctx->lam_bytes, dim * sizeof(float2));
+        const int n_blocks = 512;
+        const int t = plan->t;
+        const int64_t n_tiles = (int64_t)1 << (n - t);
+        const int64_t waves = std::max(1, (1 << plan->LW) / 64);
+        const int64_t n_slots = (int64_t)plan->grad_param.size();
+        size_t red = sizeof(double) * n_blocks * std::max<size_t>(1, g.groups.size());
+        size_t gp = sizeof(double) * (size_t)std::max<int64_t>(1, n_slots) * n_tiles * waves;
+        size_t sl = sizeof(double) * (size_t)std::max<int64_t>(1, n_slots);
+        const size_t gp_off = (red + 255) & ~size_t(255), sl_off = (gp_off + gp + 255) & ~size_t(255);
+        char *scr = (char *)ctx->ensure(ctx->scratch, ctx->scratch_bytes, sl_off + sl);
+        double *partials = (double *)scr;
+        double *gpart = (double *)(scr + gp_off);
+        double *slot_sum = (double *)(scr + sl_off);
+        DevGroup *dg = nullptr;
+        DevTerm *dt = nullptr;
+        if (!g.groups.empty()) upload_groups(ctx, g, dg, dt);
+        hip_check(launch_materialize(*plan, theta_dev, ctx->stream), "materialize");
+        hip_check(launch_apply_h(dg, (int)g.groups.size(), dt, n, (const float2 *)psi_final_dev, lam, partials,
+                                 n_blocks, energy_dev, ctx->stream),
+                  "apply_h launch");
+        for (int p = np - 1; p >= 0; --p) {
+            const float2 *src = p == np - 1 ? (const float2 *)psi_final_dev : (const float2 *)ckpt_dev + (size_t)p * dim;
+            hip_check(launch_reverse(*plan, plan->R, plan->LW, p, src, lam, gpart, n_tiles * waves, ctx->stream),
+                      "reverse launch");
+        }
+        if (plan->n_params > 0)
+            hip_check(launch_grad_reduce(*plan, gpart, n_slots, n_tiles * waves, slot_sum, grad_dev, ctx->stream),
+                      "grad reduce");
+    });
+}
+
+}  // extern "C"

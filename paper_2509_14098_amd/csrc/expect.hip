@@ -1,0 +1,160 @@
+// Expectation values of Pauli sums and the action of H on a state.
+//
+// A Pauli string P with X/Y mask xm and Z/Y mask zm maps |x> to
+// i^{#Y} (-1)^{|x & zm|} |x ^ xm>, so
+//   <psi|P|psi> = sum_x conj(psi_{x^xm}) psi_x i^{#Y} (-1)^{|x & zm|}.
+// Terms are grouped by xm; a group with xm != 0 is summed over pairs
+// (x, x^xm), each amplitude read once per group.  Products are formed and
+// accumulated in float64; block sums go to a partials array and a second
+// kernel adds them in a fixed order, so results do not depend on timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "kernels.h"
+
+namespace qsv {
+
+constexpr int RED_THREADS = 256;
+
+__device__ __forceinline__ double block_sum(double v, double *sh)
+{
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+        if (tid < s) sh[tid] += sh[tid + s];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ double parity_sign(uint64_t v) { return (__popcll(v) & 1) ? -1.0 : 1.0; }
+
+// partials[(b * n_groups + g) * gridDim.x + block]
+__global__ __launch_bounds__(RED_THREADS) void expect_kernel(const DevGroup *__restrict__ groups,
+                                                              const DevTerm *__restrict__ terms, int n,
+                                                              const float2 *__restrict__ psi,
+                                                              double *__restrict__ partials)
+{
+    __shared__ double sh[RED_THREADS];
+    const int gi = blockIdx.y;
+    const int64_t b = blockIdx.z;
+    const DevGroup G = groups[gi];
+    const float2 *__restrict__ s = psi + ((uint64_t)b << n);
+    const uint64_t stride = (uint64_t)gridDim.x * RED_THREADS;
+    double acc = 0.0;
+    if (G.x_mask == 0) {
+        const uint64_t dim = 1ull << n;
+        for (uint64_t x = (uint64_t)blockIdx.x * RED_THREADS + threadIdx.x; x < dim; x += stride) {
+            const float2 a = s[x];
+            const double p = (double)a.x * a.x + (double)a.y * a.y;
+            double w = 0.0;
+            for (int t = G.term_begin; t < G.term_end; ++t) w += terms[t].cre * parity_sign(x & terms[t].z_mask);
+            acc += p * w;
+        }
+    } else {
+        const int lb = __builtin_ctzll(G.x_mask);
+        const uint64_t low = 1ull << lb;
+        const uint64_t half = 1ull << (n - 1);
+        for (uint64_t k = (uint64_t)blockIdx.x * RED_THREADS + threadIdx.x; k < half; k += stride) {
+            const uint64_t x = ((k >> lb) << (lb + 1)) | (k & (low - 1));
+            const uint64_t y = x ^ G.x_mask;
+            const float2 a = s[x], c = s[y];
+            // z = conj(psi_y) psi_x
+            const double zr = (double)c.x * a.x + (double)c.y * a.y;
+            const double zi = (double)c.x * a.y - (double)c.y * a.x;
+            for (int t = G.term_begin; t < G.term_end; ++t) {
+                const DevTerm T = terms[t];
+                const double sx = parity_sign(x & T.z_mask), sy = parity_sign(y & T.z_mask);
+                acc += sx * (T.cre * zr - T.cim * zi) + sy * (T.cre * zr + T.cim * zi);
+            }
+        }
+    }
+    const double tot = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[((uint64_t)b * gridDim.y + gi) * gridDim.x + blockIdx.x] = tot;
+}
+
+// out[b] = sum of per_batch partials, fixed order
+__global__ __launch_bounds__(RED_THREADS) void final_sum_kernel(const double *__restrict__ partials, int per_batch,
+                                                                 double *__restrict__ out)
+{
+    __shared__ double sh[RED_THREADS];
+    const int64_t b = blockIdx.x;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < per_batch; i += RED_THREADS) acc += partials[b * per_batch + i];
+    const double tot = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[b] = tot;
+}
+
+// lam = H psi; partials[block] = sum_x Re(conj(psi_x) lam_x) over the block
+__global__ __launch_bounds__(RED_THREADS) void apply_h_kernel(const DevGroup *__restrict__ groups, int n_groups,
+                                                               const DevTerm *__restrict__ terms, int n,
+                                                               const float2 *__restrict__ psi,
+                                                               float2 *__restrict__ lam,
+                                                               double *__restrict__ partials)
+{
+    __shared__ double sh[RED_THREADS];
+    const uint64_t dim = 1ull << n;
+    const uint64_t stride = (uint64_t)gridDim.x * RED_THREADS;
+    double acc = 0.0;
+    for (uint64_t x = (uint64_t)blockIdx.x * RED_THREADS + threadIdx.x; x < dim; x += stride) {
+        const float2 px = psi[x];
+        double lr = 0.0, li = 0.0;
+        for (int g = 0; g < n_groups; ++g) {
+            const DevGroup G = groups[g];
+            const uint64_t y = x ^ G.x_mask;
+            const float2 py = G.x_mask ? psi[y] : px;
+            double wr = 0.0, wi = 0.0;
+            for (int t = G.term_begin; t < G.term_end; ++t) {
+                const double sg = parity_sign(y & terms[t].z_mask);
+                wr += sg * terms[t].cre;
+                wi += sg * terms[t].cim;
+            }
+            lr += wr * py.x - wi * py.y;
+            li += wr * py.y + wi * py.x;
+        }
+        lam[x] = float2{(float)lr, (float)li};
+        acc += (double)px.x * lr + (double)px.y * li;
+    }
+    const double tot = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+static int blocks_for(uint64_t work, int cap)
+{
+    uint64_t b = (work + RED_THREADS * 8 - 1) / (RED_THREADS * 8);
+    return (int)std::max<uint64_t>(1, std::min<uint64_t>(b, (uint64_t)cap));
+}
+
+hipError_t launch_expect(const DevGroup *groups, int n_groups, const DevTerm *terms, int n, int64_t batch,
+                         const float2 *psi, double *partials, int n_blocks, double *out, hipStream_t s)
+{
+    if (n_groups == 0) {  // empty sum: zeros
+        hipLaunchKernelGGL(final_sum_kernel, dim3((uint32_t)batch), dim3(RED_THREADS), 0, s, partials, 0, out);
+        return hipGetLastError();
+    }
+    const int nb = blocks_for(1ull << n, n_blocks);
+    hipLaunchKernelGGL(expect_kernel, dim3(nb, n_groups, (uint32_t)batch), dim3(RED_THREADS), 0, s, groups, terms, n,
+                       psi, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(final_sum_kernel, dim3((uint32_t)batch), dim3(RED_THREADS), 0, s, partials, nb * n_groups, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_h(const DevGroup *groups, int n_groups, const DevTerm *terms, int n, const float2 *psi,
+                          float2 *lam, double *partials, int n_blocks, double *energy, hipStream_t s)
+{
+    const int nb = blocks_for(1ull << n, n_blocks);
+    hipLaunchKernelGGL(apply_h_kernel, dim3(nb), dim3(RED_THREADS), 0, s, groups, n_groups, terms, n, psi, lam,
+                       partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(RED_THREADS), 0, s, partials, nb, energy);
+    return hipGetLastError();
+}
+
+}  // namespace qsv

@@ -1,0 +1,92 @@
+// Host-side structures shared by the planner, the C interface and the kernel
+// launchers.  Not part of the public interface.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/qsv.h"
+#include "plan.h"
+
+namespace qsv {
+
+// Classification of one gate, from the exact zeros of its float64 matrix
+// (fixed gates) or from the structure of its kind (parameterised rotations).
+struct GateMeta {
+    int nq = 1;
+    int q[2] = {-1, -1};
+    uint64_t qmask = 0;   // all qubits of the gate
+    uint64_t req = 0;     // qubits that must be local (Section 4.2 exemptions)
+    OpKind op = OP_U1;    // register-level kernel path
+    int ctrl = -1, tgt = -1;  // for OP_CX / OP_CU
+    GenKind gen = GEN_NONE;
+    bool param = false;
+    double m[32] = {0};   // float64 matrix (fixed gates), (re, im) row-major
+    double flops = 0;     // algorithmic flops per amplitude
+};
+
+// A partition at some level: local qubit set and gate indices in order.
+struct Part {
+    uint64_t S = 0;
+    std::vector<int> gates;
+};
+
+struct CircuitPlan {
+    int64_t g0 = 0, g1 = 0;          // gate range in the plan's gate array
+    int64_t theta_off = 0, n_params = 0;
+    std::vector<Part> parts;          // level 1 (tile / LDS)
+    std::vector<std::vector<Part>> stages;  // level 2 (registers), per partition
+    int32_t part_begin = 0;           // index of its first DevPart
+};
+
+struct ParamGate {                    // a rotation whose matrix is formed from theta on the device
+    int32_t mat;                      // pool offset
+    int32_t kind;
+    int32_t theta_index;              // absolute index into the packed theta array
+    int32_t pad;
+};
+
+struct Plan {
+    int n = 0, n_circuits = 0, k = 0, t = 0, R = 0, LW = 0;
+    uint32_t flags = 0;
+    std::vector<qsv_gate> gates;
+    std::vector<GateMeta> meta;
+    std::vector<CircuitPlan> circ;
+    int64_t n_params = 0;
+    double plan_seconds = 0, flops = 0, bytes = 0;
+
+    // lowered tables
+    std::vector<DevOp> ops;
+    std::vector<DevStage> stages;
+    std::vector<DevPart> parts;
+    std::vector<float> pool;
+    std::vector<ParamGate> pgates;
+    std::vector<int32_t> grad_param;  // grad slot -> absolute theta index
+    std::vector<int32_t> param_off, param_slots;  // theta index -> its grad slots (CSR, slot order)
+    // batched plans: per-circuit stage ranges (single tile per circuit)
+    std::vector<int32_t> batch_order; // circuits sorted by decreasing op count
+
+    // device copies (null for host-only plans)
+    int device = -1;
+    DevOp *d_ops = nullptr;
+    DevStage *d_stages = nullptr;
+    DevPart *d_parts = nullptr;
+    float *d_pool = nullptr;
+    ParamGate *d_pgates = nullptr;
+    int32_t *d_grad_param = nullptr;
+    int32_t *d_param_off = nullptr;
+    int32_t *d_param_slots = nullptr;
+    int32_t *d_batch_order = nullptr;
+    int32_t *d_circ_stage = nullptr;   // batched: [stage_begin, stage_end) per circuit
+    int64_t *d_circ_theta = nullptr;   // batched: theta offset per circuit
+    int32_t *d_circ_grad = nullptr;    // batched: first grad slot per circuit
+};
+
+// planner.cpp
+std::string validate_gate(const qsv_gate &g, int n, int64_t n_params_hint);
+GateMeta classify(const qsv_gate &g);
+std::vector<Part> greedy_partition(int n, const std::vector<GateMeta> &meta, const std::vector<int> &sub, int k,
+                                   uint64_t allowed);
+void build_plan(Plan &plan);
+
+}  // namespace qsv

@@ -1,0 +1,40 @@
+// Kernel launchers (implemented in the .hip files).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace qsv {
+
+bool kernel_shape_supported(int R, int LW);
+hipError_t launch_sweep(const Plan &plan, int R, int LW, int pidx, float2 *psi, float2 *ckpt, hipStream_t s);
+hipError_t launch_materialize(const Plan &plan, const double *theta, hipStream_t s);
+
+// Pauli sums grouped by X mask, in the form the reduction kernels read.
+struct DevTerm {
+    double cre, cim;      // coeff * i^{#Y}
+    uint64_t z_mask;
+};
+struct DevGroup {
+    uint64_t x_mask;
+    int32_t term_begin, term_end;
+};
+
+// expect.hip
+hipError_t launch_expect(const DevGroup *groups, int n_groups, const DevTerm *terms, int n, int64_t batch,
+                         const float2 *psi, double *partials, int n_blocks, double *out, hipStream_t s);
+hipError_t launch_apply_h(const DevGroup *groups, int n_groups, const DevTerm *terms, int n, const float2 *psi,
+                          float2 *lam, double *partials, int n_blocks, double *energy, hipStream_t s);
+
+// adjoint.hip
+hipError_t launch_reverse(const Plan &plan, int R, int LW, int pidx, const float2 *psi_ckpt, float2 *lam,
+                          double *gpart, int64_t n_tiles_stride, hipStream_t s);
+hipError_t launch_grad_reduce(const Plan &plan, const double *gpart, int64_t n_slots, int64_t stride,
+                              double *slot_sum, double *grad, hipStream_t s);
+
+// batched.hip
+hipError_t launch_batched(const Plan &plan, const DevGroup *groups, int n_groups, const DevTerm *terms,
+                          const double *theta, float2 *psi_out, double *energy, double *grad, int *queue,
+                          bool adjoint, int grid, hipStream_t s);
+
+}  // namespace qsv

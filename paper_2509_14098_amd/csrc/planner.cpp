@@ -1,0 +1,434 @@
+// Host planner: gate classification, contraction graph, closeness centrality,
+// greedy frontier partitioning (two levels) and lowering to device tables.
+//
+// Paper references (arXiv:2509.14098):
+//   Section 4.1, Fig. 4  contraction graph and critical-path lengths l_v
+//   Section 4.2, Eq. 10-13, Fig. 5  closeness centrality and the forward
+//                        frontier sweep with its two locality exemptions
+//   Section 4.3, Fig. 6  partition tree, tiles and on-chip buffers
+// All graph quantities are integers; centralities are compared exactly.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <stdexcept>
+
+#include "internal.h"
+
+namespace qsv {
+
+using cd = std::complex<double>;
+
+static int popc(uint64_t x) { return __builtin_popcountll(x); }
+
+static int arity(int kind)
+{
+    if ((kind >= QSV_H && kind <= QSV_U3) || kind == QSV_MAT1) return 1;
+    if ((kind >= QSV_CX && kind <= QSV_RZZ) || kind == QSV_MAT2) return 2;
+    return 0;
+}
+
+static bool is_rotation(int kind) { return kind == QSV_RX || kind == QSV_RY || kind == QSV_RZ || kind == QSV_RZZ; }
+
+std::string validate_gate(const qsv_gate &g, int n, int64_t)
+{
+    int k = arity(g.kind);
+    if (k == 0) return "unknown gate kind " + std::to_string(g.kind);
+    if (g.q0 < 0 || g.q0 >= n) return "qubit q0 out of range";
+    if (k == 2 && (g.q1 < 0 || g.q1 >= n)) return "qubit q1 out of range";
+    if (k == 2 && g.q1 == g.q0) return "two-qubit gate on one qubit";
+    if (g.param >= 0 && !is_rotation(g.kind)) return "param on a non-rotation gate";
+    return "";
+}
+
+// Gate matrix in float64 (textbook / OpenQASM 2 definitions), row-major, local
+// index j = b(q0) + 2 b(q1) for two-qubit gates.
+static void fixed_matrix(const qsv_gate &g, cd m[16])
+{
+    for (int i = 0; i < 16; ++i) m[i] = 0.0;
+    const double a = g.angle[0];
+    const double h = 1.0 / std::sqrt(2.0);
+    const cd I(0.0, 1.0);
+    switch (g.kind) {
+    case QSV_H: m[0] = h; m[1] = h; m[2] = h; m[3] = -h; break;
+    case QSV_X: m[1] = 1.0; m[2] = 1.0; break;
+    case QSV_Y: m[1] = -I; m[2] = I; break;
+    case QSV_Z: m[0] = 1.0; m[3] = -1.0; break;
+    case QSV_S: m[0] = 1.0; m[3] = I; break;
+    case QSV_SDG: m[0] = 1.0; m[3] = -I; break;
+    case QSV_T: m[0] = 1.0; m[3] = std::exp(I * (M_PI / 4.0)); break;
+    case QSV_TDG: m[0] = 1.0; m[3] = std::exp(-I * (M_PI / 4.0)); break;
+    case QSV_SX: m[0] = cd(0.5, 0.5); m[1] = cd(0.5, -0.5); m[2] = cd(0.5, -0.5); m[3] = cd(0.5, 0.5); break;
+    case QSV_RX: m[0] = std::cos(a / 2); m[1] = -I * std::sin(a / 2); m[2] = -I * std::sin(a / 2); m[3] = std::cos(a / 2); break;
+    case QSV_RY: m[0] = std::cos(a / 2); m[1] = -std::sin(a / 2); m[2] = std::sin(a / 2); m[3] = std::cos(a / 2); break;
+    case QSV_RZ: m[0] = std::exp(-I * (a / 2)); m[3] = std::exp(I * (a / 2)); break;
+    case QSV_P: m[0] = 1.0; m[3] = std::exp(I * a); break;
+    case QSV_U3: {
+        double t = g.angle[0], p = g.angle[1], l = g.angle[2];
+        m[0] = std::cos(t / 2);
+        m[1] = -std::exp(I * l) * std::sin(t / 2);
+        m[2] = std::exp(I * p) * std::sin(t / 2);
+        m[3] = std::exp(I * (p + l)) * std::cos(t / 2);
+        break;
+    }
+    case QSV_MAT1: for (int i = 0; i < 4; ++i) m[i] = cd(g.mat[2 * i], g.mat[2 * i + 1]); break;
+    case QSV_CX: m[0] = 1.0; m[10] = 1.0; m[1 * 4 + 3] = 1.0; m[3 * 4 + 1] = 1.0; break;
+    case QSV_CY: m[0] = 1.0; m[10] = 1.0; m[1 * 4 + 3] = -I; m[3 * 4 + 1] = I; break;
+    case QSV_CZ: m[0] = 1.0; m[5] = 1.0; m[10] = 1.0; m[15] = -1.0; break;
+    case QSV_CP: m[0] = 1.0; m[5] = 1.0; m[10] = 1.0; m[15] = std::exp(I * a); break;
+    case QSV_SWAP: m[0] = 1.0; m[1 * 4 + 2] = 1.0; m[2 * 4 + 1] = 1.0; m[15] = 1.0; break;
+    case QSV_RZZ:
+        m[0] = std::exp(-I * (a / 2)); m[5] = std::exp(I * (a / 2)); m[10] = std::exp(I * (a / 2)); m[15] = std::exp(-I * (a / 2));
+        break;
+    case QSV_MAT2: for (int i = 0; i < 16; ++i) m[i] = cd(g.mat[2 * i], g.mat[2 * i + 1]); break;
+    default: break;
+    }
+}
+
+GateMeta classify(const qsv_gate &g)
+{
+    GateMeta r;
+    r.nq = arity(g.kind);
+    r.q[0] = g.q0;
+    r.q[1] = r.nq == 2 ? g.q1 : -1;
+    r.qmask = (1ull << g.q0) | (r.nq == 2 ? (1ull << g.q1) : 0ull);
+    r.param = g.param >= 0;
+    if (r.param) {  // structure for a generic angle; matrix formed on the device
+        switch (g.kind) {
+        case QSV_RX: r.op = OP_U1; r.req = r.qmask; r.gen = GEN_X; r.flops = 16; break;
+        case QSV_RY: r.op = OP_R1; r.req = r.qmask; r.gen = GEN_Y; r.flops = 8; break;
+        case QSV_RZ: r.op = OP_D1; r.req = 0; r.gen = GEN_Z; r.flops = 6; break;
+        default: r.op = OP_D2; r.req = 0; r.gen = GEN_ZZ; r.flops = 6; break;  // RZZ
+        }
+        return r;
+    }
+    cd m[16];
+    fixed_matrix(g, m);
+    for (int i = 0; i < 16; ++i) { r.m[2 * i] = m[i].real(); r.m[2 * i + 1] = m[i].imag(); }
+    if (r.nq == 1) {
+        bool diag = m[1] == 0.0 && m[2] == 0.0;
+        bool real = m[0].imag() == 0 && m[1].imag() == 0 && m[2].imag() == 0 && m[3].imag() == 0;
+        if (diag) { r.op = OP_D1; r.req = 0; r.flops = 6; }
+        else if (real) { r.op = OP_R1; r.req = r.qmask; r.flops = 8; }
+        else { r.op = OP_U1; r.req = r.qmask; r.flops = 16; }
+        return r;
+    }
+    auto at = [&](int i, int j) { return m[i * 4 + j]; };
+    bool diag = true;
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j)
+            if (i != j && at(i, j) != 0.0) diag = false;
+    if (diag) {
+        bool cz = at(0, 0) == 1.0 && at(1, 1) == 1.0 && at(2, 2) == 1.0 && at(3, 3) == -1.0;
+        r.op = cz ? OP_CZ : OP_D2;
+        r.req = 0;
+        r.flops = cz ? 0 : 6;
+        return r;
+    }
+    // controlled structure: identity while the control is 0 and no mixing of
+    // the control value (Section 4.2 second exemption)
+    for (int c = 0; c < 2; ++c) {
+        int z[2], o[2];
+        if (c == 0) { z[0] = 0; z[1] = 2; o[0] = 1; o[1] = 3; }
+        else { z[0] = 0; z[1] = 1; o[0] = 2; o[1] = 3; }
+        bool mixing = false, ident = true;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                if (at(z[a], o[b]) != 0.0 || at(o[a], z[b]) != 0.0) mixing = true;
+                if (at(z[a], z[b]) != (a == b ? 1.0 : 0.0)) ident = false;
+            }
+        if (!mixing && ident) {
+            r.ctrl = r.q[c];
+            r.tgt = r.q[1 - c];
+            r.req = 1ull << r.tgt;
+            cd u[4] = {at(o[0], o[0]), at(o[0], o[1]), at(o[1], o[0]), at(o[1], o[1])};
+            for (int i = 0; i < 4; ++i) { r.m[2 * i] = u[i].real(); r.m[2 * i + 1] = u[i].imag(); }
+            for (int i = 8; i < 32; ++i) r.m[i] = 0;
+            bool x = u[0] == 0.0 && u[3] == 0.0 && u[1] == 1.0 && u[2] == 1.0;
+            r.op = x ? OP_CX : OP_CU;
+            r.flops = x ? 0 : 8;
+            return r;
+        }
+    }
+    bool swap = true;
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            int pj = (j == 1) ? 2 : (j == 2) ? 1 : j;
+            if (at(i, j) != (i == pj ? 1.0 : 0.0)) swap = false;
+        }
+    r.op = swap ? OP_SWAP : OP_U2;
+    r.req = r.qmask;
+    r.flops = swap ? 0 : 32;
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Greedy frontier partition of the gates `sub` (in circuit order) into parts
+// of at most k required-local qubits.
+//
+// Contraction graph: node 0 is the incoming state tensor, node i+1 the gate
+// sub[i]; every qubit of a gate adds an edge from the previous tensor on that
+// qubit.  l(0) = 0, l(v) = 1 + max l(pred).  RN(v) = all downstream nodes,
+// dist(v) = sum_{w in RN(v)} (l_w - l_v) (the telescoped form of Eq. 12-13),
+// CC(v) = |RN|^2 / (N dist) (Eq. 10 with the Wasserman-Faust factor) or 0 when
+// RN is empty.  Frontier sweep: among the gates whose predecessors are all
+// placed, take the one of highest CC (then lower l, then lower index) whose
+// required qubits fit; grow S by all its qubits (those in `allowed`) if they
+// fit, else by the required ones; close the part when nothing fits.  The
+// returned S are not padded.
+// ---------------------------------------------------------------------------
+std::vector<Part> greedy_partition(int n, const std::vector<GateMeta> &meta, const std::vector<int> &sub, int k,
+                                   uint64_t allowed)
+{
+    const int G = (int)sub.size();
+    std::vector<Part> parts;
+    if (G == 0) return parts;
+    const int N = G + 1;
+    std::vector<int> pred0(N, -1), pred1(N, -1);
+    std::vector<std::vector<int>> succ(N);
+    std::vector<int> last(n, 0), l(N, 0);
+    for (int i = 0; i < G; ++i) {
+        const GateMeta &g = meta[sub[i]];
+        int v = i + 1, u0 = last[g.q[0]], u1 = g.nq == 2 ? last[g.q[1]] : -1;
+        pred0[v] = u0;
+        succ[u0].push_back(v);
+        if (u1 >= 0 && u1 != u0) { pred1[v] = u1; succ[u1].push_back(v); }
+        l[v] = 1 + std::max(l[u0], u1 >= 0 ? l[u1] : 0);
+        last[g.q[0]] = v;
+        if (g.nq == 2) last[g.q[1]] = v;
+    }
+    // reachable sets as bitsets, filled from the last node backwards
+    const int words = (N + 63) / 64;
+    std::vector<uint64_t> rn((size_t)N * words, 0);
+    std::vector<int64_t> size(N, 0), dist(N, 0);
+    for (int v = N - 1; v >= 0; --v) {
+        uint64_t *rv = &rn[(size_t)v * words];
+        for (int c : succ[v]) {
+            const uint64_t *rc = &rn[(size_t)c * words];
+            for (int w = 0; w < words; ++w) rv[w] |= rc[w];
+            rv[c >> 6] |= 1ull << (c & 63);
+        }
+        int64_t cnt = 0, suml = 0;
+        for (int w = 0; w < words; ++w) {
+            uint64_t x = rv[w];
+            cnt += popc(x);
+            while (x) {
+                int b = __builtin_ctzll(x);
+                suml += l[w * 64 + b];
+                x &= x - 1;
+            }
+        }
+        size[v] = cnt;
+        dist[v] = suml - cnt * (int64_t)l[v];
+    }
+    // exact comparison of (CC desc, l asc, index asc)
+    auto better = [&](int a, int b) {
+        if (size[a] == 0 || size[b] == 0) {
+            if (size[a] != 0) return true;
+            if (size[b] != 0) return false;
+        } else {
+            unsigned __int128 lhs = (unsigned __int128)(size[a] * size[a]) * (uint64_t)dist[b];
+            unsigned __int128 rhs = (unsigned __int128)(size[b] * size[b]) * (uint64_t)dist[a];
+            if (lhs != rhs) return lhs > rhs;
+        }
+        if (l[a] != l[b]) return l[a] < l[b];
+        return a < b;
+    };
+    std::vector<int> missing(N, 0), ready;
+    for (int v = 1; v < N; ++v) {
+        missing[v] = (pred0[v] > 0) + (pred1[v] > 0);
+        if (missing[v] == 0) ready.push_back(v);
+    }
+    int placed = 0;
+    while (placed < G) {
+        Part part;
+        while (true) {
+            int best = -1;
+            for (int v : ready) {
+                const GateMeta &g = meta[sub[v - 1]];
+                if (popc(part.S | g.req) <= k && (best < 0 || better(v, best))) best = v;
+            }
+            if (best < 0) break;
+            const GateMeta &g = meta[sub[best - 1]];
+            uint64_t grow = g.qmask & allowed;
+            part.S = popc(part.S | grow) <= k ? (part.S | grow) : (part.S | g.req);
+            part.gates.push_back(sub[best - 1]);
+            ready.erase(std::find(ready.begin(), ready.end(), best));
+            for (int w : succ[best])
+                if (--missing[w] == 0) ready.push_back(w);
+            ++placed;
+        }
+        if (part.gates.empty()) throw std::logic_error("partitioner made no progress");
+        parts.push_back(std::move(part));
+    }
+    return parts;
+}
+
+// ---------------------------------------------------------------------------
+// Lowering
+// ---------------------------------------------------------------------------
+static uint64_t pad_low(uint64_t S, int n, int k)
+{
+    for (int q = 0; q < n && popc(S) < k; ++q) S |= 1ull << q;
+    return S;
+}
+
+// Register/lane/wave layout of a stage.  Register slots take the stage's
+// required qubits, padded with the highest free tile positions; lanes 0..4
+// take free positions with distinct residues mod 5 where possible, so that the
+// XOR-swizzled LDS addresses of a half-wave fall into distinct 8-byte bank
+// slots; the other thread bits take the remaining positions in order.
+static void stage_layout(uint32_t reg_posmask, int t, int R, int w, DevStage &st)
+{
+    std::vector<int> reg, freep;
+    for (int p = 0; p < t; ++p) ((reg_posmask >> p) & 1 ? reg : freep).push_back(p);
+    while ((int)reg.size() < R) {
+        reg.push_back(freep.back());
+        freep.pop_back();
+    }
+    std::sort(reg.begin(), reg.end());
+    for (int j = 0; j < R; ++j) st.regpos[j] = reg[j];
+    std::vector<int> lanes;
+    std::vector<bool> used(freep.size(), false);
+    int want = std::min(5, w);
+    bool res[5] = {false, false, false, false, false};
+    for (size_t i = 0; i < freep.size() && (int)lanes.size() < want; ++i)
+        if (!res[freep[i] % 5]) { res[freep[i] % 5] = true; lanes.push_back(freep[i]); used[i] = true; }
+    for (size_t i = 0; i < freep.size() && (int)lanes.size() < want; ++i)
+        if (!used[i]) { lanes.push_back(freep[i]); used[i] = true; }
+    for (size_t i = 0; i < freep.size(); ++i)
+        if (!used[i]) lanes.push_back(freep[i]);
+    for (int b = 0; b < w; ++b) st.thrpos[b] = lanes[b];
+}
+
+void build_plan(Plan &P)
+{
+    const int n = P.n;
+    P.meta.resize(P.gates.size());
+    for (size_t i = 0; i < P.gates.size(); ++i) P.meta[i] = classify(P.gates[i]);
+
+    // matrix pool entries, one per gate
+    std::vector<int32_t> mat_of(P.gates.size(), -1);
+    for (size_t i = 0; i < P.gates.size(); ++i) {
+        const GateMeta &m = P.meta[i];
+        if (m.op == OP_CX || m.op == OP_CZ || m.op == OP_SWAP) continue;
+        int len = m.op == OP_U2 ? 32 : 8;
+        mat_of[i] = (int32_t)P.pool.size();
+        if (m.op == OP_D2) {  // diagonal entries j = b(q0) + 2 b(q1)
+            for (int j = 0; j < 4; ++j) {
+                P.pool.push_back((float)m.m[2 * (j * 4 + j)]);
+                P.pool.push_back((float)m.m[2 * (j * 4 + j) + 1]);
+            }
+        } else {
+            for (int j = 0; j < len; ++j) P.pool.push_back((float)m.m[j]);
+        }
+    }
+
+    P.flops = 0;
+    P.bytes = 0;
+    const double dim = std::ldexp(1.0, n);
+    for (auto &C : P.circ) {
+        for (int64_t g = C.g0; g < C.g1; ++g) {
+            P.flops += P.meta[g].flops * dim;
+            if (P.meta[g].param) {
+                ParamGate pg;
+                pg.mat = mat_of[g];
+                pg.kind = P.gates[g].kind;
+                pg.theta_index = (int32_t)(C.theta_off + P.gates[g].param);
+                pg.pad = 0;
+                P.pgates.push_back(pg);
+            }
+        }
+        std::vector<int> all;
+        for (int64_t g = C.g0; g < C.g1; ++g) all.push_back((int)g);
+        const int t = std::min(P.t, n);
+        const int R = std::min(P.R, t);
+        const int w = t - R;
+        const int k = std::min(P.k, n);
+        // level 1: partitions of at most k local qubits (padded to min(k, n))
+        if (P.flags & QSV_PLAN_GATE_BY_GATE) {
+            for (int g : all) {
+                Part p;
+                p.S = P.meta[g].qmask;
+                p.gates.push_back(g);
+                C.parts.push_back(p);
+            }
+        } else {
+            C.parts = greedy_partition(n, P.meta, all, k, ~0ull);
+        }
+        C.part_begin = (int32_t)P.parts.size();
+        for (auto &part : C.parts) {
+            part.S = pad_low(part.S, n, std::min(k, n));
+            uint64_t T = part.S;
+            for (int q = 0; q < n && popc(T) < t; ++q) T |= 1ull << q;
+            DevPart dp;
+            std::memset(&dp, 0, sizeof(dp));
+            dp.t = t;
+            dp.n_glb = n - t;
+            int pos_of[64];
+            for (int q = 0, c = 0, b = 0; q < n; ++q) {
+                if ((T >> q) & 1) { dp.tq[c] = q; pos_of[q] = c++; }
+                else { dp.gq[b++] = q; pos_of[q] = -1; }
+            }
+            // level 2: register stages of this partition
+            std::vector<Part> st = greedy_partition(n, P.meta, part.gates, R, T);
+            dp.stage_begin = (int32_t)P.stages.size();
+            for (auto &s : st) {
+                DevStage ds;
+                std::memset(&ds, 0, sizeof(ds));
+                uint32_t posmask = 0;
+                for (int q = 0; q < n; ++q)
+                    if ((s.S >> q) & 1) posmask |= 1u << pos_of[q];
+                stage_layout(posmask, t, R, w, ds);
+                uint64_t regq = 0;
+                for (int j = 0; j < R; ++j) regq |= 1ull << dp.tq[ds.regpos[j]];
+                s.S = regq;
+                auto loc = [&](int q) -> int32_t {
+                    if (pos_of[q] < 0) return LOC_GLB | q;
+                    for (int j = 0; j < R; ++j)
+                        if (ds.regpos[j] == pos_of[q]) return LOC_REG | j;
+                    for (int b = 0; b < w; ++b)
+                        if (ds.thrpos[b] == pos_of[q]) return LOC_THR | b;
+                    throw std::logic_error("qubit not in layout");
+                };
+                ds.op_begin = (int32_t)P.ops.size();
+                for (int g : s.gates) {
+                    const GateMeta &m = P.meta[g];
+                    DevOp o;
+                    std::memset(&o, 0, sizeof(o));
+                    o.kind = m.op;
+                    o.gen = m.gen;
+                    o.mat = mat_of[g];
+                    o.gate = g;
+                    o.grad_slot = -1;
+                    if (m.param) {
+                        o.grad_slot = (int32_t)P.grad_param.size();
+                        P.grad_param.push_back((int32_t)(C.theta_off + P.gates[g].param));
+                    }
+                    if (m.op == OP_CX || m.op == OP_CU) { o.a = loc(m.ctrl); o.b = loc(m.tgt); }
+                    else { o.a = loc(m.q[0]); o.b = m.nq == 2 ? loc(m.q[1]) : 0; }
+                    bool need_reg_a = m.op == OP_U1 || m.op == OP_R1 || m.op == OP_U2 || m.op == OP_SWAP;
+                    bool need_reg_b = m.op == OP_CX || m.op == OP_CU || m.op == OP_U2 || m.op == OP_SWAP;
+                    if ((need_reg_a && (o.a & LOC_MASK) != LOC_REG) || (need_reg_b && (o.b & LOC_MASK) != LOC_REG))
+                        throw std::logic_error("required qubit not in registers");
+                    P.ops.push_back(o);
+                }
+                ds.op_end = (int32_t)P.ops.size();
+                P.stages.push_back(ds);
+            }
+            dp.stage_end = (int32_t)P.stages.size();
+            C.stages.push_back(std::move(st));
+            P.parts.push_back(dp);
+            P.bytes += 16.0 * dim;
+        }
+    }
+    // theta index -> gradient slots, in slot order (deterministic sums)
+    P.param_off.assign(P.n_params + 1, 0);
+    for (int32_t p : P.grad_param) P.param_off[p + 1]++;
+    for (int64_t i = 0; i < P.n_params; ++i) P.param_off[i + 1] += P.param_off[i];
+    P.param_slots.assign(P.grad_param.size(), 0);
+    std::vector<int32_t> fill(P.param_off.begin(), P.param_off.end() - (P.n_params >= 0 ? 1 : 0));
+    for (size_t s = 0; s < P.grad_param.size(); ++s) P.param_slots[fill[P.grad_param[s]]++] = (int32_t)s;
+}
+
+}  // namespace qsv

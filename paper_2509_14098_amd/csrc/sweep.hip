@@ -1,0 +1,196 @@
+// Fused partition sweep (paper Section 4.3): one launch applies all gates of
+// one partition to every tile of the state.
+//
+// Per workgroup (one tile of 2^t amplitudes: the partition's t tile qubits
+// vary, the other n - t qubits are fixed by the tile index):
+//   1. HBM -> LDS: 16-byte loads of amplitude pairs (tile position 0 is qubit
+//      0, so each pair is contiguous in HBM); runs of 2^c contiguous
+//      amplitudes where the c lowest qubits are in the tile;
+//   2. for every register stage: LDS -> registers in the stage layout, the
+//      stage's gates in registers, registers -> LDS, barrier;
+//   3. LDS -> HBM (and, when asked, the same tile to the checkpoint buffer).
+// The LDS tile is XOR-swizzled (swz) against bank conflicts.
+#include <hip/hip_runtime.h>
+
+#include "gates.cuh"
+#include "kernels.h"
+
+namespace qsv {
+
+// Global amplitude offset of canonical tile bits [lo, hi) of c.
+__device__ __forceinline__ uint64_t tile_offset(const DevPart *__restrict__ P, uint32_t c, int lo, int hi)
+{
+    uint64_t g = 0;
+    for (int b = lo; b < hi; ++b)
+        if ((c >> b) & 1u) g |= 1ull << P->tq[b];
+    return g;
+}
+
+template <int R, int LW>
+__device__ __forceinline__ uint64_t tile_base(const DevPart *__restrict__ P, uint64_t tile)
+{
+    uint64_t base = 0;
+    for (int b = 0; b < P->n_glb; ++b)
+        if ((tile >> b) & 1ull) base |= 1ull << P->gq[b];
+    return base;
+}
+
+// Load the tile HBM -> LDS.  Pair p covers canonical positions 2p, 2p+1.
+template <int LW>
+__device__ __forceinline__ void load_tile(const float2 *__restrict__ psi, float2 *lds, const DevPart *__restrict__ P,
+                                          uint64_t base, uint32_t tid)
+{
+    const int t = P->t;
+    const uint32_t npairs = 1u << (t - 1);
+    const int thr_hi = (LW + 1 < t) ? LW + 1 : t;
+    const uint64_t gthr = tile_offset(P, 2u * tid, 1, thr_hi);
+    for (uint32_t p0 = 0; p0 < npairs; p0 += (1u << LW)) {
+        const uint32_t p = p0 + tid;
+        if (p < npairs) {
+            const uint64_t g = base | gthr | tile_offset(P, 2u * p0, LW + 1, t);
+            const float4 v = *reinterpret_cast<const float4 *>(psi + g);
+            const uint32_t c = 2u * p;
+            lds[swz(c)] = float2{v.x, v.y};
+            lds[swz(c + 1)] = float2{v.z, v.w};
+        }
+    }
+}
+
+template <int LW>
+__device__ __forceinline__ void store_tile(float2 *__restrict__ psi, float2 *__restrict__ ckpt, const float2 *lds,
+                                           const DevPart *__restrict__ P, uint64_t base, uint32_t tid)
+{
+    const int t = P->t;
+    const uint32_t npairs = 1u << (t - 1);
+    const int thr_hi = (LW + 1 < t) ? LW + 1 : t;
+    const uint64_t gthr = tile_offset(P, 2u * tid, 1, thr_hi);
+    for (uint32_t p0 = 0; p0 < npairs; p0 += (1u << LW)) {
+        const uint32_t p = p0 + tid;
+        if (p < npairs) {
+            const uint64_t g = base | gthr | tile_offset(P, 2u * p0, LW + 1, t);
+            const uint32_t c = 2u * p;
+            const float2 x = lds[swz(c)], y = lds[swz(c + 1)];
+            const float4 v{x.x, x.y, y.x, y.y};
+            *reinterpret_cast<float4 *>(psi + g) = v;
+            if (ckpt) *reinterpret_cast<float4 *>(ckpt + g) = v;
+        }
+    }
+}
+
+// Run the register stages [s0, s1) of a tile held in LDS.
+template <int R, bool DAG>
+__device__ __forceinline__ void run_stages(float2 *lds, const DevStage *__restrict__ stages, const DevOp *__restrict__ ops,
+                                           const float *__restrict__ pool, int s0, int s1, int w, uint32_t tid,
+                                           uint64_t base)
+{
+    constexpr int NA = 1 << R;
+    const bool active = tid < (1u << w);
+    for (int s = s0; s < s1; ++s) {
+        const DevStage *__restrict__ S = stages + s;
+        if (active) {
+            uint32_t toff = 0;
+            for (int b = 0; b < w; ++b) toff |= ((tid >> b) & 1u) << S->thrpos[b];
+            uint32_t roff[NA];
+            roff[0] = 0;
+#pragma unroll
+            for (int i = 1; i < NA; ++i) roff[i] = roff[i & (i - 1)] | (1u << S->regpos[__builtin_ctz(i)]);
+            float2 a[NA];
+#pragma unroll
+            for (int i = 0; i < NA; ++i) a[i] = lds[swz(toff | roff[i])];
+            for (int k = S->op_begin; k < S->op_end; ++k) apply_op<R, DAG>(a, ops[k], pool, tid, base);
+#pragma unroll
+            for (int i = 0; i < NA; ++i) lds[swz(toff | roff[i])] = a[i];
+        }
+        __syncthreads();
+    }
+}
+
+template <int R, int LW>
+__global__ __launch_bounds__(1 << LW) void sweep_kernel(float2 *__restrict__ psi, float2 *__restrict__ ckpt,
+                                                          const DevPart *__restrict__ parts, int pidx,
+                                                          const DevStage *__restrict__ stages,
+                                                          const DevOp *__restrict__ ops,
+                                                          const float *__restrict__ pool)
+{
+    extern __shared__ float2 lds[];
+    const DevPart *__restrict__ P = parts + pidx;
+    const uint32_t tid = threadIdx.x;
+    const uint64_t base = tile_base<R, LW>(P, blockIdx.x);
+    load_tile<LW>(psi, lds, P, base, tid);
+    __syncthreads();
+    run_stages<R, false>(lds, stages, ops, pool, P->stage_begin, P->stage_end, P->t - R, tid, base);
+    store_tile<LW>(psi, ckpt, lds, P, base, tid);
+}
+
+// Rotation matrices from theta: cos/sin in float64, rounded to float32.
+__global__ void materialize_kernel(const ParamGate *__restrict__ pg, int n, const double *__restrict__ theta,
+                                   float *__restrict__ pool)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const ParamGate g = pg[i];
+    const double a = theta[g.theta_index];
+    double s, c;
+    sincos(0.5 * a, &s, &c);
+    float *m = pool + g.mat;
+    for (int k = 0; k < 8; ++k) m[k] = 0.f;
+    switch (g.kind) {
+    case QSV_RX:  // [[c, -i s], [-i s, c]]
+        m[0] = (float)c; m[3] = (float)-s; m[5] = (float)-s; m[6] = (float)c; break;
+    case QSV_RY:  // [[c, -s], [s, c]]
+        m[0] = (float)c; m[2] = (float)-s; m[4] = (float)s; m[6] = (float)c; break;
+    case QSV_RZ:  // diag(e^{-ia/2}, e^{ia/2}) as a full 2x2
+        m[0] = (float)c; m[1] = (float)-s; m[6] = (float)c; m[7] = (float)s; break;
+    default:      // RZZ: diagonal entries j = b(q0) + 2 b(q1): even parity e^{-ia/2}
+        m[0] = (float)c; m[1] = (float)-s; m[2] = (float)c; m[3] = (float)s;
+        m[4] = (float)c; m[5] = (float)s; m[6] = (float)c; m[7] = (float)-s; break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+template <int R, int LW>
+static hipError_t launch_sweep_t(const Plan &plan, int pidx, float2 *psi, float2 *ckpt, hipStream_t s)
+{
+    const DevPart &P = plan.parts[pidx];
+    const size_t lds = (size_t)8 << P.t;
+    static bool attr = false;
+    if (!attr) {  // allow the full 160 KiB of LDS (advisory: ignored where not needed)
+        (void)hipFuncSetAttribute((const void *)sweep_kernel<R, LW>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024);
+        (void)hipGetLastError();
+        attr = true;
+    }
+    const uint64_t tiles = 1ull << P.n_glb;
+    hipLaunchKernelGGL((sweep_kernel<R, LW>), dim3((uint32_t)tiles), dim3(1 << LW), lds, s, psi, ckpt,
+                       plan.d_parts, pidx, plan.d_stages, plan.d_ops, plan.d_pool);
+    return hipGetLastError();
+}
+
+bool kernel_shape_supported(int R, int LW)
+{
+    return (LW == 6 && R >= 1 && R <= 5) || (LW == 8 && R >= 3 && R <= 5) || (LW == 9 && (R == 4 || R == 5)) || (LW == 10 && R == 4);
+}
+
+hipError_t launch_sweep(const Plan &plan, int R, int LW, int pidx, float2 *psi, float2 *ckpt, hipStream_t s)
+{
+#define QSV_CASE(r, lw) \
+    if (R == r && LW == lw) return launch_sweep_t<r, lw>(plan, pidx, psi, ckpt, s);
+    QSV_CASE(1, 6) QSV_CASE(2, 6) QSV_CASE(3, 6) QSV_CASE(4, 6) QSV_CASE(5, 6)
+    QSV_CASE(3, 8) QSV_CASE(4, 8) QSV_CASE(5, 8)
+    QSV_CASE(4, 9) QSV_CASE(5, 9) QSV_CASE(4, 10)
+#undef QSV_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_materialize(const Plan &plan, const double *theta, hipStream_t s)
+{
+    const int n = (int)plan.pgates.size();
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(materialize_kernel, dim3((n + 255) / 256), dim3(256), 0, s, plan.d_pgates, n, theta,
+                       plan.d_pool);
+    return hipGetLastError();
+}
+
+}  // namespace qsv

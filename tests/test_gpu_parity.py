@@ -1,0 +1,274 @@
+"""GPU parity: the HIP path (through the C interface) against the complex128
+oracle on the same seeded inputs.  Tolerance (from the target precision
+policy): max |amplitude error| <= 1e-5; the relative l2 error and 1 - fidelity
+are reported and bounded too, since max-abs alone is weak when amplitudes are
+small (2^-14 at 28 qubits)."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2509_14098_amd as Q
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def sim():
+    s = Q.Simulator(0)
+    yield s
+    s.close()
+
+
+def run(sim, n, gates, k=0, flags=0, tile=None, theta=None, psi=None):
+    plan = sim.partition(n, gates, k, flags, tile)
+    try:
+        psi = sim.zero_state(n) if psi is None else psi
+        sim.apply(plan, psi, theta)
+        torch.cuda.synchronize()
+        return psi, plan.info
+    finally:
+        plan.close()
+
+
+def errors(gpu, ref):
+    gpu = np.asarray(gpu, dtype=np.complex128)
+    d = gpu - ref
+    maxabs = float(np.max(np.abs(d)))
+    rel = float(np.linalg.norm(d) / np.linalg.norm(ref))
+    fid = float(abs(np.vdot(ref, gpu)) ** 2 / (np.vdot(ref, ref).real * np.vdot(gpu, gpu).real))
+    return maxabs, rel, 1 - fid
+
+
+def assert_close(gpu, ref, tol=TOL, rel_tol=1e-5):
+    m, r, f = errors(gpu, ref)
+    assert m <= tol and r <= rel_tol, f"max-abs {m:.3e} rel-l2 {r:.3e} 1-F {f:.3e}"
+
+
+# ---------------------------------------------------------------- worked example and closed forms
+
+def test_ghz3_worked_example(sim):
+    psi, info = run(sim, 3, W.ghz(3), k=2)
+    assert info["n_partitions"] == 2
+    ref = np.zeros(8, complex)
+    ref[0] = ref[7] = 2 ** -0.5
+    assert_close(psi.cpu().numpy(), ref, 1e-7)
+
+
+@pytest.mark.parametrize("n", [1, 2, 6, 13, 20])
+def test_ghz_and_uniform(sim, n):
+    psi, _ = run(sim, n, W.ghz(n))
+    ref = np.zeros(1 << n, complex)
+    ref[0] = ref[-1] = 2 ** -0.5
+    assert_close(psi.cpu().numpy(), ref, 1e-6)
+    psi, _ = run(sim, n, W.uniform_h(n))
+    assert np.max(np.abs(psi.cpu().numpy() - 2 ** (-n / 2))) < 1e-6
+
+
+# ---------------------------------------------------------------- random circuits, every kernel shape
+
+CASES = [
+    # n, gates, k, tile
+    (1, 20, 1, None), (2, 40, 2, None), (3, 60, 2, (3, 6)), (4, 60, 3, (2, 6)), (5, 80, 4, (5, 6)),
+    (7, 100, 5, (4, 6)), (9, 150, 6, (3, 8)), (11, 200, 7, (4, 8)), (12, 200, 8, (5, 8)), (13, 250, 10, (5, 8)),
+    (14, 250, 9, (4, 8)), (15, 250, 12, (5, 8)), (15, 250, 11, (4, 9)), (16, 300, 12, (5, 9)),
+    (17, 300, 10, (4, 10)), (18, 300, 10, (3, 8)), (19, 300, 8, (5, 8)), (20, 300, 12, (5, 8)),
+]
+
+
+@pytest.mark.parametrize("n,ng,k,tile", CASES)
+def test_random_circuit_parity(sim, n, ng, k, tile):
+    theta = np.random.default_rng(n).uniform(-3, 3, size=5)
+    gates = W.random_circuit(n, ng, seed=1000 + n, n_params=5)
+    ref = oracle.apply(n, gates, theta)
+    psi, info = run(sim, n, gates, k=k, tile=tile, theta=theta)
+    assert_close(psi.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("n", [3, 11, 14, 17])
+def test_gate_by_gate_equals_fused(sim, n):
+    gates = W.random_circuit(n, 120, seed=77 + n)
+    ref = oracle.apply(n, gates)
+    a, _ = run(sim, n, gates, k=min(n, 8), flags=Q.PLAN_GATE_BY_GATE)
+    b, _ = run(sim, n, gates, k=min(n, 8))
+    assert_close(a.cpu().numpy(), ref)
+    assert_close(b.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("n", [10, 16])
+def test_every_gate_kind_in_every_position(sim, n):
+    """One circuit per kind with its qubits drawn over the whole register, so
+    each kind lands on register, lane, wave and tile-index bits."""
+    for kind in W.KIND:
+        gates = W.random_circuit(n, 60, seed=W.KIND[kind] + 31 * n, kinds=[kind, "H", "U3"])
+        ref = oracle.apply(n, gates)
+        psi, _ = run(sim, n, gates, k=min(n, 6), tile=(4, 8))
+        assert_close(psi.cpu().numpy(), ref)
+
+
+# ---------------------------------------------------------------- benchmark workloads
+
+def test_c1_full(sim):
+    gates = W.brickwork_c1()
+    ref = oracle.apply(12, gates)
+    psi, _ = run(sim, 12, gates)
+    assert_close(psi.cpu().numpy(), ref)
+    z0 = sim.expect(W.z_on(0), psi, 12)
+    assert abs(float(z0[0]) - oracle.expect(12, W.z_on(0), ref)) < 1e-6
+    for k in (6, 8, 10):
+        psi, _ = run(sim, 12, gates, k=k)
+        assert_close(psi.cpu().numpy(), ref)
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, name + ".npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    return np.load(path, allow_pickle=False)
+
+
+@pytest.mark.parametrize("name,gen,k", [("c3n24", lambda: W.brickwork_c3(n=24), 10),
+                                        ("c3n26", lambda: W.brickwork_c3(n=26), 12)])
+def test_c3_reduced_vs_golden(sim, name, gen, k):
+    g = _golden(name)
+    n = int(g["n"])
+    gates = gen()
+    assert W.circuit_hash(gates, n) == g["circuit_sha256"].item().decode()
+    psi, _ = run(sim, n, gates, k=k)
+    got = psi[torch.as_tensor(g["idx"], device=psi.device)].cpu().numpy()
+    assert np.max(np.abs(got - g["amp"])) <= TOL
+    zz = float(sim.expect(W.zz_chain(n), psi, n)[0])
+    assert abs(zz - float(g["zz"])) < 1e-5
+
+
+def test_c2_full_vs_golden(sim):
+    g = _golden("c2")
+    gates = W.brickwork_c2()
+    assert W.circuit_hash(gates, 28) == g["circuit_sha256"].item().decode()
+    for flags in (0, Q.PLAN_GATE_BY_GATE):
+        psi, _ = run(sim, 28, gates, k=10, flags=flags)
+        got = psi[torch.as_tensor(g["idx"], device=psi.device)].cpu().numpy()
+        m = np.max(np.abs(got - g["amp"]))
+        rel = np.linalg.norm(got - g["amp"]) / np.linalg.norm(g["amp"])
+        assert m <= TOL and rel < 1e-4, (flags, m, rel)
+        nrm = float(sim.expect(W.pauli_sum([(1.0, {})]), psi, 28)[0])
+        assert abs(nrm - 1) < 1e-5
+        z0 = float(sim.expect(W.z_on(0), psi, 28)[0])
+        assert abs(z0 - float(g["z0"])) < 1e-5
+        del psi
+        torch.cuda.empty_cache()
+
+
+def test_c3_full_size_properties(sim):
+    """32 qubits (32 GiB): circuit then inverse returns |0..0>, the norm stays
+    1, and a U3 layer alone matches its product-state closed form."""
+    n = 32
+    gates = W.brickwork_c3()
+    psi, info = run(sim, n, gates, k=12, tile=(5, 8))
+    nrm = float(sim.expect(W.pauli_sum([(1.0, {})]), psi, n)[0])
+    assert abs(nrm - 1) < 1e-4
+    inv = W.inverse_circuit(gates)
+    run(sim, n, inv, k=12, psi=psi)
+    assert abs(complex(psi[0].item()) - 1) < 1e-3
+    assert float(torch.max(torch.abs(psi[1:]))) < 1e-4
+    del psi
+    torch.cuda.empty_cache()
+    layer, ang = W.u3_layer(n, seed=9)
+    psi, _ = run(sim, n, layer, k=10)
+    idx = np.random.default_rng(2).integers(0, 1 << n, size=2048)
+    got = psi[torch.as_tensor(idx, device=psi.device)].cpu().numpy()
+    ref = np.ones(len(idx), complex)
+    for q in range(n):
+        b = (idx >> q) & 1
+        ref *= np.where(b == 0, np.cos(ang[q, 0] / 2), np.exp(1j * ang[q, 1]) * np.sin(ang[q, 0] / 2))
+    assert np.max(np.abs(got - ref)) < 1e-7
+    for q in (0, 13, 31):
+        assert abs(float(sim.expect(W.z_on(q), psi, n)[0]) - np.cos(ang[q, 0])) < 1e-5
+    zz = float(sim.expect(W.zz_chain(n), psi, n)[0])
+    assert abs(zz - sum(np.cos(ang[i, 0]) * np.cos(ang[i + 1, 0]) for i in range(n - 1))) < 1e-4
+    del psi
+    torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------- expectation values
+
+@pytest.mark.parametrize("n,seed", [(1, 1), (3, 2), (8, 3), (15, 4)])
+def test_expect_vs_oracle(sim, n, seed):
+    rng = np.random.default_rng(seed)
+    psi = (rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)) / np.sqrt(2 << n)
+    terms = [(float(rng.normal()), {int(q): "XYZ"[int(rng.integers(3))]
+                                    for q in rng.choice(n, size=int(rng.integers(1, n + 1)), replace=False)})
+             for _ in range(7)] + [(0.3, {})]
+    H = W.pauli_sum(terms)
+    d = torch.as_tensor(psi.astype(np.complex64), device="cuda")
+    ref = oracle.expect(n, H, d.cpu().numpy().astype(np.complex128))
+    got = float(sim.expect(H, d, n)[0])
+    assert abs(got - ref) < 1e-9 * max(1, abs(ref))
+
+
+def test_expect_batched(sim):
+    n, B = 6, 5
+    rng = np.random.default_rng(8)
+    psi = (rng.normal(size=(B, 1 << n)) + 1j * rng.normal(size=(B, 1 << n))).astype(np.complex64)
+    H = W.zz_chain_plus_x(n, 0.5)
+    got = sim.expect(H, torch.as_tensor(psi, device="cuda"), n, batch=B).cpu().numpy()
+    for b in range(B):
+        assert abs(got[b] - oracle.expect(n, H, psi[b].astype(np.complex128))) < 1e-9
+
+
+# ---------------------------------------------------------------- adjoint gradient
+
+@pytest.mark.parametrize("n,ng,seed", [(2, 30, 1), (5, 80, 2), (9, 150, 3), (14, 200, 4), (16, 200, 5)])
+def test_adjoint_vs_oracle(sim, n, ng, seed):
+    npar = 6
+    rng = np.random.default_rng(seed)
+    theta = rng.uniform(-3, 3, size=npar)
+    gates = W.random_circuit(n, ng, seed=3000 + seed, n_params=npar)
+    H = W.zz_chain_plus_x(n, 0.5) if n > 1 else W.z_on(0)
+    e_ref, g_ref = oracle.adjoint(n, gates, theta, H)
+    plan = sim.partition(n, gates, min(n, 9), Q.PLAN_GRAD, (4, 8))
+    try:
+        psi = sim.zero_state(n)
+        ckpt = sim.checkpoints(plan)
+        sim.apply(plan, psi, theta, ckpt)
+        e, g = sim.adjoint_grad(plan, H, theta, psi, ckpt)
+        torch.cuda.synchronize()
+    finally:
+        plan.close()
+    assert abs(float(e[0]) - e_ref) < 1e-4
+    g = g.cpu().numpy()  # the plan counts parameters up to the highest index used
+    assert np.max(np.abs(g - g_ref[:len(g)])) < 1e-4
+    assert np.all(g_ref[len(g):] == 0)
+
+
+def test_c4_gradient_vs_oracle_and_fd(sim):
+    """20-qubit RY.RZ + CX-ladder ansatz, 10 layers, 400 parameters:
+    adjoint gradient vs the oracle's adjoint gradient (all parameters) and vs
+    central finite differences (h = 1e-3) of the complex128 oracle energy."""
+    n = 20
+    gates, npar = W.ansatz(n, 10)
+    theta = W.ansatz_params(npar, seed=4)
+    H = W.zz_chain_plus_x(n, 0.5)
+    e_ref, g_ref = oracle.adjoint(n, gates, theta, H)
+    plan = sim.partition(n, gates, 10, Q.PLAN_GRAD)
+    try:
+        th_req = torch.as_tensor(theta, device="cuda").clone().requires_grad_(True)
+        e = Q.Energy.apply(th_req, sim, plan, H)
+        e.backward()
+        g = th_req.grad.cpu().numpy()
+    finally:
+        plan.close()
+    assert abs(float(e) - e_ref) < 1e-4
+    assert np.max(np.abs(g - g_ref)) < 1e-4
+    h = 1e-3
+    for j in (0, 1, 57, 200, 399):
+        tp, tm = theta.copy(), theta.copy()
+        tp[j] += h
+        tm[j] -= h
+        fd = (oracle.expect(n, H, oracle.apply(n, gates, tp)) - oracle.expect(n, H, oracle.apply(n, gates, tm))) / (2 * h)
+        assert abs(g[j] - fd) < 1e-4

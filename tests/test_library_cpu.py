@@ -1,0 +1,153 @@
+"""Host-side checks of the native library (no GPU needed): it loads, exports
+every entry point the header declares, its partitioner (integer work) matches
+the oracle's greedy partition exactly, its register stages satisfy the
+partition invariants, and invalid input is rejected before any device work."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2509_14098_amd as Q
+import workloads as W
+from oracle import centrality as C
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = Q.load_library()
+    header = open(os.path.join(ROOT, "include", "qsv.h")).read()
+    names = set(re.findall(r"^\s*(?:qsv_status|const char \*)\s*(qsv_\w+)\s*\(", header, re.M))
+    assert {"qsv_create", "qsv_partition", "qsv_apply", "qsv_expect", "qsv_adjoint_grad"} <= names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(Q.binding.EXPORTS) == names
+
+
+def _plan_parts(plan, level=0):
+    info = Q.qsv_plan_info(plan)
+    count = info["n_partitions"] if level == 0 else info["n_stages"]
+    return [Q.qsv_plan_partition(plan, 0, level, p) for p in range(count)]
+
+
+def _compare(n, gates, k, theta=None, tile=None):
+    plan = Q.qsv_partition(None, n, gates, None, k, 0, tile)
+    try:
+        mine = [(S, g) for S, g in _plan_parts(plan)]
+        ref = C.greedy_partition(n, gates, k, theta)
+        assert mine == [(list(S), list(g)) for S, g in ref]
+        return plan
+    except Exception:
+        Q.qsv_plan_destroy(plan)
+        raise
+
+
+def test_worked_example_ghz3():
+    plan = _compare(3, W.ghz(3), 2)
+    Q.qsv_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("name,n,k", [("c1", 12, 6), ("c1", 12, 8), ("c2", 28, 10), ("c3", 32, 8), ("c3", 32, 10),
+                                      ("c3", 32, 12), ("c4", 20, 10)])
+def test_partition_matches_oracle_on_workloads(name, n, k):
+    gates = {"c1": W.brickwork_c1, "c2": W.brickwork_c2, "c3": W.brickwork_c3,
+             "c4": lambda: W.ansatz(20, 10)[0]}[name]()
+    tile = (5, 8) if k < 13 else (5, 9)
+    plan = _compare(n, gates, k, tile=tile)
+    info = Q.qsv_plan_info(plan)
+    assert info["n_gates"] == len(gates)
+    Q.qsv_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_partition_matches_oracle_random(seed):
+    rng = np.random.default_rng(500 + seed)
+    n = int(rng.integers(2, 16))
+    k = int(rng.integers(2, n + 1))
+    if n > 13:  # a partition must leave room for at least one fill qubit in a 13-qubit tile
+        k = min(k, 12)
+    theta = rng.uniform(-3, 3, size=4)
+    gates = W.random_circuit(n, int(rng.integers(1, 150)), seed=500 + seed, n_params=4)
+    plan = _compare(n, gates, k, theta)
+    Q.qsv_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_register_stages_are_valid_partitions(seed):
+    """Level 2 (registers): every gate of a partition exactly once, in an
+    order that respects the contraction graph, with its required qubits among
+    the R register qubits of the stage."""
+    rng = np.random.default_rng(900 + seed)
+    n = int(rng.integers(6, 22))
+    gates = W.random_circuit(n, 200, seed=900 + seed, n_params=3)
+    theta = rng.uniform(-3, 3, size=3)
+    plan = Q.qsv_partition(None, n, gates, None, min(n, 9), 0, (4, 8))
+    info = Q.qsv_plan_info(plan)
+    parts = _plan_parts(plan, 0)
+    stages = _plan_parts(plan, 1)
+    R = info["reg_qubits"]
+    order = [g for _, st in stages for g in st]
+    # the stages of partition p cover exactly p's gates, before those of p+1
+    pos = 0
+    for _, p in parts:
+        assert sorted(order[pos:pos + len(p)]) == sorted(p)
+        pos += len(p)
+    assert pos == len(order)
+    C.check_partition(n, gates, n, [(list(range(n)), order)], theta)
+    for S, st in stages:
+        assert len(S) == R
+        for g in st:
+            assert set(C.required_local(gates[g], theta)) <= set(S)
+    Q.qsv_plan_destroy(plan)
+
+
+def test_gate_by_gate_plan():
+    gates = W.brickwork_c1()
+    plan = Q.qsv_partition(None, 12, gates, None, 8, Q.PLAN_GATE_BY_GATE)
+    parts = _plan_parts(plan)
+    assert [g for _, g in parts] == [[i] for i in range(len(gates))]
+    assert all(len(S) == 8 for S, _ in parts)
+    Q.qsv_plan_destroy(plan)
+
+
+def test_plan_params_offsets():
+    a, na = W.ansatz(5, 2)
+    b, nb = W.ansatz(5, 3)
+    gates = np.concatenate([a, b])
+    plan = Q.qsv_partition(None, 5, gates, [0, len(a), len(a) + len(b)], 0, 0)
+    assert Q.qsv_plan_params(plan, 0) == (0, na)
+    assert Q.qsv_plan_params(plan, 1) == (na, nb)
+    assert Q.qsv_plan_info(plan)["n_params"] == na + nb
+    Q.qsv_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("case,code", [
+    ("bad_qubit", -1), ("same_qubit", -1), ("param_on_h", -2), ("n0", -1), ("kneg", -1), ("kind", -1),
+    ("batched_big", -1), ("k_too_big", -1), ("bad_offsets", -1),
+])
+def test_invalid_input_rejected(case, code):
+    g = W.ghz(4)
+    n, k, off = 4, 2, None
+    if case == "bad_qubit":
+        g["q1"][1] = 7
+    elif case == "same_qubit":
+        g["q1"][1] = g["q0"][1]
+    elif case == "param_on_h":
+        g["param"][0] = 0
+    elif case == "n0":
+        n = 0
+    elif case == "kneg":
+        k = -1
+    elif case == "kind":
+        g["kind"][2] = 99
+    elif case == "batched_big":
+        g = np.concatenate([W.ghz(15), W.ghz(15)])
+        n, off = 15, [0, 15, 30]
+    elif case == "k_too_big":
+        g, n, k = W.ghz(20), 20, 13
+    elif case == "bad_offsets":
+        off = [0, 3, 2]
+    with pytest.raises(Q.QsvError) as e:
+        Q.qsv_partition(None, n, g, off, k, 0, (5, 8))
+    assert e.value.code == code
