@@ -1,0 +1,221 @@
+"""Benchmark of the partitioned state-vector hot path on one MI355X.
+
+Headline (the `value`): the 28-qubit random brickwork circuit (40 layers of U3
+on every qubit + alternating CZ/CX nearest-neighbour pairs + 5% random
+long-range CX, seed 2, complex64, 2 GiB state), partitioned with k = 10 local
+qubits.  One step = the whole fused circuit applied to the state resident in
+HBM (every partition sweep) plus <Z_0> reduced in float64.  value = algorithmic
+HBM bytes of the step (16 B per amplitude per sweep + 8 B per amplitude for the
+expectation) / step time, in GB/s.
+
+Side measurements (separate timed regions, not in `value`):
+  * the same circuit gate by gate (one sweep per gate) -> fused speed-up;
+  * the 20-qubit RY.RZ + CX-ladder ansatz (400 parameters): adjoint gradient
+    time / forward time;
+  * the oracle (plain complex128 CPU simulator) on a bounded prefix of the
+    headline circuit -> cpu_baseline.
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+import paper_2509_14098_amd as Q
+import workloads as W
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
+FP32_VECTOR_PEAK = 157.3     # TFLOP/s (packed FP32 VALU; unpacked issue gives half)
+
+
+def sync():
+    torch.cuda.synchronize()
+
+
+def fused_step(sim, plan, psi, Hz0, out):
+    sim.apply(plan, psi)
+    Q.qsv_expect(sim.ctx, Hz0, plan.n, 1, psi, out)
+
+
+def bench_headline(sim, args):
+    n, k = 28, args.k
+    gates = W.brickwork_c2()
+    tile = tuple(args.tile) if args.tile else None
+    plan = sim.partition(n, gates, k, 0, tile)
+    info = plan.info
+    psi = sim.zero_state(n)
+    Hz0 = W.z_on(0)
+    out = torch.empty(1, dtype=torch.float64, device=sim.device)
+    for _ in range(args.warmup):
+        fused_step(sim, plan, psi, Hz0, out)
+    sync()
+    Q.qsv_set_timing(sim.ctx, True)
+    kernel_ms, launches = 0.0, 0
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fused_step(sim, plan, psi, Hz0, out)
+        ms, nl = Q.qsv_last_sweep_ms(sim.ctx)  # waits for this step's last sweep event
+        kernel_ms += ms
+        launches += nl
+    sync()
+    wall = time.perf_counter() - t0
+    Q.qsv_set_timing(sim.ctx, False)
+    step_ms = wall * 1e3 / args.steps
+    dim = 1 << n
+    step_bytes = info["bytes_per_apply"] + 8.0 * dim
+    res = dict(plan=info, step_ms=step_ms, step_bytes=step_bytes, kernel_ms_total=kernel_ms, launches=launches,
+               z0=float(out[0]))
+    plan.close()
+    # gate by gate: same kernels, one gate per partition
+    if not args.skip_gbg:
+        plan_g = sim.partition(n, gates, k, Q.PLAN_GATE_BY_GATE, tile)
+        sim.apply(plan_g, psi)
+        sync()
+        t0 = time.perf_counter()
+        sim.apply(plan_g, psi)
+        sync()
+        res["gbg_ms"] = (time.perf_counter() - t0) * 1e3
+        res["gbg_sweeps"] = plan_g.info["n_partitions"]
+        plan_g.close()
+    del psi
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_gradient(sim, args):
+    n = 20
+    gates, npar = W.ansatz(n, 10)
+    theta = torch.as_tensor(W.ansatz_params(npar, seed=4), device=sim.device)
+    H = W.zz_chain_plus_x(n, 0.5)
+    plan = sim.partition(n, gates, 10, Q.PLAN_GRAD)
+    psi = sim.zero_state(n)
+    ckpt = sim.checkpoints(plan)
+    out = torch.empty(1, dtype=torch.float64, device=sim.device)
+    energy = torch.empty(1, dtype=torch.float64, device=sim.device)
+    grad = torch.empty(npar, dtype=torch.float64, device=sim.device)
+
+    def forward():
+        psi.zero_()
+        psi[0] = 1.0
+        sim.apply(plan, psi, theta, ckpt)
+        Q.qsv_expect(sim.ctx, H, n, 1, psi, out)
+
+    def backward():
+        Q.qsv_adjoint_grad(sim.ctx, plan.handle, H, theta, psi, ckpt, energy, grad)
+
+    for _ in range(3):
+        forward()
+        backward()
+    sync()
+    reps = 20
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        forward()
+    sync()
+    t_fwd = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        backward()
+    sync()
+    t_bwd = (time.perf_counter() - t0) / reps
+    res = dict(fwd_ms=t_fwd * 1e3, grad_ms=t_bwd * 1e3, ratio=t_bwd / t_fwd, energy=float(energy[0]),
+               partitions=plan.info["n_partitions"])
+    plan.close()
+    return res
+
+
+def bench_oracle(args, gpu_bytes_per_apply, n_gates_total):
+    """The oracle on a bounded prefix of the headline circuit (~10-30 s)."""
+    import oracle
+    n = 28
+    gates = W.brickwork_c2()
+    psi = oracle.zero_state(n)
+    done, t_total = 0, 0.0
+    chunk = 4
+    while done < len(gates) and t_total < args.cpu_seconds:
+        t0 = time.perf_counter()
+        oracle.apply_range(n, gates, done, min(done + chunk, len(gates)), psi)
+        t_total += time.perf_counter() - t0
+        done = min(done + chunk, len(gates))
+    frac = done / n_gates_total
+    return dict(value=gpu_bytes_per_apply * frac / t_total / 1e9, unit="GB/s", cores=oracle.threads(), kind="oracle",
+                sample=f"first {done} of {n_gates_total} gates of the 28-qubit headline circuit, complex128 gate by "
+                       f"gate, {t_total:.1f} s; rate expressed as the fused circuit's algorithmic bytes x fraction "
+                       f"of gates done / time")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--k", type=int, default=10)
+    ap.add_argument("--tile", type=int, nargs=2, default=None, help="reg_qubits log_threads")
+    ap.add_argument("--skip-gbg", action="store_true")
+    ap.add_argument("--skip-grad", action="store_true")
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU path is not part of this "
+              f"build", file=sys.stderr)
+        sys.exit(2)
+    sim = Q.Simulator(0)
+    head = bench_headline(sim, args)
+    info = head["plan"]
+    value = head["step_bytes"] / (head["step_ms"] * 1e-3) / 1e9
+    avg_launch_ms = head["kernel_ms_total"] / max(1, head["launches"])
+    sweep_bytes = 16.0 * (1 << 28)
+    sweep_flops = info["flops_per_apply"] / info["n_partitions"]
+    intensity = info["flops_per_apply"] / info["bytes_per_apply"]
+    ridge = FP32_VECTOR_PEAK * 1e12 / (HBM_PEAK_GBS * 1e9)
+    achieved_gbs = sweep_bytes / (avg_launch_ms * 1e-3) / 1e9
+    achieved_tf = sweep_flops / (avg_launch_ms * 1e-3) / 1e12
+    if intensity > ridge:
+        roof = dict(bound="alu", achieved=round(achieved_tf, 3), peak=FP32_VECTOR_PEAK, unit="TFLOP/s",
+                    frac=round(achieved_tf / FP32_VECTOR_PEAK, 4), traffic=None)
+    else:
+        roof = dict(bound="hbm", achieved=round(achieved_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved_gbs / HBM_PEAK_GBS, 4), traffic=None)
+    line = dict(
+        metric="state-vector sweep GB/s (% HBM peak); adjoint grad time / forward; fused vs gate-by-gate",
+        value=round(value, 2), unit="GB/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=round(head["step_ms"], 4), higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="c64/f32 (f64 reductions)", data="synthetic",
+        config=dict(workload="28-qubit random brickwork, 40 layers, U3 + CZ/CX pairs + 5% long-range CX, seed 2, "
+                             "complex64 2 GiB, k=10 fused sweeps + <Z0>",
+                    n_qubits=28, n_gates=info["n_gates"], k_local=info["k_local"], tile_qubits=info["tile_qubits"],
+                    reg_qubits=info["reg_qubits"], log_threads=info["log_threads"],
+                    partitions=info["n_partitions"], register_stages=info["n_stages"],
+                    plan_seconds=round(info["plan_seconds"], 4)),
+        hbm_frac=round(value / HBM_PEAK_GBS, 4),
+        roofline=roof,
+        roofline_hbm=dict(achieved=round(achieved_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                          frac=round(achieved_gbs / HBM_PEAK_GBS, 4)),
+        sweep=dict(avg_launch_ms=round(avg_launch_ms, 4), bytes_per_launch=sweep_bytes,
+                   flops_per_launch=sweep_flops, flops_per_byte=round(intensity, 2), ridge_flops_per_byte=round(ridge, 2),
+                   tflops=round(achieved_tf, 3)),
+    )
+    if "gbg_ms" in head:
+        line["gate_by_gate"] = dict(ms=round(head["gbg_ms"], 2), sweeps=head["gbg_sweeps"],
+                                    gbs=round(16.0 * (1 << 28) * head["gbg_sweeps"] / (head["gbg_ms"] * 1e-3) / 1e9, 1),
+                                    fused_speedup=round(head["gbg_ms"] / (head["kernel_ms_total"] / args.steps), 2))
+    if not args.skip_grad:
+        line["adjoint"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in bench_gradient(sim, args).items()}
+    if not args.skip_cpu:
+        line["cpu_baseline"] = bench_oracle(args, info["bytes_per_apply"], info["n_gates"])
+    else:
+        line["cpu_baseline"] = None
+    sim.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

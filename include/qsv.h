@@ -149,6 +149,7 @@ qsv_status qsv_set_stream(qsv_ctx *ctx, void *hip_stream);
  * device (autotuner, needs ctx).  tile may be NULL (default shape).
  * The gate array is copied; it is not retained.  The plan is freed by
  * qsv_plan_destroy.
+ * Batched plans (n_circuits > 1) keep each whole state on chip: 4 <= n <= 14.
  * Errors: QSV_E_ARG (n_qubits < 1 or > 34, k_local < 0, qubit out of range,
  * q0 == q1, unknown kind, bad offsets, a batched plan with n_qubits > 14),
  * QSV_E_RANGE (param >= 0 on a non-rotation), QSV_E_NOMEM, QSV_E_DEVICE.
@@ -173,6 +174,8 @@ qsv_status qsv_plan_partition(const qsv_plan *plan, int32_t circuit, int32_t lev
 /*
  * Apply the planned circuits in place: psi_b <- C_b(theta_b) psi_b on
  * complex64[n_circuits][2^n] (the caller initialises psi, e.g. to |0..0>).
+ * Batched plans (n_circuits > 1) always start from |0..0> and write the final
+ * states into psi (one persistent launch).
  * theta_dev: float64 device array of qsv_plan_info.n_params entries (may be
  * NULL when the plan has none); rotation matrices are formed on the device
  * (cos/sin in float64, rounded to float32).  When ckpt_dev is non-NULL
@@ -200,13 +203,21 @@ qsv_status qsv_expect(qsv_ctx *ctx, const qsv_pauli_term *H, int32_t n_terms, in
  * Single-circuit plans: psi_final_dev is the state qsv_apply produced and
  * ckpt_dev the checkpoints it wrote; the plan must carry QSV_PLAN_GRAD.
  * Batched plans (n_circuits > 1): forward, energy and adjoint run in one
- * persistent launch from |0..0>; psi_final_dev and ckpt_dev are ignored and
- * may be NULL.  grad_dev: float64[n_params], energy_dev: float64[n_circuits].
+ * persistent launch from |0..0> (longest circuits first); ckpt_dev is
+ * ignored, psi_final_dev may be NULL or receive the final states
+ * (complex64[n_circuits][2^n]).  grad_dev: float64[n_params], energy_dev:
+ * float64[n_circuits].
  * Errors: QSV_E_STATE (no QSV_PLAN_GRAD or missing checkpoints), QSV_E_ARG.
  */
 qsv_status qsv_adjoint_grad(qsv_ctx *ctx, const qsv_plan *plan, const qsv_pauli_term *H, int32_t n_terms,
                             const double *theta_dev, const void *psi_final_dev, const void *ckpt_dev,
                             double *energy_dev, double *grad_dev);
+
+/* Candidates timed by the last autotuning run in this process (k_local == 0
+ * on a context): writes up to cap records of 4 int32 (k, reg_qubits,
+ * log_threads, microseconds for the whole circuit) and returns the number of
+ * candidates. */
+int32_t qsv_last_autotune(int32_t *out, int32_t cap);
 
 /* Time-stamped launch counters of the last call on ctx (for benchmarks):
  * average duration in ms of the sweep kernels of the last qsv_apply, measured

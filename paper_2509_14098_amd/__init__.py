@@ -11,6 +11,6 @@ from .binding import (  # noqa: F401
     QsvError, GATE_DTYPE, PAULI_DTYPE, KIND, PLAN_GATE_BY_GATE, PLAN_GRAD,
     qsv_create, qsv_destroy, qsv_set_stream, qsv_partition, qsv_plan_destroy, qsv_plan_info,
     qsv_plan_params, qsv_plan_partition, qsv_apply, qsv_expect, qsv_adjoint_grad,
-    qsv_set_timing, qsv_last_sweep_ms, library_path, load_library,
+    qsv_set_timing, qsv_last_sweep_ms, qsv_last_autotune, library_path, load_library,
 )
 from .sim import Simulator, Plan, Energy  # noqa: F401

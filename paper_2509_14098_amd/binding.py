@@ -48,7 +48,7 @@ class _PlanInfo(ctypes.Structure):
 _lib = None
 EXPORTS = ["qsv_last_error", "qsv_create", "qsv_destroy", "qsv_set_stream", "qsv_partition", "qsv_plan_destroy",
            "qsv_plan_get_info", "qsv_plan_params", "qsv_plan_partition", "qsv_apply", "qsv_expect",
-           "qsv_adjoint_grad", "qsv_set_timing", "qsv_last_sweep_ms"]
+           "qsv_adjoint_grad", "qsv_set_timing", "qsv_last_sweep_ms", "qsv_last_autotune"]
 
 
 def library_path() -> str:
@@ -72,7 +72,7 @@ def load_library():
         "qsv_plan_partition": [V, I32, I32, I64, V, V, I64, V],
         "qsv_apply": [V, V, V, V, V], "qsv_expect": [V, V, I32, I32, I64, V, V],
         "qsv_adjoint_grad": [V, V, V, I32, V, V, V, V, V],
-        "qsv_set_timing": [V, I32], "qsv_last_sweep_ms": [V, V, V],
+        "qsv_set_timing": [V, I32], "qsv_last_sweep_ms": [V, V, V], "qsv_last_autotune": [V, I32],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -141,6 +141,14 @@ def qsv_partition(ctx, n_qubits: int, gates, circ_offsets=None, k_local: int = 0
                                          off.ctypes.data_as(ctypes.c_void_p), len(off) - 1, k_local, flags,
                                          ctypes.byref(tc), ctypes.byref(h)))
     return h
+
+
+def qsv_last_autotune():
+    """[(k, reg_qubits, log_threads, ms)] of the last autotuning run in this process."""
+    n = load_library().qsv_last_autotune(None, 0)
+    buf = np.zeros(4 * max(n, 1), dtype=np.int32)
+    load_library().qsv_last_autotune(buf.ctypes.data_as(ctypes.c_void_p), n)
+    return [(int(buf[4 * i]), int(buf[4 * i + 1]), int(buf[4 * i + 2]), buf[4 * i + 3] / 1000.0) for i in range(n)]
 
 
 def qsv_plan_destroy(plan):

@@ -15,53 +15,6 @@
 
 namespace qsv {
 
-__device__ __forceinline__ double im_conj_mul(float2 l, float2 a) { return (double)l.x * a.y - (double)l.y * a.x; }
-__device__ __forceinline__ double re_conj_mul(float2 l, float2 a) { return (double)l.x * a.x + (double)l.y * a.y; }
-
-template <int R, int J>
-__device__ __forceinline__ double grad_pairs(const float2 (&a)[1 << R], const float2 (&l)[1 << R], bool y_gen)
-{
-    double acc = 0.0;
-#pragma unroll
-    for (int i = 0; i < (1 << R); ++i) {
-        if (i & (1 << J)) continue;
-        const float2 a0 = a[i], a1 = a[i | (1 << J)], l0 = l[i], l1 = l[i | (1 << J)];
-        if (y_gen)  // Y: (Y psi)_0 = -i psi_1, (Y psi)_1 = i psi_0
-            acc += re_conj_mul(l1, a0) - re_conj_mul(l0, a1);
-        else        // X: (X psi)_0 = psi_1, (X psi)_1 = psi_0
-            acc += im_conj_mul(l0, a1) + im_conj_mul(l1, a0);
-    }
-    return acc;
-}
-
-// Im <lambda|P|psi> over this thread's amplitudes for the op's generator.
-template <int R>
-__device__ __forceinline__ double grad_term(const float2 (&a)[1 << R], const float2 (&l)[1 << R], const DevOp &o,
-                                            uint32_t tid, uint64_t base)
-{
-    double acc = 0.0;
-    if (o.gen == GEN_Z || o.gen == GEN_ZZ) {
-        uint32_t p = loc_pattern(o.a, tid, base);
-        if (o.gen == GEN_ZZ) p ^= loc_pattern(o.b, tid, base);
-#pragma unroll
-        for (int i = 0; i < (1 << R); ++i) {
-            const double v = im_conj_mul(l[i], a[i]);
-            acc += ((p >> i) & 1u) ? -v : v;
-        }
-    } else {
-        const bool y = o.gen == GEN_Y;
-        on_reg<R>(o.a & 0x3F, [&](auto J) __attribute__((always_inline)) { acc = grad_pairs<R, std::decay_t<decltype(J)>::value>(a, l, y); });
-    }
-    return acc;
-}
-
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
-    return v;
-}
-
 template <int LW>
 __device__ __forceinline__ void load_pairs(const float2 *__restrict__ src, float2 *lds, const DevPart *__restrict__ P,
                                            uint64_t base, uint32_t tid)

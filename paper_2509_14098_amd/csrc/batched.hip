@@ -1,0 +1,238 @@
+// Batched persistent kernel: many small circuits (n <= 14) with uneven depths,
+// each run entirely on chip by one workgroup.
+//
+// The grid holds one workgroup per compute unit.  A workgroup takes the next
+// circuit from a device queue (circuits ordered by decreasing work, so the
+// longest start first) until the queue is empty; every workgroup reaches that
+// exit.  Per circuit:
+//   forward  — |0..0> in LDS, the register stages of the circuit (one
+//              partition covers the whole state), final state optionally
+//              written out;
+//   energy   — lambda = H psi in the last stage's register layout, reading the
+//              partner amplitudes of each Pauli group from LDS; <H> reduced in
+//              float64 in a fixed order;
+//   adjoint  — stages walked backwards with psi and lambda both in registers,
+//              remapped between stage layouts through LDS; for every
+//              parameterised rotation Im <lambda|P|psi> is summed per wave
+//              (float64) before U^dagger is applied to both states; the
+//              circuit's gradient entries are then reduced in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include "gates.cuh"
+#include "kernels.h"
+
+namespace qsv {
+
+struct BatchArgs {
+    const DevPart *parts;
+    const DevStage *stages;
+    const DevOp *ops;
+    const float *pool;
+    const int32_t *order;       // queue position -> circuit
+    const int32_t *circ_part;   // circuit -> its DevPart
+    const int64_t *circ_theta;  // circuit -> first theta index
+    const int64_t *circ_npar;   // circuit -> number of parameters
+    const int32_t *param_off;   // theta index -> grad slots (CSR)
+    const int32_t *param_slots;
+    const DevGroup *groups;
+    const DevTerm *terms;
+    int n_groups;
+    int n_circuits;
+    int n;
+    float2 *psi_out;            // may be null
+    double *energy;             // [n_circuits] (adjoint only)
+    double *grad;               // [n_params]   (adjoint only)
+    double *gpart;              // [n_slots][waves] scratch
+    int *queue;
+    int adjoint;
+};
+
+template <int R>
+__device__ __forceinline__ void stage_offsets(const DevStage *__restrict__ S, int w, uint32_t tid, uint32_t &toff,
+                                              uint32_t (&roff)[1 << R])
+{
+    toff = 0;
+    for (int b = 0; b < w; ++b) toff |= ((tid >> b) & 1u) << S->thrpos[b];
+    roff[0] = 0;
+#pragma unroll
+    for (int i = 1; i < (1 << R); ++i) roff[i] = roff[i & (i - 1)] | (1u << S->regpos[__builtin_ctz(i)]);
+}
+
+// Registers in the layout (toff, roff) -> LDS -> registers in the layout (toff2, roff2).
+template <int R>
+__device__ __forceinline__ void remap(float2 (&v)[1 << R], float2 *lds, bool active, uint32_t toff,
+                                      const uint32_t (&roff)[1 << R], uint32_t toff2, const uint32_t (&roff2)[1 << R])
+{
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < (1 << R); ++i) lds[swz(toff | roff[i])] = v[i];
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < (1 << R); ++i) v[i] = lds[swz(toff2 | roff2[i])];
+    }
+}
+
+template <int R, int LW>
+__global__ __launch_bounds__(1 << LW) void batched_kernel(BatchArgs A)
+{
+    constexpr int NA = 1 << R, WAVES = (1 << LW) / 64;
+    extern __shared__ float2 lds[];
+    __shared__ int s_item;
+    __shared__ double s_red[WAVES];
+    const uint32_t tid = threadIdx.x;
+    const int wave = tid >> 6;
+    while (true) {
+        if (tid == 0) s_item = atomicAdd(A.queue, 1);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= A.n_circuits) break;
+        const int c = A.order[item];
+        const DevPart *__restrict__ P = A.parts + A.circ_part[c];
+        const int t = P->t, w = t - R;
+        const bool active = tid < (1u << w);
+        const uint32_t dim = 1u << t;
+        // forward from |0..0>
+        for (uint32_t x = tid; x < dim; x += (1u << LW)) lds[swz(x)] = float2{x == 0 ? 1.f : 0.f, 0.f};
+        __syncthreads();
+        run_stages<R, false>(lds, A.stages, A.ops, A.pool, P->stage_begin, P->stage_end, w, tid, 0);
+        if (A.psi_out) {  // the tile is the whole state and its positions are the qubits in order
+            float2 *dst = A.psi_out + (uint64_t)c * dim;
+            for (uint32_t x = tid; x < dim; x += (1u << LW)) dst[x] = lds[swz(x)];
+        }
+        if (!A.adjoint) {
+            __syncthreads();
+            continue;
+        }
+        // lambda = H psi and the energy, in the last stage's layout
+        const int s_last = P->stage_end - 1;
+        uint32_t toff, roff[NA];
+        stage_offsets<R>(A.stages + s_last, w, tid, toff, roff);
+        float2 a[NA], l[NA];
+        double e_part = 0.0;
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            a[i] = float2{0.f, 0.f};
+            l[i] = float2{0.f, 0.f};
+            if (active) {
+                const uint32_t x = toff | roff[i];
+                a[i] = lds[swz(x)];
+                double lr = 0.0, li = 0.0;
+                for (int g = 0; g < A.n_groups; ++g) {
+                    const DevGroup G = A.groups[g];
+                    const uint32_t y = x ^ (uint32_t)G.x_mask;
+                    const float2 py = lds[swz(y)];
+                    double wr = 0.0, wi = 0.0;
+                    for (int k = G.term_begin; k < G.term_end; ++k) {
+                        const double sg = (__popcll(y & A.terms[k].z_mask) & 1) ? -1.0 : 1.0;
+                        wr += sg * A.terms[k].cre;
+                        wi += sg * A.terms[k].cim;
+                    }
+                    lr += wr * py.x - wi * py.y;
+                    li += wr * py.y + wi * py.x;
+                }
+                l[i] = float2{(float)lr, (float)li};
+                e_part += (double)a[i].x * lr + (double)a[i].y * li;
+            }
+        }
+        e_part = wave_sum(e_part);
+        if ((tid & 63) == 0) s_red[wave] = e_part;
+        __syncthreads();
+        if (tid == 0) {
+            double e = 0.0;
+            for (int v = 0; v < WAVES; ++v) e += s_red[v];
+            A.energy[c] = e;
+        }
+        // reverse walk over the stages
+        for (int s = s_last; s >= P->stage_begin; --s) {
+            if (s != s_last) {  // remap psi, then lambda, from the layout of stage s+1 to that of stage s
+                uint32_t toff2, roff2[NA];
+                stage_offsets<R>(A.stages + s, w, tid, toff2, roff2);
+                remap<R>(a, lds, active, toff, roff, toff2, roff2);
+                remap<R>(l, lds, active, toff, roff, toff2, roff2);
+                toff = toff2;
+#pragma unroll
+                for (int i = 0; i < NA; ++i) roff[i] = roff2[i];
+            }
+            const DevStage *__restrict__ S = A.stages + s;
+            for (int k = S->op_end - 1; k >= S->op_begin; --k) {
+                const DevOp o = A.ops[k];
+                if (o.grad_slot >= 0) {
+                    const double v = wave_sum(grad_term<R>(a, l, o, tid, 0));
+                    if ((tid & 63) == 0) A.gpart[(int64_t)o.grad_slot * WAVES + wave] = v;
+                }
+                apply_op<R, true>(a, o, A.pool, tid, 0);
+                apply_op<R, true>(l, o, A.pool, tid, 0);
+            }
+        }
+        // this circuit's gradient entries: slots in slot order, waves in order
+        __threadfence_block();
+        __syncthreads();
+        const int64_t p0 = A.circ_theta[c], np = A.circ_npar[c];
+        for (int64_t p = tid; p < np; p += (1 << LW)) {
+            double acc = 0.0;
+            for (int32_t k = A.param_off[p0 + p]; k < A.param_off[p0 + p + 1]; ++k)
+                for (int v = 0; v < WAVES; ++v) acc += A.gpart[(int64_t)A.param_slots[k] * WAVES + v];
+            A.grad[p0 + p] = acc;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void reset_counter_kernel(int *q)
+{
+    if (threadIdx.x == 0) *q = 0;
+}
+
+constexpr int BATCH_R = 4, BATCH_LW = 10;
+
+hipError_t launch_batched(const Plan &plan, const DevGroup *groups, int n_groups, const DevTerm *terms,
+                          const double *theta, float2 *psi_out, double *energy, double *grad, double *gpart,
+                          int *queue, bool adjoint, int grid, hipStream_t s)
+{
+    if (plan.R != BATCH_R || plan.LW != BATCH_LW) return hipErrorInvalidValue;
+    hipError_t e = launch_materialize(plan, theta, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, queue);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    BatchArgs A;
+    A.parts = plan.d_parts;
+    A.stages = plan.d_stages;
+    A.ops = plan.d_ops;
+    A.pool = plan.d_pool;
+    A.order = plan.d_batch_order;
+    A.circ_part = plan.d_circ_part;
+    A.circ_theta = plan.d_circ_theta;
+    A.circ_npar = plan.d_circ_npar;
+    A.param_off = plan.d_param_off;
+    A.param_slots = plan.d_param_slots;
+    A.groups = groups;
+    A.terms = terms;
+    A.n_groups = n_groups;
+    A.n_circuits = plan.n_circuits;
+    A.n = plan.n;
+    A.psi_out = psi_out;
+    A.energy = energy;
+    A.grad = grad;
+    A.gpart = gpart;
+    A.queue = queue;
+    A.adjoint = adjoint ? 1 : 0;
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void *)batched_kernel<BATCH_R, BATCH_LW>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        (void)hipGetLastError();
+        attr = true;
+    }
+    const size_t lds = (size_t)8 << plan.t;
+    hipLaunchKernelGGL((batched_kernel<BATCH_R, BATCH_LW>), dim3(grid), dim3(1 << BATCH_LW), lds, s, A);
+    return hipGetLastError();
+}
+
+int batched_waves() { return (1 << BATCH_LW) / 64; }
+
+}  // namespace qsv

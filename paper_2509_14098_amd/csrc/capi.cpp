@@ -108,6 +108,18 @@ struct qsv_ctx {
     size_t pinned_bytes = 0;
     hipEvent_t pinned_ready = nullptr;
     int *queue = nullptr;
+    int n_cu = 0;
+
+    int *ensure_queue()
+    {
+        if (!queue && hipMalloc((void **)&queue, 256) != hipSuccess) fail(QSV_E_NOMEM, "queue allocation failed");
+        return queue;
+    }
+    int grid_batched(int n_items)
+    {
+        if (n_cu == 0) hip_check(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device), "attr");
+        return std::max(1, std::min(n_cu, n_items));
+    }
 
     void *ensure(void *&p, size_t &have, size_t need)
     {
@@ -256,6 +268,127 @@ qsv_status qsv_last_sweep_ms(qsv_ctx *ctx, double *total_ms, int64_t *n_launches
     });
 }
 
+// Build (and, with a context, upload) a plan for validated input.
+static qsv_plan *make_plan(qsv_ctx *ctx, int n_qubits, const qsv_gate *gates, const std::vector<int64_t> &off,
+                           uint32_t flags, int k, int R, int LW)
+{
+    const int n_circuits = (int)off.size() - 1;
+    auto P = new qsv_plan();
+    std::unique_ptr<qsv_plan, void (*)(qsv_plan *)> guard(P, [](qsv_plan *p) { qsv_plan_destroy(p); });
+    P->n = n_qubits;
+    P->n_circuits = n_circuits;
+    P->flags = flags;
+    if (n_circuits > 1) {
+        P->R = R;
+        P->LW = LW;
+        P->t = n_qubits;
+    } else {
+        choose_shape(n_qubits, R, LW, P->R, P->LW, P->t);
+    }
+    P->k = std::min(k, n_qubits);
+    P->gates.assign(gates, gates + off[n_circuits]);
+    int64_t theta_off = 0;
+    for (int c = 0; c < n_circuits; ++c) {
+        CircuitPlan C;
+        C.g0 = off[c];
+        C.g1 = off[c + 1];
+        int64_t np = 0;
+        for (int64_t g = C.g0; g < C.g1; ++g) np = std::max<int64_t>(np, (int64_t)P->gates[g].param + 1);
+        C.theta_off = theta_off;
+        C.n_params = np;
+        theta_off += np;
+        P->circ.push_back(C);
+    }
+    P->n_params = theta_off;
+    build_plan(*P);
+    if (ctx) {
+        hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+        P->device = ctx->device;
+        P->d_ops = dev_upload(P->ops);
+        P->d_stages = dev_upload(P->stages);
+        P->d_parts = dev_upload(P->parts);
+        std::vector<float> pool = P->pool;
+        if (pool.empty()) pool.push_back(0.f);
+        P->d_pool = dev_upload(pool);
+        P->d_pgates = dev_upload(P->pgates);
+        P->d_grad_param = dev_upload(P->grad_param);
+        P->d_param_off = dev_upload(P->param_off);
+        P->d_param_slots = dev_upload(P->param_slots);
+        if (n_circuits > 1) {
+            std::vector<int32_t> cpart;
+            std::vector<int64_t> ctheta, cnpar;
+            for (auto &C : P->circ) {
+                cpart.push_back(C.part_begin);
+                ctheta.push_back(C.theta_off);
+                cnpar.push_back(C.n_params);
+            }
+            P->d_batch_order = dev_upload(P->batch_order);
+            P->d_circ_part = dev_upload(cpart);
+            P->d_circ_theta = dev_upload(ctheta);
+            P->d_circ_npar = dev_upload(cnpar);
+        }
+    }
+    return guard.release();
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: time the whole circuit for each candidate (k, tile shape) on a
+// scratch state of the real size and keep the fastest.  Results are cached per
+// (device, qubit count, flags, gate bytes) for the life of the process.
+struct TuneChoice {
+    int k, R, LW;
+    double ms;
+};
+static std::map<std::pair<int, size_t>, TuneChoice> g_tune_cache;
+static std::vector<TuneChoice> g_last_tune;
+
+static TuneChoice autotune(qsv_ctx *ctx, int n, const qsv_gate *gates, const std::vector<int64_t> &off, uint32_t flags)
+{
+    std::string key((const char *)gates, sizeof(qsv_gate) * (size_t)off.back());
+    key += std::to_string(n) + "/" + std::to_string(flags);
+    auto ck = std::make_pair(ctx->device, std::hash<std::string>()(key));
+    auto it = g_tune_cache.find(ck);
+    if (it != g_tune_cache.end()) return it->second;
+    TuneChoice best{std::min(10, n), 5, 8, -1.0};
+    g_last_tune.clear();
+    void *psi = nullptr;
+    if (hipMalloc(&psi, (size_t)8 << n) != hipSuccess) {
+        (void)hipGetLastError();
+        return best;  // no room for a trial state: default shape
+    }
+    hip_check(hipMemsetAsync(psi, 0, (size_t)8 << n, ctx->stream), "hipMemsetAsync");
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0), "hipEventCreate");
+    hip_check(hipEventCreate(&e1), "hipEventCreate");
+    const int shapes[][2] = {{5, 8}, {4, 8}, {4, 9}, {5, 9}, {4, 10}};
+    for (auto &sh : shapes) {
+        const int R = sh[0], LW = sh[1], t = R + LW;
+        if ((flags & QSV_PLAN_GRAD) && t > 13) continue;
+        for (int k : {8, 10, 12}) {
+            if (k >= t || k > n) continue;
+            qsv_plan *P = make_plan(ctx, n, gates, off, flags, k, R, LW);
+            float ms = 0;
+            for (int rep = 0; rep < 2; ++rep) {  // first run warms up
+                hip_check(hipEventRecord(e0, ctx->stream), "hipEventRecord");
+                for (int p = 0; p < (int)P->parts.size(); ++p)
+                    hip_check(launch_sweep(*P, P->R, P->LW, p, (float2 *)psi, nullptr, ctx->stream), "sweep");
+                hip_check(hipEventRecord(e1, ctx->stream), "hipEventRecord");
+                hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+                hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            }
+            qsv_plan_destroy(P);
+            g_last_tune.push_back(TuneChoice{k, R, LW, ms});
+            if (best.ms < 0 || ms < best.ms) best = TuneChoice{k, R, LW, ms};
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    hip_check(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    dev_free(psi);
+    g_tune_cache[ck] = best;
+    return best;
+}
+
 qsv_status qsv_partition(qsv_ctx *ctx, int32_t n_qubits, const qsv_gate *gates, const int64_t *circ_offsets,
                          int32_t n_circuits, int32_t k_local, uint32_t flags, const qsv_tile_config *tile,
                          qsv_plan **out)
@@ -276,64 +409,56 @@ qsv_status qsv_partition(qsv_ctx *ctx, int32_t n_qubits, const qsv_gate *gates, 
         const int64_t G = off[n_circuits];
         if (G > 0 && !gates) fail(QSV_E_ARG, "gates is null");
         if (n_circuits > 1 && n_qubits > 14) fail(QSV_E_ARG, "batched plans need n_qubits <= 14");
+        for (int c = 0; c < n_circuits; ++c)
+            for (int64_t g = off[c]; g < off[c + 1]; ++g) {
+                std::string e = validate_gate(gates[g], n_qubits, 0);
+                if (!e.empty()) {
+                    bool range = e.find("param") != std::string::npos;
+                    fail(range ? QSV_E_RANGE : QSV_E_ARG, "gate " + std::to_string(g - off[c]) + ": " + e);
+                }
+            }
+        bool user_tile = tile && (tile->reg_qubits || tile->log_threads);
         int R = 5, LW = 8;
-        if (tile && (tile->reg_qubits || tile->log_threads)) {
+        if (user_tile) {
             R = tile->reg_qubits;
             LW = tile->log_threads;
             if (!kernel_shape_supported(R, LW)) fail(QSV_E_ARG, "unsupported tile shape");
         }
-        if (n_circuits > 1) { R = 4; LW = 10; }
+        if (n_circuits > 1) {
+            if (n_qubits < 4) fail(QSV_E_UNSUPPORTED, "batched plans need n_qubits >= 4");
+            R = 4;
+            LW = 10;
+        }
         if ((flags & QSV_PLAN_GRAD) && n_circuits == 1 && R + LW > 13 && n_qubits > 13)
             fail(QSV_E_UNSUPPORTED, "gradient plans need a tile of at most 13 qubits");
         int k = k_local == 0 ? (n_qubits <= R + LW ? n_qubits : R + LW - 3) : k_local;
-        if (n_qubits > R + LW && k >= R + LW) fail(QSV_E_ARG, "k_local must be below the tile size");
-
-        auto P = new qsv_plan();
-        std::unique_ptr<qsv_plan, void (*)(qsv_plan *)> guard(P, [](qsv_plan *p) { qsv_plan_destroy(p); });
-        P->n = n_qubits;
-        P->n_circuits = n_circuits;
-        P->flags = flags;
-        choose_shape(n_qubits, R, LW, P->R, P->LW, P->t);
-        P->k = std::min(k, n_qubits);
-        P->gates.assign(gates, gates + G);
-        int64_t theta_off = 0;
-        for (int c = 0; c < n_circuits; ++c) {
-            CircuitPlan C;
-            C.g0 = off[c];
-            C.g1 = off[c + 1];
-            int64_t np = 0;
-            for (int64_t g = C.g0; g < C.g1; ++g) {
-                std::string e = validate_gate(P->gates[g], n_qubits, 0);
-                if (!e.empty()) {
-                    bool range = e.find("param") != std::string::npos;
-                    fail(range ? QSV_E_RANGE : QSV_E_ARG, "gate " + std::to_string(g - C.g0) + ": " + e);
-                }
-                np = std::max<int64_t>(np, (int64_t)P->gates[g].param + 1);
-            }
-            C.theta_off = theta_off;
-            C.n_params = np;
-            theta_off += np;
-            P->circ.push_back(C);
-        }
-        P->n_params = theta_off;
-        build_plan(*P);
-        if (ctx) {
+        if (n_circuits > 1) k = n_qubits;  // one partition per circuit: the whole state stays on chip
+        if (k_local == 0 && ctx && n_circuits == 1 && !user_tile && n_qubits > R + LW &&
+            !(flags & QSV_PLAN_GATE_BY_GATE)) {
             hip_check(hipSetDevice(ctx->device), "hipSetDevice");
-            P->device = ctx->device;
-            P->d_ops = dev_upload(P->ops);
-            P->d_stages = dev_upload(P->stages);
-            P->d_parts = dev_upload(P->parts);
-            std::vector<float> pool = P->pool;
-            if (pool.empty()) pool.push_back(0.f);
-            P->d_pool = dev_upload(pool);
-            P->d_pgates = dev_upload(P->pgates);
-            P->d_grad_param = dev_upload(P->grad_param);
-            P->d_param_off = dev_upload(P->param_off);
-            P->d_param_slots = dev_upload(P->param_slots);
+            TuneChoice c = autotune(ctx, n_qubits, gates, off, flags);
+            k = c.k;
+            R = c.R;
+            LW = c.LW;
         }
+        if (n_qubits > R + LW && k >= R + LW) fail(QSV_E_ARG, "k_local must be below the tile size");
+        qsv_plan *P = make_plan(ctx, n_qubits, gates, off, flags, k, R, LW);
         P->plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        *out = guard.release();
+        *out = P;
     });
+}
+
+// Candidates timed by the last autotuning run of this process: (k, R, LW, ms) x n.
+int32_t qsv_last_autotune(int32_t *out, int32_t cap)
+{
+    int32_t n = (int32_t)g_last_tune.size();
+    for (int32_t i = 0; out && i < std::min(n, cap); ++i) {
+        out[4 * i] = g_last_tune[i].k;
+        out[4 * i + 1] = g_last_tune[i].R;
+        out[4 * i + 2] = g_last_tune[i].LW;
+        out[4 * i + 3] = (int32_t)(g_last_tune[i].ms * 1000.0);
+    }
+    return n;
 }
 
 qsv_status qsv_plan_destroy(qsv_plan *plan)
@@ -350,9 +475,9 @@ qsv_status qsv_plan_destroy(qsv_plan *plan)
         dev_free(plan->d_param_off);
         dev_free(plan->d_param_slots);
         dev_free(plan->d_batch_order);
-        dev_free(plan->d_circ_stage);
+        dev_free(plan->d_circ_part);
         dev_free(plan->d_circ_theta);
-        dev_free(plan->d_circ_grad);
+        dev_free(plan->d_circ_npar);
         delete plan;
     });
 }
@@ -431,7 +556,14 @@ qsv_status qsv_apply(qsv_ctx *ctx, const qsv_plan *plan, const double *theta_dev
             fail(QSV_E_STATE, "plan has no device tables on this context's device");
         if (plan->n_params > 0 && !theta_dev) fail(QSV_E_ARG, "theta is null");
         hip_check(hipSetDevice(ctx->device), "hipSetDevice");
-        if (plan->n_circuits > 1) fail(QSV_E_UNSUPPORTED, "batched forward-only apply not built");
+        if (plan->n_circuits > 1) {
+            hip_check(launch_batched(*plan, nullptr, 0, nullptr, theta_dev, (float2 *)psi_dev, nullptr, nullptr,
+                                     nullptr, ctx->ensure_queue(), false, ctx->grid_batched(plan->n_circuits),
+                                     ctx->stream),
+                      "batched launch");
+            ctx->last_launches = 0;
+            return;
+        }
         hip_check(launch_materialize(*plan, theta_dev, ctx->stream), "materialize");
         const int np = (int)plan->parts.size();
         if (ctx->timing) {
@@ -486,7 +618,19 @@ qsv_status qsv_adjoint_grad(qsv_ctx *ctx, const qsv_plan *plan, const qsv_pauli_
         if (plan->device != ctx->device) fail(QSV_E_STATE, "plan has no device tables on this context's device");
         HostGroups g = group_terms(H, n_terms, plan->n);
         hip_check(hipSetDevice(ctx->device), "hipSetDevice");
-        if (plan->n_circuits > 1) fail(QSV_E_UNSUPPORTED, "batched adjoint not built");
+        if (plan->n_circuits > 1) {
+            const int64_t n_slots = (int64_t)plan->grad_param.size();
+            size_t need = sizeof(double) * (size_t)std::max<int64_t>(1, n_slots) * batched_waves();
+            double *gpart = (double *)ctx->ensure(ctx->scratch, ctx->scratch_bytes, need);
+            DevGroup *dg = nullptr;
+            DevTerm *dt = nullptr;
+            if (!g.groups.empty()) upload_groups(ctx, g, dg, dt);
+            hip_check(launch_batched(*plan, dg, (int)g.groups.size(), dt, theta_dev, (float2 *)psi_final_dev,
+                                     energy_dev, grad_dev, gpart, ctx->ensure_queue(), true,
+                                     ctx->grid_batched(plan->n_circuits), ctx->stream),
+                      "batched launch");
+            return;
+        }
         if (!(plan->flags & QSV_PLAN_GRAD)) fail(QSV_E_STATE, "plan was built without QSV_PLAN_GRAD");
         if (!psi_final_dev) fail(QSV_E_ARG, "psi_final is null");
         const int np = (int)plan->parts.size();

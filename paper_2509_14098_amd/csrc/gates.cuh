@@ -254,9 +254,87 @@ __device__ __forceinline__ void apply_op(float2 (&a)[1 << R], const DevOp &o, co
     }
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint helpers: Im <lambda|P|psi> for the generator P of a rotation
+// exp(-i a P / 2), over one thread's amplitudes, in float64.
+__device__ __forceinline__ double im_conj_mul(float2 l, float2 a) { return (double)l.x * a.y - (double)l.y * a.x; }
+__device__ __forceinline__ double re_conj_mul(float2 l, float2 a) { return (double)l.x * a.x + (double)l.y * a.y; }
+
+template <int R, int J>
+__device__ __forceinline__ double grad_pairs(const float2 (&a)[1 << R], const float2 (&l)[1 << R], bool y_gen)
+{
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < (1 << R); ++i) {
+        if (i & (1 << J)) continue;
+        const float2 a0 = a[i], a1 = a[i | (1 << J)], l0 = l[i], l1 = l[i | (1 << J)];
+        if (y_gen)  // Y: (Y psi)_0 = -i psi_1, (Y psi)_1 = i psi_0
+            acc += re_conj_mul(l1, a0) - re_conj_mul(l0, a1);
+        else        // X: (X psi)_0 = psi_1, (X psi)_1 = psi_0
+            acc += im_conj_mul(l0, a1) + im_conj_mul(l1, a0);
+    }
+    return acc;
+}
+
+// Im <lambda|P|psi> over this thread's amplitudes for the op's generator.
+template <int R>
+__device__ __forceinline__ double grad_term(const float2 (&a)[1 << R], const float2 (&l)[1 << R], const DevOp &o,
+                                            uint32_t tid, uint64_t base)
+{
+    double acc = 0.0;
+    if (o.gen == GEN_Z || o.gen == GEN_ZZ) {
+        uint32_t p = loc_pattern(o.a, tid, base);
+        if (o.gen == GEN_ZZ) p ^= loc_pattern(o.b, tid, base);
+#pragma unroll
+        for (int i = 0; i < (1 << R); ++i) {
+            const double v = im_conj_mul(l[i], a[i]);
+            acc += ((p >> i) & 1u) ? -v : v;
+        }
+    } else {
+        const bool y = o.gen == GEN_Y;
+        on_reg<R>(o.a & 0x3F, [&](auto J) __attribute__((always_inline)) { acc = grad_pairs<R, std::decay_t<decltype(J)>::value>(a, l, y); });
+    }
+    return acc;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
 // XOR swizzle of an 8-byte LDS slot: bits 5-9 and 10-14 of the tile position
 // are folded into bits 0-4, so 32 lanes whose positions differ in bits with
 // distinct residues mod 5 hit distinct bank pairs.
 __device__ __forceinline__ uint32_t swz(uint32_t c) { return c ^ ((c >> 5) & 31u) ^ ((c >> 10) & 31u); }
+
+// Run the register stages [s0, s1) of a tile held in LDS.
+template <int R, bool DAG>
+__device__ __forceinline__ void run_stages(float2 *lds, const DevStage *__restrict__ stages, const DevOp *__restrict__ ops,
+                                           const float *__restrict__ pool, int s0, int s1, int w, uint32_t tid,
+                                           uint64_t base)
+{
+    constexpr int NA = 1 << R;
+    const bool active = tid < (1u << w);
+    for (int s = s0; s < s1; ++s) {
+        const DevStage *__restrict__ S = stages + s;
+        if (active) {
+            uint32_t toff = 0;
+            for (int b = 0; b < w; ++b) toff |= ((tid >> b) & 1u) << S->thrpos[b];
+            uint32_t roff[NA];
+            roff[0] = 0;
+#pragma unroll
+            for (int i = 1; i < NA; ++i) roff[i] = roff[i & (i - 1)] | (1u << S->regpos[__builtin_ctz(i)]);
+            float2 a[NA];
+#pragma unroll
+            for (int i = 0; i < NA; ++i) a[i] = lds[swz(toff | roff[i])];
+            for (int k = S->op_begin; k < S->op_end; ++k) apply_op<R, DAG>(a, ops[k], pool, tid, base);
+#pragma unroll
+            for (int i = 0; i < NA; ++i) lds[swz(toff | roff[i])] = a[i];
+        }
+        __syncthreads();
+    }
+}
 
 }  // namespace qsv

@@ -76,10 +76,10 @@ struct Plan {
     int32_t *d_grad_param = nullptr;
     int32_t *d_param_off = nullptr;
     int32_t *d_param_slots = nullptr;
-    int32_t *d_batch_order = nullptr;
-    int32_t *d_circ_stage = nullptr;   // batched: [stage_begin, stage_end) per circuit
+    int32_t *d_batch_order = nullptr;  // batched: queue position -> circuit
+    int32_t *d_circ_part = nullptr;    // batched: circuit -> its DevPart
     int64_t *d_circ_theta = nullptr;   // batched: theta offset per circuit
-    int32_t *d_circ_grad = nullptr;    // batched: first grad slot per circuit
+    int64_t *d_circ_npar = nullptr;    // batched: parameter count per circuit
 };
 
 // planner.cpp

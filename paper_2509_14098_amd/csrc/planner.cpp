@@ -356,6 +356,7 @@ void build_plan(Plan &P)
         } else {
             C.parts = greedy_partition(n, P.meta, all, k, ~0ull);
         }
+        if (C.parts.empty()) C.parts.push_back(Part());  // an empty circuit still gets one (empty) sweep
         C.part_begin = (int32_t)P.parts.size();
         for (auto &part : C.parts) {
             part.S = pad_low(part.S, n, std::min(k, n));
@@ -372,6 +373,7 @@ void build_plan(Plan &P)
             }
             // level 2: register stages of this partition
             std::vector<Part> st = greedy_partition(n, P.meta, part.gates, R, T);
+            if (st.empty()) st.push_back(Part());  // every partition has at least one stage
             dp.stage_begin = (int32_t)P.stages.size();
             for (auto &s : st) {
                 DevStage ds;
@@ -422,6 +424,12 @@ void build_plan(Plan &P)
             P.bytes += 16.0 * dim;
         }
     }
+    // batched plans: longest circuits first in the work queue
+    P.batch_order.resize(P.circ.size());
+    for (size_t c = 0; c < P.circ.size(); ++c) P.batch_order[c] = (int32_t)c;
+    std::stable_sort(P.batch_order.begin(), P.batch_order.end(), [&](int32_t x, int32_t y) {
+        return P.circ[x].g1 - P.circ[x].g0 > P.circ[y].g1 - P.circ[y].g0;
+    });
     // theta index -> gradient slots, in slot order (deterministic sums)
     P.param_off.assign(P.n_params + 1, 0);
     for (int32_t p : P.grad_param) P.param_off[p + 1]++;

@@ -77,34 +77,6 @@ __device__ __forceinline__ void store_tile(float2 *__restrict__ psi, float2 *__r
     }
 }
 
-// Run the register stages [s0, s1) of a tile held in LDS.
-template <int R, bool DAG>
-__device__ __forceinline__ void run_stages(float2 *lds, const DevStage *__restrict__ stages, const DevOp *__restrict__ ops,
-                                           const float *__restrict__ pool, int s0, int s1, int w, uint32_t tid,
-                                           uint64_t base)
-{
-    constexpr int NA = 1 << R;
-    const bool active = tid < (1u << w);
-    for (int s = s0; s < s1; ++s) {
-        const DevStage *__restrict__ S = stages + s;
-        if (active) {
-            uint32_t toff = 0;
-            for (int b = 0; b < w; ++b) toff |= ((tid >> b) & 1u) << S->thrpos[b];
-            uint32_t roff[NA];
-            roff[0] = 0;
-#pragma unroll
-            for (int i = 1; i < NA; ++i) roff[i] = roff[i & (i - 1)] | (1u << S->regpos[__builtin_ctz(i)]);
-            float2 a[NA];
-#pragma unroll
-            for (int i = 0; i < NA; ++i) a[i] = lds[swz(toff | roff[i])];
-            for (int k = S->op_begin; k < S->op_end; ++k) apply_op<R, DAG>(a, ops[k], pool, tid, base);
-#pragma unroll
-            for (int i = 0; i < NA; ++i) lds[swz(toff | roff[i])] = a[i];
-        }
-        __syncthreads();
-    }
-}
-
 template <int R, int LW>
 __global__ __launch_bounds__(1 << LW) void sweep_kernel(float2 *__restrict__ psi, float2 *__restrict__ ckpt,
                                                           const DevPart *__restrict__ parts, int pidx,

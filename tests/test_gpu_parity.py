@@ -272,3 +272,104 @@ def test_c4_gradient_vs_oracle_and_fd(sim):
         tm[j] -= h
         fd = (oracle.expect(n, H, oracle.apply(n, gates, tp)) - oracle.expect(n, H, oracle.apply(n, gates, tm))) / (2 * h)
         assert abs(g[j] - fd) < 1e-4
+
+
+# ---------------------------------------------------------------- batched persistent launch
+
+def _batch(circs, thetas):
+    gates = np.concatenate(circs)
+    off = np.concatenate([[0], np.cumsum([len(c) for c in circs])])
+    theta = np.concatenate(thetas) if thetas else np.zeros(0)
+    return gates, off, theta
+
+
+@pytest.mark.parametrize("n,B,seed", [(4, 3, 1), (9, 7, 2), (14, 64, 5)])
+def test_batched_energy_gradient_and_states(sim, n, B, seed):
+    """Uneven-depth ansatz instances in one persistent launch: every
+    instance's final state, energy and gradient against the oracle run on
+    that instance alone (depths span the extremes 4 and 16)."""
+    circs, depths, thetas = W.ansatz_batch(B, n, 4, 16, seed=seed)
+    depths[0], depths[-1] = 4, 16
+    circs[0], _ = W.ansatz(n, 4)
+    circs[-1], _ = W.ansatz(n, 16)
+    thetas[0] = W.ansatz_params(2 * n * 4, seed=seed + 100)
+    thetas[-1] = W.ansatz_params(2 * n * 16, seed=seed + 101)
+    gates, off, theta = _batch(circs, thetas)
+    H = W.zz_chain_plus_x(n, 0.5)
+    plan = sim.partition(n, gates, 0, Q.PLAN_GRAD, None, circ_offsets=off)
+    try:
+        assert plan.n_params == len(theta)
+        psi = torch.empty((B, 1 << n), dtype=torch.complex64, device="cuda")
+        energy, grad = sim.adjoint_grad(plan, H, theta, psi)
+        torch.cuda.synchronize()
+        psi2 = torch.empty_like(psi)
+        sim.apply(plan, psi2, theta)
+        torch.cuda.synchronize()
+    finally:
+        plan.close()
+    energy, grad, psi, psi2 = energy.cpu().numpy(), grad.cpu().numpy(), psi.cpu().numpy(), psi2.cpu().numpy()
+    assert np.array_equal(psi, psi2)  # forward-only launch gives the same states
+    for b in range(B):
+        o0, o1 = off[b], off[b + 1]
+        p0 = sum(len(t) for t in thetas[:b])
+        e_ref, g_ref = oracle.adjoint(n, circs[b], thetas[b], H)
+        assert abs(energy[b] - e_ref) < 1e-4, b
+        assert np.max(np.abs(grad[p0:p0 + len(thetas[b])] - g_ref)) < 1e-4, b
+        ref = oracle.apply(n, circs[b], thetas[b])
+        assert np.max(np.abs(psi[b] - ref)) < 1e-5, b
+
+
+def test_batched_instance_equals_alone(sim):
+    """T5: an instance inside a batch gives what the single-circuit tiled path
+    gives for it alone (different kernels, so agreement within rounding)."""
+    n = 10
+    circs, depths, thetas = W.ansatz_batch(16, n, 4, 16, seed=9)
+    gates, off, theta = _batch(circs, thetas)
+    H = W.zz_chain_plus_x(n, 0.5)
+    plan = sim.partition(n, gates, 0, Q.PLAN_GRAD, None, circ_offsets=off)
+    e_all, g_all = sim.adjoint_grad(plan, H, theta)
+    plan.close()
+    for b in (0, 7, 15):
+        single = sim.partition(n, circs[b], 0, Q.PLAN_GRAD)
+        psi = sim.zero_state(n)
+        ckpt = sim.checkpoints(single)
+        sim.apply(single, psi, thetas[b], ckpt)
+        e1, g1 = sim.adjoint_grad(single, H, thetas[b], psi, ckpt)
+        single.close()
+        p0 = sum(len(t) for t in thetas[:b])
+        assert abs(float(e_all[b]) - float(e1[0])) < 1e-5
+        assert np.max(np.abs(g_all.cpu().numpy()[p0:p0 + len(thetas[b])] - g1.cpu().numpy())) < 1e-5
+
+
+def test_batched_with_empty_circuit(sim):
+    n = 5
+    a, na = W.ansatz(n, 3)
+    empty = a[:0]
+    circs, thetas = [a, empty, a], [W.ansatz_params(na, 1), np.zeros(0), W.ansatz_params(na, 2)]
+    gates, off, theta = _batch(circs, thetas)
+    H = W.zz_chain_plus_x(n, 0.5)
+    plan = sim.partition(n, gates, 0, Q.PLAN_GRAD, None, circ_offsets=off)
+    psi = torch.empty((3, 1 << n), dtype=torch.complex64, device="cuda")
+    e, g = sim.adjoint_grad(plan, H, theta, psi)
+    plan.close()
+    assert abs(float(e[1]) - oracle.expect(n, H, oracle.zero_state(n))) < 1e-6
+    assert abs(complex(psi[1, 0].item()) - 1) < 1e-7
+    for b in (0, 2):
+        e_ref, g_ref = oracle.adjoint(n, circs[b], thetas[b], H)
+        assert abs(float(e[b]) - e_ref) < 1e-5
+
+
+def test_autotuner_choice_is_correct(sim):
+    n = 17
+    gates = W.brickwork_c3(n=17, layers=6, seed=3)
+    plan = sim.partition(n, gates, 0)
+    tried = Q.qsv_last_autotune()
+    info = plan.info
+    psi = sim.zero_state(n)
+    sim.apply(plan, psi)
+    torch.cuda.synchronize()
+    plan.close()
+    assert len(tried) >= 3
+    best = min(tried, key=lambda r: r[3])
+    assert (info["k_local"], info["reg_qubits"], info["log_threads"]) == best[:3]
+    assert_close(psi.cpu().numpy(), oracle.apply(n, gates))

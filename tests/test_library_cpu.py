@@ -18,7 +18,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def test_library_exports_every_declared_symbol():
     lib = Q.load_library()
     header = open(os.path.join(ROOT, "include", "qsv.h")).read()
-    names = set(re.findall(r"^\s*(?:qsv_status|const char \*)\s*(qsv_\w+)\s*\(", header, re.M))
+    names = set(re.findall(r"^\s*(?:qsv_status|int32_t|const char \*)\s*(qsv_\w+)\s*\(", header, re.M))
     assert {"qsv_create", "qsv_partition", "qsv_apply", "qsv_expect", "qsv_adjoint_grad"} <= names
     for name in names:
         assert hasattr(lib, name), name
