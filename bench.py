@@ -12,6 +12,8 @@ Side measurements (separate timed regions, not in `value`):
   * the same circuit gate by gate (one sweep per gate) -> fused speed-up;
   * the 20-qubit RY.RZ + CX-ladder ansatz (400 parameters): adjoint gradient
     time / forward time;
+  * 2048 x 14-qubit ansatz instances (depths 4..16): energy + gradient of all
+    instances in one persistent launch;
   * the oracle (plain complex128 CPU simulator) on a bounded prefix of the
     headline circuit -> cpu_baseline.
 Prints one JSON line.
@@ -131,6 +133,45 @@ def bench_gradient(sim, args):
     return res
 
 
+def bench_batched(sim, args):
+    """2048 instances of the 14-qubit ansatz (depths U{4..16}), energy and
+    gradient of every instance in one persistent launch."""
+    n, B = 14, 2048
+    circs, depths, thetas = W.ansatz_batch(B, n, 4, 16, seed=5)
+    gates = np.concatenate(circs)
+    off = np.concatenate([[0], np.cumsum([len(c) for c in circs])])
+    theta = torch.as_tensor(np.concatenate(thetas), device=sim.device)
+    H = W.zz_chain_plus_x(n, 0.5)
+    t0 = time.perf_counter()
+    plan = sim.partition(n, gates, 0, Q.PLAN_GRAD, None, circ_offsets=off)
+    plan_s = time.perf_counter() - t0
+    energy = torch.empty(B, dtype=torch.float64, device=sim.device)
+    grad = torch.empty(len(theta), dtype=torch.float64, device=sim.device)
+    for _ in range(2):
+        Q.qsv_adjoint_grad(sim.ctx, plan.handle, H, theta, None, None, energy, grad)
+    sync()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        Q.qsv_adjoint_grad(sim.ctx, plan.handle, H, theta, None, None, energy, grad)
+    sync()
+    dt = (time.perf_counter() - t0) / reps
+    psi = torch.empty((B, 1 << n), dtype=torch.complex64, device=sim.device)
+    Q.qsv_apply(sim.ctx, plan.handle, theta, psi)
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        Q.qsv_apply(sim.ctx, plan.handle, theta, psi)
+    sync()
+    dtf = (time.perf_counter() - t0) / reps
+    info = plan.info
+    plan.close()
+    return dict(instances=B, n_qubits=n, gates=int(len(gates)), params=int(len(theta)),
+                fwd_energy_grad_ms=round(dt * 1e3, 3), instances_per_s=round(B / dt, 1),
+                forward_only_ms=round(dtf * 1e3, 3), grad_over_forward=round(dt / dtf, 3),
+                register_stages=info["n_stages"], plan_seconds=round(plan_s, 3))
+
+
 def bench_oracle(args, gpu_bytes_per_apply, n_gates_total):
     """The oracle on a bounded prefix of the headline circuit (~10-30 s)."""
     import oracle
@@ -160,6 +201,7 @@ def main():
     ap.add_argument("--tile", type=int, nargs=2, default=None, help="reg_qubits log_threads")
     ap.add_argument("--skip-gbg", action="store_true")
     ap.add_argument("--skip-grad", action="store_true")
+    ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
@@ -209,6 +251,8 @@ def main():
                                     fused_speedup=round(head["gbg_ms"] / (head["kernel_ms_total"] / args.steps), 2))
     if not args.skip_grad:
         line["adjoint"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in bench_gradient(sim, args).items()}
+    if not args.skip_batched:
+        line["batched"] = bench_batched(sim, args)
     if not args.skip_cpu:
         line["cpu_baseline"] = bench_oracle(args, info["bytes_per_apply"], info["n_gates"])
     else:

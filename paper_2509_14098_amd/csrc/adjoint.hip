@@ -84,17 +84,13 @@ __global__ __launch_bounds__(1 << LW) void reverse_kernel(const float2 *__restri
     const int64_t part_index = (int64_t)blockIdx.x * waves + (tid >> 6);
     for (int s = P->stage_end - 1; s >= P->stage_begin; --s) {
         const DevStage *__restrict__ S = stages + s;
-        uint32_t toff = 0;
-        for (int b = 0; b < w; ++b) toff |= ((tid >> b) & 1u) << S->thrpos[b];
-        uint32_t roff[NA];
-        roff[0] = 0;
-#pragma unroll
-        for (int i = 1; i < NA; ++i) roff[i] = roff[i & (i - 1)] | (1u << S->regpos[__builtin_ctz(i)]);
+        uint32_t toff, roff[NA];
+        stage_offsets<R>(S, w, tid, toff, roff);
         float2 a[NA], l[NA];
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
-            a[i] = active ? lds_psi[swz(toff | roff[i])] : float2{0.f, 0.f};
-            l[i] = active ? lds_lam[swz(toff | roff[i])] : float2{0.f, 0.f};
+            a[i] = active ? lds_psi[toff ^ roff[i]] : float2{0.f, 0.f};
+            l[i] = active ? lds_lam[toff ^ roff[i]] : float2{0.f, 0.f};
         }
         for (int k = S->op_end - 1; k >= S->op_begin; --k) {
             const DevOp o = ops[k];
@@ -108,8 +104,8 @@ __global__ __launch_bounds__(1 << LW) void reverse_kernel(const float2 *__restri
         if (active) {
 #pragma unroll
             for (int i = 0; i < NA; ++i) {
-                lds_psi[swz(toff | roff[i])] = a[i];
-                lds_lam[swz(toff | roff[i])] = l[i];
+                lds_psi[toff ^ roff[i]] = a[i];
+                lds_lam[toff ^ roff[i]] = l[i];
             }
         }
         __syncthreads();

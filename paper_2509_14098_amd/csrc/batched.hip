@@ -47,18 +47,8 @@ struct BatchArgs {
     int adjoint;
 };
 
-template <int R>
-__device__ __forceinline__ void stage_offsets(const DevStage *__restrict__ S, int w, uint32_t tid, uint32_t &toff,
-                                              uint32_t (&roff)[1 << R])
-{
-    toff = 0;
-    for (int b = 0; b < w; ++b) toff |= ((tid >> b) & 1u) << S->thrpos[b];
-    roff[0] = 0;
-#pragma unroll
-    for (int i = 1; i < (1 << R); ++i) roff[i] = roff[i & (i - 1)] | (1u << S->regpos[__builtin_ctz(i)]);
-}
-
-// Registers in the layout (toff, roff) -> LDS -> registers in the layout (toff2, roff2).
+// Registers in the layout (toff, roff) -> LDS -> registers in the layout (toff2,
+// roff2); offsets are already swizzled.
 template <int R>
 __device__ __forceinline__ void remap(float2 (&v)[1 << R], float2 *lds, bool active, uint32_t toff,
                                       const uint32_t (&roff)[1 << R], uint32_t toff2, const uint32_t (&roff2)[1 << R])
@@ -66,12 +56,12 @@ __device__ __forceinline__ void remap(float2 (&v)[1 << R], float2 *lds, bool act
     __syncthreads();
     if (active) {
 #pragma unroll
-        for (int i = 0; i < (1 << R); ++i) lds[swz(toff | roff[i])] = v[i];
+        for (int i = 0; i < (1 << R); ++i) lds[toff ^ roff[i]] = v[i];
     }
     __syncthreads();
     if (active) {
 #pragma unroll
-        for (int i = 0; i < (1 << R); ++i) v[i] = lds[swz(toff2 | roff2[i])];
+        for (int i = 0; i < (1 << R); ++i) v[i] = lds[toff2 ^ roff2[i]];
     }
 }
 
@@ -118,8 +108,9 @@ __global__ __launch_bounds__(1 << LW) void batched_kernel(BatchArgs A)
             a[i] = float2{0.f, 0.f};
             l[i] = float2{0.f, 0.f};
             if (active) {
-                const uint32_t x = toff | roff[i];
-                a[i] = lds[swz(x)];
+                const uint32_t sx = toff ^ roff[i];  // swizzled slot of amplitude x
+                const uint32_t x = swz(sx);          // swz is an involution here: recovers x
+                a[i] = lds[sx];
                 double lr = 0.0, li = 0.0;
                 for (int g = 0; g < A.n_groups; ++g) {
                     const DevGroup G = A.groups[g];

@@ -278,12 +278,15 @@ static qsv_plan *make_plan(qsv_ctx *ctx, int n_qubits, const qsv_gate *gates, co
     P->n = n_qubits;
     P->n_circuits = n_circuits;
     P->flags = flags;
+    // a register stage must hold every gate's required qubits (up to 2)
+    int need_r = 1;
+    for (int64_t g = 0; g < off[n_circuits]; ++g) need_r = std::max(need_r, __builtin_popcountll(classify(gates[g]).req));
     if (n_circuits > 1) {
         P->R = R;
         P->LW = LW;
         P->t = n_qubits;
     } else {
-        choose_shape(n_qubits, R, LW, P->R, P->LW, P->t);
+        choose_shape(n_qubits, std::max(R, std::min(need_r, n_qubits)), LW, P->R, P->LW, P->t);
     }
     P->k = std::min(k, n_qubits);
     P->gates.assign(gates, gates + off[n_circuits]);
@@ -308,7 +311,7 @@ static qsv_plan *make_plan(qsv_ctx *ctx, int n_qubits, const qsv_gate *gates, co
         P->d_stages = dev_upload(P->stages);
         P->d_parts = dev_upload(P->parts);
         std::vector<float> pool = P->pool;
-        if (pool.empty()) pool.push_back(0.f);
+        pool.resize(pool.size() + 8, 0.f);  // op prefetch reads 8 floats at any offset
         P->d_pool = dev_upload(pool);
         P->d_pgates = dev_upload(P->pgates);
         P->d_grad_param = dev_upload(P->grad_param);
@@ -349,7 +352,7 @@ static TuneChoice autotune(qsv_ctx *ctx, int n, const qsv_gate *gates, const std
     auto ck = std::make_pair(ctx->device, std::hash<std::string>()(key));
     auto it = g_tune_cache.find(ck);
     if (it != g_tune_cache.end()) return it->second;
-    TuneChoice best{std::min(10, n), 5, 8, -1.0};
+    TuneChoice best{std::min(9, n), 4, 8, -1.0};
     g_last_tune.clear();
     void *psi = nullptr;
     if (hipMalloc(&psi, (size_t)8 << n) != hipSuccess) {
@@ -418,7 +421,7 @@ qsv_status qsv_partition(qsv_ctx *ctx, int32_t n_qubits, const qsv_gate *gates, 
                 }
             }
         bool user_tile = tile && (tile->reg_qubits || tile->log_threads);
-        int R = 5, LW = 8;
+        int R = 4, LW = 8;  // default shape: 4 register qubits, 256 threads, 12-qubit tiles
         if (user_tile) {
             R = tile->reg_qubits;
             LW = tile->log_threads;
@@ -595,7 +598,7 @@ qsv_status qsv_expect(qsv_ctx *ctx, const qsv_pauli_term *H, int32_t n_terms, in
         if (batch < 1) fail(QSV_E_ARG, "batch must be >= 1");
         HostGroups g = group_terms(H, n_terms, n_qubits);
         hip_check(hipSetDevice(ctx->device), "hipSetDevice");
-        const int n_blocks = 512;
+        const int n_blocks = 2048;  // partials below are sized for this cap
         size_t need = sizeof(double) * (size_t)n_blocks * std::max<size_t>(1, g.groups.size()) * (size_t)batch;
         double *partials = (double *)ctx->ensure(ctx->scratch, ctx->scratch_bytes, need);
         DevGroup *dg = nullptr;

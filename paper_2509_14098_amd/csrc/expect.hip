@@ -47,13 +47,27 @@ __global__ __launch_bounds__(RED_THREADS) void expect_kernel(const DevGroup *__r
     const uint64_t stride = (uint64_t)gridDim.x * RED_THREADS;
     double acc = 0.0;
     if (G.x_mask == 0) {
-        const uint64_t dim = 1ull << n;
-        for (uint64_t x = (uint64_t)blockIdx.x * RED_THREADS + threadIdx.x; x < dim; x += stride) {
-            const float2 a = s[x];
-            const double p = (double)a.x * a.x + (double)a.y * a.y;
+        // diagonal group: amplitudes read as 16-byte pairs, four pairs in flight per thread
+        auto weight = [&](uint64_t x) __attribute__((always_inline)) {
             double w = 0.0;
             for (int t = G.term_begin; t < G.term_end; ++t) w += terms[t].cre * parity_sign(x & terms[t].z_mask);
-            acc += p * w;
+            return w;
+        };
+        auto pair = [&](uint64_t i, float4 v) __attribute__((always_inline)) {
+            const double p0 = (double)v.x * v.x + (double)v.y * v.y, p1 = (double)v.z * v.z + (double)v.w * v.w;
+            return p0 * weight(2 * i) + p1 * weight(2 * i + 1);
+        };
+        if (n == 1) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) acc = pair(0, *reinterpret_cast<const float4 *>(s));
+        } else {
+            const uint64_t n2 = 1ull << (n - 1);
+            const float4 *__restrict__ s4 = reinterpret_cast<const float4 *>(s);
+            uint64_t i = (uint64_t)blockIdx.x * RED_THREADS + threadIdx.x;
+            for (; i + 3 * stride < n2; i += 4 * stride) {
+                const float4 v0 = s4[i], v1 = s4[i + stride], v2 = s4[i + 2 * stride], v3 = s4[i + 3 * stride];
+                acc += pair(i, v0) + pair(i + stride, v1) + pair(i + 2 * stride, v2) + pair(i + 3 * stride, v3);
+            }
+            for (; i < n2; i += stride) acc += pair(i, s4[i]);
         }
     } else {
         const int lb = __builtin_ctzll(G.x_mask);
@@ -125,7 +139,7 @@ __global__ __launch_bounds__(RED_THREADS) void apply_h_kernel(const DevGroup *__
 
 static int blocks_for(uint64_t work, int cap)
 {
-    uint64_t b = (work + RED_THREADS * 8 - 1) / (RED_THREADS * 8);
+    uint64_t b = (work + RED_THREADS * 16 - 1) / (RED_THREADS * 16);
     return (int)std::max<uint64_t>(1, std::min<uint64_t>(b, (uint64_t)cap));
 }
 

@@ -59,6 +59,17 @@ struct C2 {
     float r, i;
 };
 
+// The 8 floats of a 2x2 gate matrix (or 4 diagonal entries), loaded as one
+// scalar block so the next op's matrix can be fetched while this one runs.
+struct M8 {
+    float v[8];
+};
+
+__device__ __forceinline__ M8 load_m8(const float *__restrict__ pool, int32_t mat)
+{
+    return *reinterpret_cast<const M8 *>(pool + (mat < 0 ? 0 : mat));
+}
+
 __device__ __forceinline__ C2 ld2(const float *__restrict__ m, int k, bool conj)
 {
     return C2{m[2 * k], conj ? -m[2 * k + 1] : m[2 * k + 1]};
@@ -117,6 +128,14 @@ __device__ __forceinline__ void g_d1(float2 (&a)[1 << R], const float *__restric
         bool s = (p >> i) & 1u;
         a[i] = cmul(a[i], C2{s ? d1.r : d0.r, s ? d1.i : d0.i});
     }
+}
+
+// Diagonal over the register index: a[i] *= d[i] (d uniform across threads).
+template <int R, bool DAG>
+__device__ __forceinline__ void g_dreg(float2 (&a)[1 << R], const float *__restrict__ d)
+{
+#pragma unroll
+    for (int i = 0; i < (1 << R); ++i) a[i] = cmul(a[i], C2{d[2 * i], DAG ? -d[2 * i + 1] : d[2 * i + 1]});
 }
 
 // -1 where both qubits are 1 (pattern p = pa & pb).
@@ -209,15 +228,19 @@ __device__ __forceinline__ void g_swap(float2 (&a)[1 << R])
 }
 
 // Apply one op (or its conjugate transpose) to a thread's amplitudes.
+// mm holds the op's 8 leading matrix floats (load_m8); dense 4x4 ops read the
+// rest from the pool.
 template <int R, bool DAG>
-__device__ __forceinline__ void apply_op(float2 (&a)[1 << R], const DevOp &o, const float *__restrict__ pool,
-                                         uint32_t tid, uint64_t base)
+__device__ __forceinline__ void apply_op(float2 (&a)[1 << R], const DevOp &o, const M8 &mm,
+                                         const float *__restrict__ pool, uint32_t tid, uint64_t base)
 {
-    const float *__restrict__ m = pool + (o.mat < 0 ? 0 : o.mat);
+    const float *m = mm.v;
+    const float *__restrict__ m32 = pool + (o.mat < 0 ? 0 : o.mat);
     switch (o.kind) {
     case OP_U1: on_reg<R>(o.a & 0x3F, [&](auto J) __attribute__((always_inline)) { g_u1<R, std::decay_t<decltype(J)>::value, DAG>(a, m); }); break;
     case OP_R1: on_reg<R>(o.a & 0x3F, [&](auto J) __attribute__((always_inline)) { g_r1<R, std::decay_t<decltype(J)>::value, DAG>(a, m); }); break;
     case OP_D1: g_d1<R, DAG>(a, m, loc_pattern(o.a, tid, base)); break;
+    case OP_DREG: g_dreg<R, DAG>(a, m32); break;
     case OP_CZ: g_cz<R>(a, loc_pattern(o.a, tid, base) & loc_pattern(o.b, tid, base)); break;
     case OP_D2: g_d2<R, DAG>(a, m, loc_pattern(o.a, tid, base), loc_pattern(o.b, tid, base)); break;
     case OP_CX: {
@@ -235,7 +258,7 @@ __device__ __forceinline__ void apply_op(float2 (&a)[1 << R], const DevOp &o, co
             on_reg<R>(o.a & 0x3F, [&](auto JA) __attribute__((always_inline)) {
                 on_reg<R>(o.b & 0x3F, [&](auto JB) __attribute__((always_inline)) {
                     if constexpr (std::decay_t<decltype(JA)>::value != std::decay_t<decltype(JB)>::value)
-                        g_u2<R, std::decay_t<decltype(JA)>::value, std::decay_t<decltype(JB)>::value, DAG>(a, m);
+                        g_u2<R, std::decay_t<decltype(JA)>::value, std::decay_t<decltype(JB)>::value, DAG>(a, m32);
                 });
             });
         }
@@ -252,6 +275,13 @@ __device__ __forceinline__ void apply_op(float2 (&a)[1 << R], const DevOp &o, co
         break;
     default: break;
     }
+}
+
+template <int R, bool DAG>
+__device__ __forceinline__ void apply_op(float2 (&a)[1 << R], const DevOp &o, const float *__restrict__ pool,
+                                         uint32_t tid, uint64_t base)
+{
+    apply_op<R, DAG>(a, o, load_m8(pool, o.mat), pool, tid, base);
 }
 
 // ---------------------------------------------------------------------------
@@ -306,8 +336,28 @@ __device__ __forceinline__ double wave_sum(double v)
 
 // XOR swizzle of an 8-byte LDS slot: bits 5-9 and 10-14 of the tile position
 // are folded into bits 0-4, so 32 lanes whose positions differ in bits with
-// distinct residues mod 5 hit distinct bank pairs.
+// distinct residues mod 5 hit distinct bank pairs.  swz is linear over GF(2):
+// for positions with disjoint bits swz(a | b) = swz(a) ^ swz(b), so a thread
+// swizzles its thread-bit offset once and the register-bit offsets (uniform)
+// are swizzled in scalar registers.
 __device__ __forceinline__ uint32_t swz(uint32_t c) { return c ^ ((c >> 5) & 31u) ^ ((c >> 10) & 31u); }
+
+// Swizzled LDS offsets of a stage layout: the thread's own part and the
+// register-index parts (uniform).
+template <int R>
+__device__ __forceinline__ void stage_offsets(const DevStage *__restrict__ S, int w, uint32_t tid, uint32_t &toff,
+                                              uint32_t (&roff)[1 << R])
+{
+    uint32_t t = 0;
+    for (int b = 0; b < w; ++b) t |= ((tid >> b) & 1u) << S->thrpos[b];
+    toff = swz(t);
+    uint32_t r[1 << R];
+    r[0] = 0;
+#pragma unroll
+    for (int i = 1; i < (1 << R); ++i) r[i] = r[i & (i - 1)] | (1u << S->regpos[__builtin_ctz(i)]);
+#pragma unroll
+    for (int i = 0; i < (1 << R); ++i) roff[i] = swz(r[i]);
+}
 
 // Run the register stages [s0, s1) of a tile held in LDS.
 template <int R, bool DAG>
@@ -320,18 +370,26 @@ __device__ __forceinline__ void run_stages(float2 *lds, const DevStage *__restri
     for (int s = s0; s < s1; ++s) {
         const DevStage *__restrict__ S = stages + s;
         if (active) {
-            uint32_t toff = 0;
-            for (int b = 0; b < w; ++b) toff |= ((tid >> b) & 1u) << S->thrpos[b];
-            uint32_t roff[NA];
-            roff[0] = 0;
-#pragma unroll
-            for (int i = 1; i < NA; ++i) roff[i] = roff[i & (i - 1)] | (1u << S->regpos[__builtin_ctz(i)]);
+            uint32_t toff, roff[NA];
+            stage_offsets<R>(S, w, tid, toff, roff);
             float2 a[NA];
 #pragma unroll
-            for (int i = 0; i < NA; ++i) a[i] = lds[swz(toff | roff[i])];
-            for (int k = S->op_begin; k < S->op_end; ++k) apply_op<R, DAG>(a, ops[k], pool, tid, base);
+            for (int i = 0; i < NA; ++i) a[i] = lds[toff ^ roff[i]];
+            const int k0 = S->op_begin, k1 = S->op_end;
+            if (k0 < k1) {  // the next op and its matrix are fetched while the current one runs
+                DevOp cur = ops[k0];
+                M8 mc = load_m8(pool, cur.mat);
+                for (int k = k0; k < k1; ++k) {
+                    const int kn = k + 1 < k1 ? k + 1 : k;
+                    const DevOp nxt = ops[kn];
+                    const M8 mn = load_m8(pool, nxt.mat);
+                    apply_op<R, DAG>(a, cur, mc, pool, tid, base);
+                    cur = nxt;
+                    mc = mn;
+                }
+            }
 #pragma unroll
-            for (int i = 0; i < NA; ++i) lds[swz(toff | roff[i])] = a[i];
+            for (int i = 0; i < NA; ++i) lds[toff ^ roff[i]] = a[i];
         }
         __syncthreads();
     }

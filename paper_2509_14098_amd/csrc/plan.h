@@ -28,6 +28,7 @@ enum OpKind : uint8_t {
     OP_D2 = 7,   // diagonal 4x4 on two qubits anywhere
     OP_U2 = 8,   // dense 4x4 on two register qubits
     OP_SWAP = 9, // exchange of two register qubits
+    OP_DREG = 10, // diagonal over the register index: 2^R complex entries, same for every thread
 };
 
 // Location of a qubit in a stage layout: register slot, thread-id bit, or a
@@ -72,6 +73,7 @@ struct DevPart {
 };
 
 // Matrix pool layout: a 2x2 gate takes 8 floats (row-major re,im), a 4x4
-// gate 32 floats (local index j = b(q0) + 2 b(q1)).
+// gate 32 floats (local index j = b(q0) + 2 b(q1)), a register diagonal 2^R
+// complex entries; every entry starts at a multiple of 8 floats.
 
 }  // namespace qsv

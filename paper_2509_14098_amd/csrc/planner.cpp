@@ -10,7 +10,9 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <array>
 #include <cstring>
+#include <functional>
 #include <stdexcept>
 
 #include "internal.h"
@@ -95,8 +97,8 @@ GateMeta classify(const qsv_gate &g)
     r.param = g.param >= 0;
     if (r.param) {  // structure for a generic angle; matrix formed on the device
         switch (g.kind) {
-        case QSV_RX: r.op = OP_U1; r.req = r.qmask; r.gen = GEN_X; r.flops = 16; break;
-        case QSV_RY: r.op = OP_R1; r.req = r.qmask; r.gen = GEN_Y; r.flops = 8; break;
+        case QSV_RX: r.op = OP_U1; r.req = r.qmask; r.gen = GEN_X; r.flops = 14; break;
+        case QSV_RY: r.op = OP_R1; r.req = r.qmask; r.gen = GEN_Y; r.flops = 6; break;
         case QSV_RZ: r.op = OP_D1; r.req = 0; r.gen = GEN_Z; r.flops = 6; break;
         default: r.op = OP_D2; r.req = 0; r.gen = GEN_ZZ; r.flops = 6; break;  // RZZ
         }
@@ -109,8 +111,8 @@ GateMeta classify(const qsv_gate &g)
         bool diag = m[1] == 0.0 && m[2] == 0.0;
         bool real = m[0].imag() == 0 && m[1].imag() == 0 && m[2].imag() == 0 && m[3].imag() == 0;
         if (diag) { r.op = OP_D1; r.req = 0; r.flops = 6; }
-        else if (real) { r.op = OP_R1; r.req = r.qmask; r.flops = 8; }
-        else { r.op = OP_U1; r.req = r.qmask; r.flops = 16; }
+        else if (real) { r.op = OP_R1; r.req = r.qmask; r.flops = 6; }
+        else { r.op = OP_U1; r.req = r.qmask; r.flops = 14; }
         return r;
     }
     auto at = [&](int i, int j) { return m[i * 4 + j]; };
@@ -146,7 +148,7 @@ GateMeta classify(const qsv_gate &g)
             for (int i = 8; i < 32; ++i) r.m[i] = 0;
             bool x = u[0] == 0.0 && u[3] == 0.0 && u[1] == 1.0 && u[2] == 1.0;
             r.op = x ? OP_CX : OP_CU;
-            r.flops = x ? 0 : 8;
+            r.flops = x ? 0 : 7;
             return r;
         }
     }
@@ -158,7 +160,7 @@ GateMeta classify(const qsv_gate &g)
         }
     r.op = swap ? OP_SWAP : OP_U2;
     r.req = r.qmask;
-    r.flops = swap ? 0 : 32;
+    r.flops = swap ? 0 : 30;
     return r;
 }
 
@@ -301,6 +303,256 @@ static void stage_layout(uint32_t reg_posmask, int t, int R, int w, DevStage &st
     for (int b = 0; b < w; ++b) st.thrpos[b] = lanes[b];
 }
 
+// ---------------------------------------------------------------------------
+// Register-stage lowering with diagonal folding.
+//
+// Every 2x2 unitary factors exactly as U = D1 R D2 with D1, D2 diagonal and R
+// real ([[c, -s], [s, c]]); U3(t, p, l) = P(p) RY(t) P(l) is the familiar case.
+// Inside a stage, diagonal factors and diagonal gates on register qubits
+// commute with rotations on other qubits, so they are accumulated into one
+// diagonal over the register index (2^R complex entries, the same for every
+// thread) and applied as one complex multiply per amplitude.  The pending
+// block is kept as  Dpost * (rotations on distinct qubits) * Dpre  (Dpre
+// first).  A CX or SWAP between register qubits is crossed by permuting the
+// diagonal's entries.  Parameterised gates (matrices formed on the device) and
+// ops on thread or tile-index qubits that do not commute with the block end it.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Diag {
+    std::vector<cd> d;
+    explicit Diag(int na = 0) : d(na, cd(1.0, 0.0)) {}
+    bool identity() const
+    {
+        for (auto &v : d)
+            if (v != cd(1.0, 0.0)) return false;
+        return true;
+    }
+    bool depends_on(int j) const
+    {
+        for (size_t i = 0; i < d.size(); ++i)
+            if (d[i] != d[i ^ (size_t(1) << j)]) return true;
+        return false;
+    }
+};
+
+// U = D1 R D2, with D2 = diag(1, e^{i b2}); false when U is not (numerically) unitary-shaped.
+bool split_unitary(const double *m, cd &d1a, cd &d1b, double &c, double &sn, cd &d2b)
+{
+    const cd a(m[0], m[1]), b(m[2], m[3]), cc(m[4], m[5]), d(m[6], m[7]);
+    c = std::abs(a);
+    sn = std::abs(cc);
+    if (std::abs(c * c + sn * sn - 1.0) > 1e-12) return false;
+    double al1, al2, be2;
+    if (c > 1e-300 && sn > 1e-300) {
+        al1 = std::arg(a);
+        al2 = std::arg(cc);
+        be2 = std::arg(-b) - al1;
+    } else if (sn <= 1e-300) {  // diagonal: handled as a diagonal gate, not here
+        return false;
+    } else {                    // anti-diagonal: R = [[0, -1], [1, 0]]
+        al1 = 0.0;
+        al2 = std::arg(cc);
+        be2 = std::arg(-b);
+    }
+    d1a = std::polar(1.0, al1);
+    d1b = std::polar(1.0, al2);
+    d2b = std::polar(1.0, be2);
+    // reconstruct and check
+    const cd ra = d1a * c, rb = -d1a * sn * d2b, rc = d1b * sn, rd = d1b * c * d2b;
+    const double err = std::abs(ra - a) + std::abs(rb - b) + std::abs(rc - cc) + std::abs(rd - d);
+    return err < 1e-12;
+}
+
+struct StageLowering {
+    Plan &P;
+    const GateMeta *meta;
+    const std::vector<int32_t> &mat_of;
+    int R, NA;
+    std::function<int32_t(int)> loc;
+    const CircuitPlan &C;
+    Diag pre, post;
+    std::vector<std::pair<int, std::array<double, 4>>> rots;  // (register slot, real matrix)
+    uint32_t rot_mask = 0;
+
+    StageLowering(Plan &P_, const std::vector<int32_t> &mo, int R_, std::function<int32_t(int)> loc_,
+                  const CircuitPlan &C_)
+        : P(P_), meta(P_.meta.data()), mat_of(mo), R(R_), NA(1 << R_), loc(std::move(loc_)), C(C_), pre(1 << R_),
+          post(1 << R_)
+    {
+    }
+
+    static bool is_reg(int32_t l) { return (l & LOC_MASK) == LOC_REG; }
+
+    DevOp base_op(int kind, int gate)
+    {
+        DevOp o;
+        std::memset(&o, 0, sizeof(o));
+        o.kind = kind;
+        o.gate = gate;
+        o.grad_slot = -1;
+        o.mat = -1;
+        return o;
+    }
+    void add(const DevOp &o, double flops)
+    {
+        P.ops.push_back(o);
+        P.flops += flops * std::ldexp(1.0, P.n);
+    }
+    void emit_diag(Diag &D, int gate)
+    {
+        if (D.identity()) return;
+        DevOp o = base_op(OP_DREG, gate);
+        o.mat = (int32_t)P.pool.size();
+        for (auto &v : D.d) {
+            P.pool.push_back((float)v.real());
+            P.pool.push_back((float)v.imag());
+        }
+        while (P.pool.size() % 8) P.pool.push_back(0.f);
+        add(o, 6);
+        D = Diag(NA);
+    }
+    void emit_rots(int gate)
+    {
+        for (auto &r : rots) {
+            DevOp o = base_op(OP_R1, gate);
+            o.a = LOC_REG | r.first;
+            o.mat = (int32_t)P.pool.size();
+            const double *m = r.second.data();
+            const float f[8] = {(float)m[0], 0.f, (float)m[1], 0.f, (float)m[2], 0.f, (float)m[3], 0.f};
+            P.pool.insert(P.pool.end(), f, f + 8);
+            add(o, 6);
+        }
+        rots.clear();
+        rot_mask = 0;
+    }
+    // emit Dpre and the rotations; Dpost becomes the new pending Dpre
+    void flush_rots(int gate)
+    {
+        if (rots.empty()) {
+            for (int i = 0; i < NA; ++i) pre.d[i] *= post.d[i];
+            post = Diag(NA);
+            return;
+        }
+        emit_diag(pre, gate);
+        emit_rots(gate);
+        pre = post;
+        post = Diag(NA);
+    }
+    void flush_all(int gate)
+    {
+        flush_rots(gate);
+        emit_diag(pre, gate);
+    }
+    // value of a gate's diagonal entry for register index i (all qubits in registers)
+    cd diag_value(const GateMeta &m, int32_t la, int32_t lb, int i) const
+    {
+        const int ba = (i >> (la & 0x3F)) & 1;
+        if (m.nq == 1) return cd(m.m[2 * (ba * 3)], m.m[2 * (ba * 3) + 1]);
+        const int bb = (i >> (lb & 0x3F)) & 1;
+        const int j = ba + 2 * bb;
+        return cd(m.m[2 * (j * 4 + j)], m.m[2 * (j * 4 + j) + 1]);
+    }
+    void emit_plain(int g)
+    {
+        const GateMeta &m = meta[g];
+        DevOp o = base_op(m.op, g);
+        o.gen = m.gen;
+        o.mat = mat_of[g];
+        if (m.param) {
+            o.grad_slot = (int32_t)P.grad_param.size();
+            P.grad_param.push_back((int32_t)(C.theta_off + P.gates[g].param));
+        }
+        if (m.op == OP_CX || m.op == OP_CU) { o.a = loc(m.ctrl); o.b = loc(m.tgt); }
+        else { o.a = loc(m.q[0]); o.b = m.nq == 2 ? loc(m.q[1]) : 0; }
+        bool need_reg_a = m.op == OP_U1 || m.op == OP_R1 || m.op == OP_U2 || m.op == OP_SWAP;
+        bool need_reg_b = m.op == OP_CX || m.op == OP_CU || m.op == OP_U2 || m.op == OP_SWAP;
+        if ((need_reg_a && !is_reg(o.a)) || (need_reg_b && !is_reg(o.b)))
+            throw std::logic_error("required qubit not in registers");
+        add(o, m.flops);
+    }
+    void gate(int g, bool fold)
+    {
+        const GateMeta &m = meta[g];
+        if (!fold) { emit_plain(g); return; }
+        const bool diag = m.op == OP_D1 || m.op == OP_D2 || m.op == OP_CZ;
+        if (m.param) {  // matrix formed on the device: ends the block
+            flush_all(g);
+            emit_plain(g);
+            return;
+        }
+        if (diag) {
+            const int32_t la = loc(m.q[0]), lb = m.nq == 2 ? loc(m.q[1]) : LOC_REG;
+            const bool all_reg = is_reg(la) && is_reg(lb);
+            if (all_reg) {
+                for (int i = 0; i < NA; ++i) post.d[i] *= diag_value(m, la, lb, i);
+                return;
+            }
+            // touches a thread or tile-index qubit: commutes with the block unless a pending
+            // rotation acts on its register qubit
+            uint32_t regs = (is_reg(la) ? 1u << (la & 0x3F) : 0u) | (m.nq == 2 && is_reg(lb) ? 1u << (lb & 0x3F) : 0u);
+            if (regs & rot_mask) flush_rots(g);
+            emit_plain(g);
+            return;
+        }
+        if ((m.op == OP_U1 || m.op == OP_R1) && is_reg(loc(m.q[0]))) {
+            const int j = loc(m.q[0]) & 0x3F;
+            cd d1a, d1b, d2b;
+            double c, sn;
+            if (split_unitary(m.m, d1a, d1b, c, sn, d2b)) {
+                if ((rot_mask >> j) & 1u || post.depends_on(j)) flush_rots(g);
+                for (int i = 0; i < NA; ++i) {
+                    if ((i >> j) & 1) {
+                        pre.d[i] *= d2b;
+                        post.d[i] *= d1b;
+                    } else {
+                        post.d[i] *= d1a;
+                    }
+                }
+                rots.push_back({j, {c, -sn, sn, c}});
+                rot_mask |= 1u << j;
+                return;
+            }
+        }
+        if ((m.op == OP_CX || m.op == OP_SWAP) && is_reg(loc(m.q[0])) && is_reg(loc(m.q[1]))) {
+            // the diagonal pending before the permutation X is carried past it:
+            // X D = D' X with D'(i) = D(X(i))
+            flush_rots(g);
+            emit_plain(g);
+            Diag moved(NA);
+            for (int i = 0; i < NA; ++i) {
+                int k = i;
+                if (m.op == OP_CX) {
+                    const int c = loc(m.ctrl) & 0x3F, t = loc(m.tgt) & 0x3F;
+                    if ((i >> c) & 1) k ^= 1 << t;
+                } else {
+                    const int a = loc(m.q[0]) & 0x3F, b = loc(m.q[1]) & 0x3F;
+                    if (((i >> a) & 1) != ((i >> b) & 1)) k ^= (1 << a) | (1 << b);
+                }
+                moved.d[i] = pre.d[k];
+            }
+            pre = moved;
+            return;
+        }
+        flush_all(g);
+        emit_plain(g);
+    }
+};
+
+// VALU instructions per amplitude of an op kind (for choosing a lowering).
+double op_cost(int kind)
+{
+    switch (kind) {
+    case OP_U1: return 8;
+    case OP_R1: case OP_D1: case OP_D2: case OP_DREG: return 4;
+    case OP_CU: return 9;
+    case OP_U2: return 16;
+    default: return 1;  // CX, CZ, SWAP: selects and moves
+    }
+}
+
+}  // namespace
+
 void build_plan(Plan &P)
 {
     const int n = P.n;
@@ -329,7 +581,6 @@ void build_plan(Plan &P)
     const double dim = std::ldexp(1.0, n);
     for (auto &C : P.circ) {
         for (int64_t g = C.g0; g < C.g1; ++g) {
-            P.flops += P.meta[g].flops * dim;
             if (P.meta[g].param) {
                 ParamGate pg;
                 pg.mat = mat_of[g];
@@ -394,26 +645,24 @@ void build_plan(Plan &P)
                     throw std::logic_error("qubit not in layout");
                 };
                 ds.op_begin = (int32_t)P.ops.size();
-                for (int g : s.gates) {
-                    const GateMeta &m = P.meta[g];
-                    DevOp o;
-                    std::memset(&o, 0, sizeof(o));
-                    o.kind = m.op;
-                    o.gen = m.gen;
-                    o.mat = mat_of[g];
-                    o.gate = g;
-                    o.grad_slot = -1;
-                    if (m.param) {
-                        o.grad_slot = (int32_t)P.grad_param.size();
-                        P.grad_param.push_back((int32_t)(C.theta_off + P.gates[g].param));
-                    }
-                    if (m.op == OP_CX || m.op == OP_CU) { o.a = loc(m.ctrl); o.b = loc(m.tgt); }
-                    else { o.a = loc(m.q[0]); o.b = m.nq == 2 ? loc(m.q[1]) : 0; }
-                    bool need_reg_a = m.op == OP_U1 || m.op == OP_R1 || m.op == OP_U2 || m.op == OP_SWAP;
-                    bool need_reg_b = m.op == OP_CX || m.op == OP_CU || m.op == OP_U2 || m.op == OP_SWAP;
-                    if ((need_reg_a && (o.a & LOC_MASK) != LOC_REG) || (need_reg_b && (o.b & LOC_MASK) != LOC_REG))
-                        throw std::logic_error("required qubit not in registers");
-                    P.ops.push_back(o);
+                // lower with diagonal folding; keep it only if it needs fewer instructions
+                const size_t ops0 = P.ops.size(), pool0 = P.pool.size(), grad0 = P.grad_param.size();
+                const double flops0 = P.flops;
+                double plain_cost = 0, folded_cost = 0;
+                for (int g : s.gates) plain_cost += op_cost(P.meta[g].op);
+                {
+                    StageLowering L(P, mat_of, R, loc, C);
+                    for (int g : s.gates) L.gate(g, true);
+                    L.flush_all(s.gates.empty() ? -1 : s.gates.back());
+                    for (size_t k = ops0; k < P.ops.size(); ++k) folded_cost += op_cost(P.ops[k].kind);
+                }
+                if (folded_cost >= plain_cost) {
+                    P.ops.resize(ops0);
+                    P.pool.resize(pool0);
+                    P.grad_param.resize(grad0);
+                    P.flops = flops0;
+                    StageLowering L(P, mat_of, R, loc, C);
+                    for (int g : s.gates) L.gate(g, false);
                 }
                 ds.op_end = (int32_t)P.ops.size();
                 P.stages.push_back(ds);

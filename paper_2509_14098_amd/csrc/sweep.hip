@@ -35,19 +35,47 @@ __device__ __forceinline__ uint64_t tile_base(const DevPart *__restrict__ P, uin
     return base;
 }
 
-// Load the tile HBM -> LDS.  Pair p covers canonical positions 2p, 2p+1.
-template <int LW>
+// Uniform HBM offsets of the pair rows handled in iteration it: bits of it
+// sit at canonical tile positions LW+1, LW+2, ...
+template <int ITER, int LW>
+__device__ __forceinline__ void row_offsets(const DevPart *__restrict__ P, uint64_t (&g)[ITER])
+{
+    g[0] = 0;
+#pragma unroll
+    for (int it = 1; it < ITER; ++it) g[it] = g[it & (it - 1)] | (1ull << P->tq[LW + 1 + __builtin_ctz(it)]);
+}
+
+// Load the tile HBM -> LDS.  Pair p covers canonical positions 2p, 2p+1 (an
+// aligned 16-byte pair in HBM, since tile position 0 is qubit 0).  A full
+// tile (t = R + LW) issues all of a thread's loads before the LDS writes.
+template <int R, int LW>
 __device__ __forceinline__ void load_tile(const float2 *__restrict__ psi, float2 *lds, const DevPart *__restrict__ P,
                                           uint64_t base, uint32_t tid)
 {
     const int t = P->t;
-    const uint32_t npairs = 1u << (t - 1);
     const int thr_hi = (LW + 1 < t) ? LW + 1 : t;
-    const uint64_t gthr = tile_offset(P, 2u * tid, 1, thr_hi);
+    const uint64_t gthr = base | tile_offset(P, 2u * tid, 1, thr_hi);
+    if (t == R + LW) {
+        constexpr int ITER = 1 << (R - 1);
+        uint64_t g[ITER];
+        row_offsets<ITER, LW>(P, g);
+        float4 v[ITER];
+#pragma unroll
+        for (int it = 0; it < ITER; ++it) v[it] = *reinterpret_cast<const float4 *>(psi + (gthr | g[it]));
+        const uint32_t st = swz(2u * tid);  // swz is linear and leaves bit 0 alone
+#pragma unroll
+        for (int it = 0; it < ITER; ++it) {
+            const uint32_t sc = st ^ swz(2u * (uint32_t)(it << LW));
+            lds[sc] = float2{v[it].x, v[it].y};
+            lds[sc ^ 1u] = float2{v[it].z, v[it].w};
+        }
+        return;
+    }
+    const uint32_t npairs = 1u << (t - 1);
     for (uint32_t p0 = 0; p0 < npairs; p0 += (1u << LW)) {
         const uint32_t p = p0 + tid;
         if (p < npairs) {
-            const uint64_t g = base | gthr | tile_offset(P, 2u * p0, LW + 1, t);
+            const uint64_t g = gthr | tile_offset(P, 2u * p0, LW + 1, t);
             const float4 v = *reinterpret_cast<const float4 *>(psi + g);
             const uint32_t c = 2u * p;
             lds[swz(c)] = float2{v.x, v.y};
@@ -56,18 +84,38 @@ __device__ __forceinline__ void load_tile(const float2 *__restrict__ psi, float2
     }
 }
 
-template <int LW>
+template <int R, int LW>
 __device__ __forceinline__ void store_tile(float2 *__restrict__ psi, float2 *__restrict__ ckpt, const float2 *lds,
                                            const DevPart *__restrict__ P, uint64_t base, uint32_t tid)
 {
     const int t = P->t;
-    const uint32_t npairs = 1u << (t - 1);
     const int thr_hi = (LW + 1 < t) ? LW + 1 : t;
-    const uint64_t gthr = tile_offset(P, 2u * tid, 1, thr_hi);
+    const uint64_t gthr = base | tile_offset(P, 2u * tid, 1, thr_hi);
+    if (t == R + LW) {
+        constexpr int ITER = 1 << (R - 1);
+        uint64_t g[ITER];
+        row_offsets<ITER, LW>(P, g);
+        float4 v[ITER];
+        const uint32_t st = swz(2u * tid);
+#pragma unroll
+        for (int it = 0; it < ITER; ++it) {
+            const uint32_t sc = st ^ swz(2u * (uint32_t)(it << LW));
+            const float2 x = lds[sc], y = lds[sc ^ 1u];
+            v[it] = float4{x.x, x.y, y.x, y.y};
+        }
+#pragma unroll
+        for (int it = 0; it < ITER; ++it) *reinterpret_cast<float4 *>(psi + (gthr | g[it])) = v[it];
+        if (ckpt) {
+#pragma unroll
+            for (int it = 0; it < ITER; ++it) *reinterpret_cast<float4 *>(ckpt + (gthr | g[it])) = v[it];
+        }
+        return;
+    }
+    const uint32_t npairs = 1u << (t - 1);
     for (uint32_t p0 = 0; p0 < npairs; p0 += (1u << LW)) {
         const uint32_t p = p0 + tid;
         if (p < npairs) {
-            const uint64_t g = base | gthr | tile_offset(P, 2u * p0, LW + 1, t);
+            const uint64_t g = gthr | tile_offset(P, 2u * p0, LW + 1, t);
             const uint32_t c = 2u * p;
             const float2 x = lds[swz(c)], y = lds[swz(c + 1)];
             const float4 v{x.x, x.y, y.x, y.y};
@@ -88,10 +136,10 @@ __global__ __launch_bounds__(1 << LW) void sweep_kernel(float2 *__restrict__ psi
     const DevPart *__restrict__ P = parts + pidx;
     const uint32_t tid = threadIdx.x;
     const uint64_t base = tile_base<R, LW>(P, blockIdx.x);
-    load_tile<LW>(psi, lds, P, base, tid);
+    load_tile<R, LW>(psi, lds, P, base, tid);
     __syncthreads();
     run_stages<R, false>(lds, stages, ops, pool, P->stage_begin, P->stage_end, P->t - R, tid, base);
-    store_tile<LW>(psi, ckpt, lds, P, base, tid);
+    store_tile<R, LW>(psi, ckpt, lds, P, base, tid);
 }
 
 // Rotation matrices from theta: cos/sin in float64, rounded to float32.

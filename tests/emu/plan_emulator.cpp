@@ -1,0 +1,104 @@
+// Test-only CPU execution of lowered plans: the host planner builds the plan
+// tables exactly as for the GPU, and the register-level op code (gates.cuh) is
+// run thread by thread, stage by stage, over LDS-like tile buffers.  It checks
+// the lowering (tile and stage layouts, op locations, diagonal folding) on the
+// CPU; it is not reachable from the library's API.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "../../paper_2509_14098_amd/csrc/gates.cuh"
+#include "../../paper_2509_14098_amd/csrc/internal.h"
+
+using namespace qsv;
+
+template <int R, bool DAG>
+static void run_part(const Plan &P, int pidx, std::vector<float2> &psi, const std::vector<float> &pool)
+{
+    const DevPart &D = P.parts[pidx];
+    const int t = D.t, w = t - R;
+    std::vector<float2> lds(size_t(1) << t);
+    for (uint64_t tile = 0; tile < (1ull << D.n_glb); ++tile) {
+        uint64_t base = 0;
+        for (int b = 0; b < D.n_glb; ++b)
+            if ((tile >> b) & 1) base |= 1ull << D.gq[b];
+        auto gidx = [&](uint32_t c) {
+            uint64_t g = base;
+            for (int b = 0; b < t; ++b)
+                if ((c >> b) & 1) g |= 1ull << D.tq[b];
+            return g;
+        };
+        for (uint32_t c = 0; c < (1u << t); ++c) lds[swz(c)] = psi[gidx(c)];
+        const int s0 = DAG ? D.stage_end - 1 : D.stage_begin, s1 = DAG ? D.stage_begin - 1 : D.stage_end;
+        for (int s = s0; s != s1; s += DAG ? -1 : 1) {
+            const DevStage &S = P.stages[s];
+            for (uint32_t tid = 0; tid < (1u << w); ++tid) {
+                uint32_t toff, roff[1 << R];
+                stage_offsets<R>(&S, w, tid, toff, roff);
+                float2 a[1 << R];
+                for (int i = 0; i < (1 << R); ++i) a[i] = lds[toff ^ roff[i]];
+                if (!DAG)
+                    for (int k = S.op_begin; k < S.op_end; ++k) apply_op<R, false>(a, P.ops[k], pool.data(), tid, base);
+                else
+                    for (int k = S.op_end - 1; k >= S.op_begin; --k) apply_op<R, true>(a, P.ops[k], pool.data(), tid, base);
+                for (int i = 0; i < (1 << R); ++i) lds[toff ^ roff[i]] = a[i];
+            }
+        }
+        for (uint32_t c = 0; c < (1u << t); ++c) psi[gidx(c)] = lds[swz(c)];
+    }
+}
+
+// Build a plan with the given shape and run it on |0..0> (inverse = 0) or run
+// its conjugate transpose on the given state (inverse = 1).  Rotation
+// parameters are taken from theta (float64) the way the device forms them.
+extern "C" int emu_run(int n, const qsv_gate *gates, int ng, const double *theta, int n_params, int k, int R, int LW,
+                       int flags, int inverse, float *state)
+{
+    Plan P;
+    P.n = n;
+    P.n_circuits = 1;
+    P.k = std::min(k, n);
+    P.t = std::min(n, R + LW);
+    int need_r = 1;  // the library never picks fewer register qubits than a gate requires
+    for (int g = 0; g < ng; ++g) need_r = std::max(need_r, __builtin_popcountll(classify(gates[g]).req));
+    P.R = std::min(std::max(R, need_r), P.t);
+    P.LW = LW;
+    P.flags = (uint32_t)flags;
+    P.gates.assign(gates, gates + ng);
+    CircuitPlan C;
+    C.g0 = 0;
+    C.g1 = ng;
+    C.theta_off = 0;
+    C.n_params = n_params;
+    P.circ.push_back(C);
+    P.n_params = n_params;
+    build_plan(P);
+    std::vector<float> pool = P.pool;
+    pool.resize(pool.size() + 8, 0.f);
+    for (const ParamGate &g : P.pgates) {  // same formulas as the device's materialisation
+        const double a = theta[g.theta_index], c = std::cos(0.5 * a), s = std::sin(0.5 * a);
+        float *m = pool.data() + g.mat;
+        for (int i = 0; i < 8; ++i) m[i] = 0.f;
+        if (g.kind == QSV_RX) { m[0] = (float)c; m[3] = (float)-s; m[5] = (float)-s; m[6] = (float)c; }
+        else if (g.kind == QSV_RY) { m[0] = (float)c; m[2] = (float)-s; m[4] = (float)s; m[6] = (float)c; }
+        else if (g.kind == QSV_RZ) { m[0] = (float)c; m[1] = (float)-s; m[6] = (float)c; m[7] = (float)s; }
+        else { m[0] = (float)c; m[1] = (float)-s; m[2] = (float)c; m[3] = (float)s; m[4] = (float)c; m[5] = (float)s; m[6] = (float)c; m[7] = (float)-s; }
+    }
+    std::vector<float2> psi(size_t(1) << n);
+    std::memcpy(psi.data(), state, psi.size() * sizeof(float2));
+    const int np = (int)P.parts.size();
+    for (int q = 0; q < np; ++q) {
+        const int p = inverse ? np - 1 - q : q;
+        switch (P.R) {
+        case 1: inverse ? run_part<1, true>(P, p, psi, pool) : run_part<1, false>(P, p, psi, pool); break;
+        case 2: inverse ? run_part<2, true>(P, p, psi, pool) : run_part<2, false>(P, p, psi, pool); break;
+        case 3: inverse ? run_part<3, true>(P, p, psi, pool) : run_part<3, false>(P, p, psi, pool); break;
+        case 4: inverse ? run_part<4, true>(P, p, psi, pool) : run_part<4, false>(P, p, psi, pool); break;
+        default: inverse ? run_part<5, true>(P, p, psi, pool) : run_part<5, false>(P, p, psi, pool); break;
+        }
+    }
+    std::memcpy(state, psi.data(), psi.size() * sizeof(float2));
+    return np;
+}

@@ -65,8 +65,8 @@ def test_partition_matches_oracle_random(seed):
     rng = np.random.default_rng(500 + seed)
     n = int(rng.integers(2, 16))
     k = int(rng.integers(2, n + 1))
-    if n > 13:  # a partition must leave room for at least one fill qubit in a 13-qubit tile
-        k = min(k, 12)
+    if n > 12:  # a partition must leave room for at least one fill qubit in the default 12-qubit tile
+        k = min(k, 11)
     theta = rng.uniform(-3, 3, size=4)
     gates = W.random_circuit(n, int(rng.integers(1, 150)), seed=500 + seed, n_params=4)
     plan = _compare(n, gates, k, theta)

@@ -1,0 +1,84 @@
+"""The lowered plans executed on the CPU (test-only emulation of the kernels'
+register-level op code, tests/emu/) against the complex128 oracle: checks the
+lowering — tile and stage layouts, op locations, the diagonal folding of
+register stages — for every kernel shape without a GPU.  The GPU parity tests
+then check the kernels themselves."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+SRC = os.path.join(HERE, "emu", "plan_emulator.cpp")
+PLANNER = os.path.join(ROOT, "paper_2509_14098_amd", "csrc", "planner.cpp")
+
+
+@pytest.fixture(scope="module")
+def emu(tmp_path_factory):
+    lib = str(tmp_path_factory.mktemp("emu") / "libplanemu.so")
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-I", os.path.join(HERE, "emu", "shim"),
+                           "-o", lib, SRC, PLANNER])
+    L = ctypes.CDLL(lib)
+    V = ctypes.c_void_p
+    L.emu_run.argtypes = [ctypes.c_int, V, ctypes.c_int, V, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                          ctypes.c_int, ctypes.c_int, V]
+
+    def run(n, gates, k, R, LW, theta=None, flags=0, inverse=False, state=None):
+        g = np.ascontiguousarray(gates)
+        th = np.ascontiguousarray(np.zeros(1) if theta is None else theta, dtype=np.float64)
+        st = np.zeros(1 << n, np.complex64)
+        if state is None:
+            st[0] = 1
+        else:
+            st[:] = state
+        L.emu_run(n, g.ctypes.data_as(V), len(g), th.ctypes.data_as(V), 0 if theta is None else len(theta), k, R,
+                  LW, flags, int(inverse), st.ctypes.data_as(V))
+        return st
+    return run
+
+
+SHAPES = [(1, 6), (2, 6), (3, 6), (4, 6), (5, 6), (3, 8), (4, 8), (5, 8), (4, 9), (5, 9), (4, 10)]
+
+
+@pytest.mark.parametrize("R,LW", SHAPES)
+def test_random_circuits_every_shape(emu, R, LW):
+    for n in (2, 5, 9, 13, 15):
+        if n < 2:
+            continue
+        theta = np.random.default_rng(n).uniform(-3, 3, size=4)
+        gates = W.random_circuit(n, 120, seed=40 + n + R, n_params=4)
+        k = min(n, R + LW - 1, 9)
+        out = emu(n, gates, k, R, LW, theta)
+        assert np.max(np.abs(out - oracle.apply(n, gates, theta))) < 1e-5, (n, R, LW)
+
+
+@pytest.mark.parametrize("name,n,gen", [("c1", 12, W.brickwork_c1),
+                                        ("c2-16", 16, lambda: W.brickwork_c2(n=16, layers=12)),
+                                        ("c3-16", 16, lambda: W.brickwork_c3(n=16, layers=12))])
+def test_benchmark_shapes(emu, name, n, gen):
+    gates = gen()
+    ref = oracle.apply(n, gates)
+    for R, LW, k in ((4, 8, 10), (5, 8, 10), (4, 9, 12)):
+        assert np.max(np.abs(emu(n, gates, k, R, LW) - ref)) < 1e-5, (name, R, LW)
+
+
+def test_inverse_walk_returns_to_start(emu):
+    """The conjugate-transpose walk (used by the adjoint) undoes the forward plan."""
+    n = 14
+    theta = np.random.default_rng(3).uniform(-3, 3, size=6)
+    gates = W.random_circuit(n, 200, seed=11, n_params=6)
+    fwd = emu(n, gates, 10, 4, 8, theta)
+    back = emu(n, gates, 10, 4, 8, theta, inverse=True, state=fwd)
+    assert abs(back[0] - 1) < 1e-5 and np.max(np.abs(back[1:])) < 1e-5
+
+
+def test_gate_by_gate_plan(emu):
+    n = 11
+    gates = W.random_circuit(n, 80, seed=5)
+    assert np.max(np.abs(emu(n, gates, 8, 4, 6, flags=1) - oracle.apply(n, gates))) < 1e-5
