@@ -204,7 +204,17 @@ def main():
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 2 GiB device copy 5 times (reference for HBM traffic counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.complex64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        sync()
+        print(json.dumps(dict(copy_bytes_read=8 << 28, copy_bytes_written=8 << 28, launches=5)))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU path is not part of this "
               f"build", file=sys.stderr)

@@ -102,6 +102,7 @@ __global__ __launch_bounds__(1 << LW) void reverse_kernel(const float2 *__restri
             apply_op<R, true>(l, o, pool, tid, base);
         }
         if (active) {
+            asm volatile("" : "+v"(toff));  // recompute the write-back addresses instead of keeping 2^R live
 #pragma unroll
             for (int i = 0; i < NA; ++i) {
                 lds_psi[toff ^ roff[i]] = a[i];

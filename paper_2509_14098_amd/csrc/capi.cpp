@@ -7,6 +7,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -344,12 +345,14 @@ struct TuneChoice {
 };
 static std::map<std::pair<int, size_t>, TuneChoice> g_tune_cache;
 static std::vector<TuneChoice> g_last_tune;
+static std::mutex g_tune_mutex;  // the cache and the last-run record are process-wide
 
 static TuneChoice autotune(qsv_ctx *ctx, int n, const qsv_gate *gates, const std::vector<int64_t> &off, uint32_t flags)
 {
     std::string key((const char *)gates, sizeof(qsv_gate) * (size_t)off.back());
     key += std::to_string(n) + "/" + std::to_string(flags);
     auto ck = std::make_pair(ctx->device, std::hash<std::string>()(key));
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
     auto it = g_tune_cache.find(ck);
     if (it != g_tune_cache.end()) return it->second;
     TuneChoice best{std::min(9, n), 4, 8, -1.0};
@@ -454,6 +457,7 @@ qsv_status qsv_partition(qsv_ctx *ctx, int32_t n_qubits, const qsv_gate *gates, 
 // Candidates timed by the last autotuning run of this process: (k, R, LW, ms) x n.
 int32_t qsv_last_autotune(int32_t *out, int32_t cap)
 {
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
     int32_t n = (int32_t)g_last_tune.size();
     for (int32_t i = 0; out && i < std::min(n, cap); ++i) {
         out[4 * i] = g_last_tune[i].k;

@@ -151,10 +151,14 @@ hipError_t launch_expect(const DevGroup *groups, int n_groups, const DevTerm *te
         return hipGetLastError();
     }
     const int nb = blocks_for(1ull << n, n_blocks);
-    hipLaunchKernelGGL(expect_kernel, dim3(nb, n_groups, (uint32_t)batch), dim3(RED_THREADS), 0, s, groups, terms, n,
-                       psi, partials);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    const int64_t zmax = 65535;  // grid z limit: batches beyond it go in chunks
+    for (int64_t b0 = 0; b0 < batch; b0 += zmax) {
+        const int64_t nz = std::min<int64_t>(zmax, batch - b0);
+        hipLaunchKernelGGL(expect_kernel, dim3(nb, n_groups, (uint32_t)nz), dim3(RED_THREADS), 0, s, groups, terms, n,
+                           psi + ((uint64_t)b0 << n), partials + (uint64_t)b0 * n_groups * nb);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(final_sum_kernel, dim3((uint32_t)batch), dim3(RED_THREADS), 0, s, partials, nb * n_groups, out);
     return hipGetLastError();
 }

@@ -388,6 +388,7 @@ __device__ __forceinline__ void run_stages(float2 *lds, const DevStage *__restri
                     mc = mn;
                 }
             }
+            asm volatile("" : "+v"(toff));  // recompute the write-back addresses instead of keeping 2^R live
 #pragma unroll
             for (int i = 0; i < NA; ++i) lds[toff ^ roff[i]] = a[i];
         }

@@ -139,7 +139,7 @@ def test_c3_reduced_vs_golden(sim, name, gen, k):
     n = int(g["n"])
     gates = gen()
     assert W.circuit_hash(gates, n) == g["circuit_sha256"].item().decode()
-    psi, _ = run(sim, n, gates, k=k)
+    psi, _ = run(sim, n, gates, k=k, tile=(4, 9))
     got = psi[torch.as_tensor(g["idx"], device=psi.device)].cpu().numpy()
     assert np.max(np.abs(got - g["amp"])) <= TOL
     zz = float(sim.expect(W.zz_chain(n), psi, n)[0])
@@ -173,7 +173,7 @@ def test_c3_full_size_properties(sim):
     nrm = float(sim.expect(W.pauli_sum([(1.0, {})]), psi, n)[0])
     assert abs(nrm - 1) < 1e-4
     inv = W.inverse_circuit(gates)
-    run(sim, n, inv, k=12, psi=psi)
+    run(sim, n, inv, k=12, tile=(5, 8), psi=psi)
     assert abs(complex(psi[0].item()) - 1) < 1e-3
     assert float(torch.max(torch.abs(psi[1:]))) < 1e-4
     del psi
