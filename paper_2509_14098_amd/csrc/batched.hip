@@ -23,19 +23,10 @@
 
 namespace qsv {
 
+// The read-only tables (plan and Hamiltonian) are separate restrict kernel
+// arguments: the compiler then knows the kernel's stores cannot change them
+// and fetches ops and matrices with scalar loads.
 struct BatchArgs {
-    const DevPart *parts;
-    const DevStage *stages;
-    const DevOp *ops;
-    const float *pool;
-    const int32_t *order;       // queue position -> circuit
-    const int32_t *circ_part;   // circuit -> its DevPart
-    const int64_t *circ_theta;  // circuit -> first theta index
-    const int64_t *circ_npar;   // circuit -> number of parameters
-    const int32_t *param_off;   // theta index -> grad slots (CSR)
-    const int32_t *param_slots;
-    const DevGroup *groups;
-    const DevTerm *terms;
     int n_groups;
     int n_circuits;
     int n;
@@ -66,7 +57,12 @@ __device__ __forceinline__ void remap(float2 (&v)[1 << R], float2 *lds, bool act
 }
 
 template <int R, int LW>
-__global__ __launch_bounds__(1 << LW) void batched_kernel(BatchArgs A)
+__global__ __launch_bounds__(1 << LW) void batched_kernel(
+    const DevPart *__restrict__ parts, const DevStage *__restrict__ stages, const DevOp *__restrict__ ops,
+    const float *__restrict__ pool, const int32_t *__restrict__ order, const int32_t *__restrict__ circ_part,
+    const int64_t *__restrict__ circ_theta, const int64_t *__restrict__ circ_npar,
+    const int32_t *__restrict__ param_off, const int32_t *__restrict__ param_slots,
+    const DevGroup *__restrict__ groups, const DevTerm *__restrict__ terms, BatchArgs A)
 {
     constexpr int NA = 1 << R, WAVES = (1 << LW) / 64;
     extern __shared__ float2 lds[];
@@ -77,18 +73,18 @@ __global__ __launch_bounds__(1 << LW) void batched_kernel(BatchArgs A)
     while (true) {
         if (tid == 0) s_item = atomicAdd(A.queue, 1);
         __syncthreads();
-        const int item = s_item;
+        const int item = __builtin_amdgcn_readfirstlane(s_item);  // the same for every thread
         __syncthreads();
         if (item >= A.n_circuits) break;
-        const int c = A.order[item];
-        const DevPart *__restrict__ P = A.parts + A.circ_part[c];
+        const int c = order[item];
+        const DevPart *__restrict__ P = parts + circ_part[c];
         const int t = P->t, w = t - R;
         const bool active = tid < (1u << w);
         const uint32_t dim = 1u << t;
         // forward from |0..0>
         for (uint32_t x = tid; x < dim; x += (1u << LW)) lds[swz(x)] = float2{x == 0 ? 1.f : 0.f, 0.f};
         __syncthreads();
-        run_stages<R, false>(lds, A.stages, A.ops, A.pool, P->stage_begin, P->stage_end, w, tid, 0);
+        run_stages<R, false>(lds, stages, ops, pool, P->stage_begin, P->stage_end, w, tid, 0);
         if (A.psi_out) {  // the tile is the whole state and its positions are the qubits in order
             float2 *dst = A.psi_out + (uint64_t)c * dim;
             for (uint32_t x = tid; x < dim; x += (1u << LW)) dst[x] = lds[swz(x)];
@@ -100,7 +96,7 @@ __global__ __launch_bounds__(1 << LW) void batched_kernel(BatchArgs A)
         // lambda = H psi and the energy, in the last stage's layout
         const int s_last = P->stage_end - 1;
         uint32_t toff, roff[NA];
-        stage_offsets<R>(A.stages + s_last, w, tid, toff, roff);
+        stage_offsets<R>(stages + s_last, w, tid, toff, roff);
         float2 a[NA], l[NA];
         double e_part = 0.0;
 #pragma unroll
@@ -113,14 +109,14 @@ __global__ __launch_bounds__(1 << LW) void batched_kernel(BatchArgs A)
                 a[i] = lds[sx];
                 double lr = 0.0, li = 0.0;
                 for (int g = 0; g < A.n_groups; ++g) {
-                    const DevGroup G = A.groups[g];
+                    const DevGroup G = groups[g];
                     const uint32_t y = x ^ (uint32_t)G.x_mask;
                     const float2 py = lds[swz(y)];
                     double wr = 0.0, wi = 0.0;
                     for (int k = G.term_begin; k < G.term_end; ++k) {
-                        const double sg = (__popcll(y & A.terms[k].z_mask) & 1) ? -1.0 : 1.0;
-                        wr += sg * A.terms[k].cre;
-                        wi += sg * A.terms[k].cim;
+                        const double sg = (__popcll(y & terms[k].z_mask) & 1) ? -1.0 : 1.0;
+                        wr += sg * terms[k].cre;
+                        wi += sg * terms[k].cim;
                     }
                     lr += wr * py.x - wi * py.y;
                     li += wr * py.y + wi * py.x;
@@ -141,32 +137,32 @@ __global__ __launch_bounds__(1 << LW) void batched_kernel(BatchArgs A)
         for (int s = s_last; s >= P->stage_begin; --s) {
             if (s != s_last) {  // remap psi, then lambda, from the layout of stage s+1 to that of stage s
                 uint32_t toff2, roff2[NA];
-                stage_offsets<R>(A.stages + s, w, tid, toff2, roff2);
+                stage_offsets<R>(stages + s, w, tid, toff2, roff2);
                 remap<R>(a, lds, active, toff, roff, toff2, roff2);
                 remap<R>(l, lds, active, toff, roff, toff2, roff2);
                 toff = toff2;
 #pragma unroll
                 for (int i = 0; i < NA; ++i) roff[i] = roff2[i];
             }
-            const DevStage *__restrict__ S = A.stages + s;
+            const DevStage *__restrict__ S = stages + s;
             for (int k = S->op_end - 1; k >= S->op_begin; --k) {
-                const DevOp o = A.ops[k];
+                const DevOp o = ops[k];
                 if (o.grad_slot >= 0) {
                     const double v = wave_sum(grad_term<R>(a, l, o, tid, 0));
                     if ((tid & 63) == 0) A.gpart[(int64_t)o.grad_slot * WAVES + wave] = v;
                 }
-                apply_op<R, true>(a, o, A.pool, tid, 0);
-                apply_op<R, true>(l, o, A.pool, tid, 0);
+                apply_op<R, true>(a, o, pool, tid, 0);
+                apply_op<R, true>(l, o, pool, tid, 0);
             }
         }
         // this circuit's gradient entries: slots in slot order, waves in order
         __threadfence_block();
         __syncthreads();
-        const int64_t p0 = A.circ_theta[c], np = A.circ_npar[c];
+        const int64_t p0 = circ_theta[c], np = circ_npar[c];
         for (int64_t p = tid; p < np; p += (1 << LW)) {
             double acc = 0.0;
-            for (int32_t k = A.param_off[p0 + p]; k < A.param_off[p0 + p + 1]; ++k)
-                for (int v = 0; v < WAVES; ++v) acc += A.gpart[(int64_t)A.param_slots[k] * WAVES + v];
+            for (int32_t k = param_off[p0 + p]; k < param_off[p0 + p + 1]; ++k)
+                for (int v = 0; v < WAVES; ++v) acc += A.gpart[(int64_t)param_slots[k] * WAVES + v];
             A.grad[p0 + p] = acc;
         }
         __syncthreads();
@@ -191,18 +187,6 @@ hipError_t launch_batched(const Plan &plan, const DevGroup *groups, int n_groups
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     BatchArgs A;
-    A.parts = plan.d_parts;
-    A.stages = plan.d_stages;
-    A.ops = plan.d_ops;
-    A.pool = plan.d_pool;
-    A.order = plan.d_batch_order;
-    A.circ_part = plan.d_circ_part;
-    A.circ_theta = plan.d_circ_theta;
-    A.circ_npar = plan.d_circ_npar;
-    A.param_off = plan.d_param_off;
-    A.param_slots = plan.d_param_slots;
-    A.groups = groups;
-    A.terms = terms;
     A.n_groups = n_groups;
     A.n_circuits = plan.n_circuits;
     A.n = plan.n;
@@ -220,7 +204,9 @@ hipError_t launch_batched(const Plan &plan, const DevGroup *groups, int n_groups
         attr = true;
     }
     const size_t lds = (size_t)8 << plan.t;
-    hipLaunchKernelGGL((batched_kernel<BATCH_R, BATCH_LW>), dim3(grid), dim3(1 << BATCH_LW), lds, s, A);
+    hipLaunchKernelGGL((batched_kernel<BATCH_R, BATCH_LW>), dim3(grid), dim3(1 << BATCH_LW), lds, s, plan.d_parts,
+                       plan.d_stages, plan.d_ops, plan.d_pool, plan.d_batch_order, plan.d_circ_part,
+                       plan.d_circ_theta, plan.d_circ_npar, plan.d_param_off, plan.d_param_slots, groups, terms, A);
     return hipGetLastError();
 }
 

@@ -33,6 +33,31 @@ __device__ __forceinline__ void on_reg(int j, F &&f)
     }
 }
 
+// A uniform value whose derivation the compiler cannot see.  Op dispatch tests
+// single bits of such values, so each op body becomes a two-way branch that
+// the amplitudes pass through unchanged when skipped; a multi-way switch
+// instead gives every case its own register assignment and costs register
+// copies wherever the cases merge.
+__device__ __forceinline__ uint32_t opaque(uint32_t v)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    v = __builtin_amdgcn_readfirstlane(v);  // op fields are uniform; this states it where the compiler cannot prove it
+    asm("" : "+s"(v));
+#endif
+    return v;
+}
+
+// Call f(IC<J>) for the register slot J whose bit is set in the one-hot
+// (opaque) mask bits.
+template <int R, typename F, int J = 0>
+__device__ __forceinline__ void on_slot(uint32_t bits, F &&f)
+{
+    if constexpr (J < R) {
+        if (bits & (1u << J)) f(IC<J>{});
+        on_slot<R, F, J + 1>(bits, static_cast<F &&>(f));
+    }
+}
+
 __device__ __forceinline__ uint32_t reg_pattern(int j)
 {
     switch (j) {
@@ -59,6 +84,13 @@ struct C2 {
     float r, i;
 };
 
+// Value (0 or 1) of a thread or tile-index qubit for this thread and tile.
+__device__ __forceinline__ uint32_t lane_bit(int32_t loc, uint32_t tid, uint64_t base)
+{
+    const int k = loc & 0x3F;
+    return (loc & LOC_MASK) == LOC_THR ? (tid >> k) & 1u : (uint32_t)(base >> k) & 1u;
+}
+
 // The 8 floats of a 2x2 gate matrix (or 4 diagonal entries), loaded as one
 // scalar block so the next op's matrix can be fetched while this one runs.
 struct M8 {
@@ -84,6 +116,91 @@ __device__ __forceinline__ float2 cmac2(C2 u0, float2 x, C2 u1, float2 y)
     return o;
 }
 
+// In-place updates x <- s x + t and x <- s x - t with s uniform.  Written as
+// instructions whose result is tied to x's register so that an op's outputs
+// stay in the registers its inputs came from: the op dispatch loop then needs
+// no register copies where its cases merge.  (The test emulator compiles the
+// same expressions for the host.)
+__device__ __forceinline__ void fma_ip(float &x, float s, float t)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm("v_fma_f32 %0, %1, %0, %2" : "+v"(x) : "s"(s), "v"(t));
+#else
+    x = s * x + t;
+#endif
+}
+__device__ __forceinline__ void fms_ip(float &x, float s, float t)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm("v_fma_f32 %0, %1, %0, -%2" : "+v"(x) : "s"(s), "v"(t));
+#else
+    x = s * x - t;
+#endif
+}
+
+// x <- s x + t with s per lane
+__device__ __forceinline__ void fma_ipv(float &x, float s, float t)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm("v_fma_f32 %0, %1, %0, %2" : "+v"(x) : "v"(s), "v"(t));
+#else
+    x = s * x + t;
+#endif
+}
+__device__ __forceinline__ void fms_ipv(float &x, float s, float t)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm("v_fma_f32 %0, %1, %0, -%2" : "+v"(x) : "v"(s), "v"(t));
+#else
+    x = s * x - t;
+#endif
+}
+// exchange two registers
+__device__ __forceinline__ void swap_ip(float &x, float &y)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm("v_swap_b32 %0, %1" : "+v"(x), "+v"(y));
+#else
+    const float t = x;
+    x = y;
+    y = t;
+#endif
+}
+// x <- x ^ d (bit pattern), in place
+__device__ __forceinline__ void xor_ip(float &x, uint32_t d)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm("v_xor_b32 %0, %0, %1" : "+v"(x) : "v"(d));
+#else
+    x = __uint_as_float(__float_as_uint(x) ^ d);
+#endif
+}
+// x <- x ^ d with d uniform
+__device__ __forceinline__ void xor_ips(float &x, uint32_t d)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm("v_xor_b32 %0, %1, %0" : "+v"(x) : "s"(d));
+#else
+    x = __uint_as_float(__float_as_uint(x) ^ d);
+#endif
+}
+
+// a <- a d (complex, d per lane), in place
+__device__ __forceinline__ void cmul_ipv(float2 &a, float dr, float di)
+{
+    const float t = a.y * di, u = a.x * di;
+    fms_ipv(a.x, dr, t);
+    fma_ipv(a.y, dr, u);
+}
+
+// a <- a d (complex, d uniform), in place
+__device__ __forceinline__ void cmul_ip(float2 &a, float dr, float di)
+{
+    const float t = a.y * di, u = a.x * di;
+    fms_ip(a.x, dr, t);
+    fma_ip(a.y, dr, u);
+}
+
 __device__ __forceinline__ float2 cmul(float2 a, C2 d)
 {
     return float2{a.x * d.r - a.y * d.i, a.x * d.i + a.y * d.r};
@@ -98,9 +215,16 @@ __device__ __forceinline__ void g_u1(float2 (&a)[1 << R], const float *__restric
 #pragma unroll
     for (int i = 0; i < (1 << R); ++i) {
         if (i & (1 << J)) continue;
-        float2 x = a[i], y = a[i | (1 << J)];
-        a[i] = cmac2(m00, x, m01, y);
-        a[i | (1 << J)] = cmac2(m10, x, m11, y);
+        float2 &x = a[i], &y = a[i | (1 << J)];
+        // every term but the diagonal one first, then the diagonal term in place
+        const float t0 = m01.r * y.x - m00.i * x.y - m01.i * y.y;
+        const float t1 = m01.r * y.y + m00.i * x.x + m01.i * y.x;
+        const float t2 = m10.r * x.x - m10.i * x.y - m11.i * y.y;
+        const float t3 = m10.r * x.y + m10.i * x.x + m11.i * y.x;
+        fma_ip(x.x, m00.r, t0);
+        fma_ip(x.y, m00.r, t1);
+        fma_ip(y.x, m11.r, t2);
+        fma_ip(y.y, m11.r, t3);
     }
 }
 
@@ -108,25 +232,66 @@ __device__ __forceinline__ void g_u1(float2 (&a)[1 << R], const float *__restric
 template <int R, int J, bool DAG>
 __device__ __forceinline__ void g_r1(float2 (&a)[1 << R], const float *__restrict__ m)
 {
-    float m00 = m[0], m01 = m[DAG ? 4 : 2], m10 = m[DAG ? 2 : 4], m11 = m[6];
+    const float m00 = m[0], m01 = m[DAG ? 4 : 2], m10 = m[DAG ? 2 : 4], m11 = m[6];
 #pragma unroll
     for (int i = 0; i < (1 << R); ++i) {
         if (i & (1 << J)) continue;
-        float2 x = a[i], y = a[i | (1 << J)];
-        a[i] = float2{m00 * x.x + m01 * y.x, m00 * x.y + m01 * y.y};
-        a[i | (1 << J)] = float2{m10 * x.x + m11 * y.x, m10 * x.y + m11 * y.y};
+        float2 &x = a[i], &y = a[i | (1 << J)];
+        const float tx = m01 * y.x, ty = m01 * y.y, ux = m10 * x.x, uy = m10 * x.y;
+        fma_ip(x.x, m00, tx);
+        fma_ip(x.y, m00, ty);
+        fma_ip(y.x, m11, ux);
+        fma_ip(y.y, m11, uy);
     }
 }
 
-// Diagonal 2x2 on a qubit anywhere (pattern p).
+// Diagonal 2x2 on a qubit anywhere (location loc).
 template <int R, bool DAG>
-__device__ __forceinline__ void g_d1(float2 (&a)[1 << R], const float *__restrict__ m, uint32_t p)
+__device__ __forceinline__ void g_d1(float2 (&a)[1 << R], const float *__restrict__ m, int32_t loc, uint32_t tid,
+                                     uint64_t base)
 {
-    C2 d0 = ld2(m, 0, DAG), d1 = ld2(m, 3, DAG);
+    const C2 d0 = ld2(m, 0, DAG), d1 = ld2(m, 3, DAG);
+    if ((loc & LOC_MASK) == LOC_REG) {
+        on_slot<R>(opaque(1u << (loc & 0x3F)), [&](auto Jc) __attribute__((always_inline)) {
+            constexpr int J = std::decay_t<decltype(Jc)>::value;
+#pragma unroll
+            for (int i = 0; i < (1 << R); ++i) {
+                const C2 d = (i >> J) & 1 ? d1 : d0;
+                cmul_ip(a[i], d.r, d.i);
+            }
+        });
+    } else {  // one factor per thread
+        const bool s = lane_bit(loc, tid, base);
+        const float dr = s ? d1.r : d0.r, di = s ? d1.i : d0.i;
+#pragma unroll
+        for (int i = 0; i < (1 << R); ++i) cmul_ipv(a[i], dr, di);
+    }
+}
+
+// Real rotation [[c00, c01], [c10, c11]] on register slot J (transposed for DAG).
+template <int R, int J, bool DAG>
+__device__ __forceinline__ void g_rot(float2 (&a)[1 << R], float c00, float c01, float c10, float c11)
+{
+    const float m01 = DAG ? c10 : c01, m10 = DAG ? c01 : c10;
 #pragma unroll
     for (int i = 0; i < (1 << R); ++i) {
-        bool s = (p >> i) & 1u;
-        a[i] = cmul(a[i], C2{s ? d1.r : d0.r, s ? d1.i : d0.i});
+        if (i & (1 << J)) continue;
+        float2 &x = a[i], &y = a[i | (1 << J)];
+        const float tx = m01 * y.x, ty = m01 * y.y, ux = m10 * x.x, uy = m10 * x.y;
+        fma_ip(x.x, c00, tx);
+        fma_ip(x.y, c00, ty);
+        fma_ip(y.x, c11, ux);
+        fma_ip(y.y, c11, uy);
+    }
+}
+
+// Rotations on the register slots in mask (slot J's 4 floats at r + 4 J).
+template <int R, bool DAG, int J = 0>
+__device__ __forceinline__ void g_rot_layer(float2 (&a)[1 << R], const float *__restrict__ r, uint32_t mask)
+{
+    if constexpr (J < R) {
+        if ((mask >> J) & 1u) g_rot<R, J, DAG>(a, r[4 * J], r[4 * J + 1], r[4 * J + 2], r[4 * J + 3]);
+        g_rot_layer<R, DAG, J + 1>(a, r, mask);
     }
 }
 
@@ -135,16 +300,55 @@ template <int R, bool DAG>
 __device__ __forceinline__ void g_dreg(float2 (&a)[1 << R], const float *__restrict__ d)
 {
 #pragma unroll
-    for (int i = 0; i < (1 << R); ++i) a[i] = cmul(a[i], C2{d[2 * i], DAG ? -d[2 * i + 1] : d[2 * i + 1]});
+    for (int i = 0; i < (1 << R); ++i) cmul_ip(a[i], d[2 * i], DAG ? -d[2 * i + 1] : d[2 * i + 1]);
 }
 
-// -1 where both qubits are 1 (pattern p = pa & pb).
-template <int R>
-__device__ __forceinline__ void g_cz(float2 (&a)[1 << R], uint32_t p)
+// Layer op: register diagonal then rotations (the conjugate transpose reverses
+// the order).  Straight-line code, so consecutive layers run without the
+// register copies a multi-way dispatch costs.
+template <int R, bool DAG>
+__device__ __forceinline__ void g_layer(float2 (&a)[1 << R], const float *__restrict__ p, uint32_t mask)
 {
+    if (!DAG) g_dreg<R, false>(a, p);
+    g_rot_layer<R, DAG>(a, p + 2 * (1 << R), mask);
+    if (DAG) g_dreg<R, true>(a, p);
+}
+
+// -1 where both qubits (locations la, lb) are 1: sign-bit flips.
+template <int R>
+__device__ __forceinline__ void g_cz(float2 (&a)[1 << R], int32_t la, int32_t lb, uint32_t tid, uint64_t base)
+{
+    if ((la & LOC_MASK) != LOC_REG) {  // a register qubit, if any, in la
+        const int32_t t = la;
+        la = lb;
+        lb = t;
+    }
+    if ((la & LOC_MASK) != LOC_REG) {  // neither in registers: one sign per thread
+        const uint32_t sg = (lane_bit(la, tid, base) & lane_bit(lb, tid, base)) << 31;
 #pragma unroll
-    for (int i = 0; i < (1 << R); ++i) {
-        if ((p >> i) & 1u) a[i] = float2{-a[i].x, -a[i].y};
+        for (int i = 0; i < (1 << R); ++i) {
+            xor_ip(a[i].x, sg);
+            xor_ip(a[i].y, sg);
+        }
+    } else if ((lb & LOC_MASK) != LOC_REG) {  // register slot and thread qubit
+        const uint32_t sg = lane_bit(lb, tid, base) << 31;
+        on_slot<R>(opaque(1u << (la & 0x3F)), [&](auto Jc) __attribute__((always_inline)) {
+            constexpr int J = std::decay_t<decltype(Jc)>::value;
+#pragma unroll
+            for (int i = 0; i < (1 << R); ++i) {
+                if (!((i >> J) & 1)) continue;
+                xor_ip(a[i].x, sg);
+                xor_ip(a[i].y, sg);
+            }
+        });
+    } else {  // both in registers
+        const uint32_t p = reg_pattern(la & 0x3F) & reg_pattern(lb & 0x3F);
+#pragma unroll
+        for (int i = 0; i < (1 << R); ++i) {
+            const uint32_t sg = ((p >> i) & 1u) << 31;
+            xor_ips(a[i].x, sg);
+            xor_ips(a[i].y, sg);
+        }
     }
 }
 
@@ -158,21 +362,36 @@ __device__ __forceinline__ void g_d2(float2 (&a)[1 << R], const float *__restric
         bool sa = (pa >> i) & 1u, sb = (pb >> i) & 1u;
         C2 lo{sa ? d1.r : d0.r, sa ? d1.i : d0.i};
         C2 hi{sa ? d3.r : d2.r, sa ? d3.i : d2.i};
-        a[i] = cmul(a[i], C2{sb ? hi.r : lo.r, sb ? hi.i : lo.i});
+        cmul_ipv(a[i], sb ? hi.r : lo.r, sb ? hi.i : lo.i);
     }
 }
 
-// X on register slot J where the control pattern pc is 1.
+// X on register slot J controlled by register slot C: a fixed permutation.
+template <int R, int C, int J>
+__device__ __forceinline__ void g_cx_reg(float2 (&a)[1 << R])
+{
+#pragma unroll
+    for (int i = 0; i < (1 << R); ++i) {
+        if ((i & (1 << J)) || !(i & (1 << C))) continue;
+        swap_ip(a[i].x, a[i | (1 << J)].x);
+        swap_ip(a[i].y, a[i | (1 << J)].y);
+    }
+}
+
+// X on register slot J where the thread's control bit is 1 (mask m: all ones or zero).
 template <int R, int J>
-__device__ __forceinline__ void g_cx(float2 (&a)[1 << R], uint32_t pc)
+__device__ __forceinline__ void g_cx_lane(float2 (&a)[1 << R], uint32_t m)
 {
 #pragma unroll
     for (int i = 0; i < (1 << R); ++i) {
         if (i & (1 << J)) continue;
-        bool s = (pc >> i) & 1u;
-        float2 x = a[i], y = a[i | (1 << J)];
-        a[i] = s ? y : x;
-        a[i | (1 << J)] = s ? x : y;
+        float2 &x = a[i], &y = a[i | (1 << J)];
+        const uint32_t dr = (__float_as_uint(x.x) ^ __float_as_uint(y.x)) & m;
+        const uint32_t di = (__float_as_uint(x.y) ^ __float_as_uint(y.y)) & m;
+        xor_ip(x.x, dr);
+        xor_ip(y.x, dr);
+        xor_ip(x.y, di);
+        xor_ip(y.y, di);
     }
 }
 
@@ -221,59 +440,66 @@ __device__ __forceinline__ void g_swap(float2 (&a)[1 << R])
 #pragma unroll
     for (int i = 0; i < (1 << R); ++i) {
         if (i & ((1 << JA) | (1 << JB))) continue;
-        float2 t = a[i | (1 << JA)];
-        a[i | (1 << JA)] = a[i | (1 << JB)];
-        a[i | (1 << JB)] = t;
+        swap_ip(a[i | (1 << JA)].x, a[i | (1 << JB)].x);
+        swap_ip(a[i | (1 << JA)].y, a[i | (1 << JB)].y);
     }
 }
 
 // Apply one op (or its conjugate transpose) to a thread's amplitudes.
-// mm holds the op's 8 leading matrix floats (load_m8); dense 4x4 ops read the
-// rest from the pool.
+// mm holds the op's 8 leading matrix floats (load_m8); layer, register
+// diagonal and dense 4x4 ops read theirs from the pool.  The op kind and the
+// register slots are tested bit by bit on opaque one-hot masks (see opaque()).
 template <int R, bool DAG>
 __device__ __forceinline__ void apply_op(float2 (&a)[1 << R], const DevOp &o, const M8 &mm,
                                          const float *__restrict__ pool, uint32_t tid, uint64_t base)
 {
     const float *m = mm.v;
     const float *__restrict__ m32 = pool + (o.mat < 0 ? 0 : o.mat);
-    switch (o.kind) {
-    case OP_U1: on_reg<R>(o.a & 0x3F, [&](auto J) __attribute__((always_inline)) { g_u1<R, std::decay_t<decltype(J)>::value, DAG>(a, m); }); break;
-    case OP_R1: on_reg<R>(o.a & 0x3F, [&](auto J) __attribute__((always_inline)) { g_r1<R, std::decay_t<decltype(J)>::value, DAG>(a, m); }); break;
-    case OP_D1: g_d1<R, DAG>(a, m, loc_pattern(o.a, tid, base)); break;
-    case OP_DREG: g_dreg<R, DAG>(a, m32); break;
-    case OP_CZ: g_cz<R>(a, loc_pattern(o.a, tid, base) & loc_pattern(o.b, tid, base)); break;
-    case OP_D2: g_d2<R, DAG>(a, m, loc_pattern(o.a, tid, base), loc_pattern(o.b, tid, base)); break;
-    case OP_CX: {
-        uint32_t pc = loc_pattern(o.a, tid, base);
-        on_reg<R>(o.b & 0x3F, [&](auto J) __attribute__((always_inline)) { g_cx<R, std::decay_t<decltype(J)>::value>(a, pc); });
-        break;
+    const uint32_t kb = opaque(1u << o.kind);
+    const uint32_t ja = opaque(1u << (o.a & 0x3F)), jb = opaque(1u << (o.b & 0x3F));
+    if (kb & (1u << OP_LAYER)) g_layer<R, DAG>(a, m32, (uint32_t)o.a);
+    if (kb & (1u << OP_DREG)) g_dreg<R, DAG>(a, m32);
+    if (kb & (1u << OP_U1))
+        on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { g_u1<R, std::decay_t<decltype(J)>::value, DAG>(a, m); });
+    if (kb & (1u << OP_R1))
+        on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { g_r1<R, std::decay_t<decltype(J)>::value, DAG>(a, m); });
+    if (kb & (1u << OP_CZ)) g_cz<R>(a, o.a, o.b, tid, base);
+    if (kb & (1u << OP_CX)) {
+        if ((o.a & LOC_MASK) == LOC_REG) {
+            on_slot<R>(ja, [&](auto C) __attribute__((always_inline)) {
+                on_slot<R>(jb, [&](auto J) __attribute__((always_inline)) {
+                    if constexpr (std::decay_t<decltype(C)>::value != std::decay_t<decltype(J)>::value)
+                        g_cx_reg<R, std::decay_t<decltype(C)>::value, std::decay_t<decltype(J)>::value>(a);
+                });
+            });
+        } else {
+            const uint32_t mk = 0u - lane_bit(o.a, tid, base);
+            on_slot<R>(jb, [&](auto J) __attribute__((always_inline)) { g_cx_lane<R, std::decay_t<decltype(J)>::value>(a, mk); });
+        }
     }
-    case OP_CU: {
-        uint32_t pc = loc_pattern(o.a, tid, base);
-        on_reg<R>(o.b & 0x3F, [&](auto J) __attribute__((always_inline)) { g_cu<R, std::decay_t<decltype(J)>::value, DAG>(a, m, pc); });
-        break;
+    if (kb & (1u << OP_D1)) g_d1<R, DAG>(a, m, o.a, tid, base);
+    if (kb & (1u << OP_D2)) g_d2<R, DAG>(a, m, loc_pattern(o.a, tid, base), loc_pattern(o.b, tid, base));
+    if (kb & (1u << OP_CU)) {
+        const uint32_t pc = loc_pattern(o.a, tid, base);
+        on_slot<R>(jb, [&](auto J) __attribute__((always_inline)) { g_cu<R, std::decay_t<decltype(J)>::value, DAG>(a, m, pc); });
     }
-    case OP_U2:
-        if constexpr (R >= 2) {
-            on_reg<R>(o.a & 0x3F, [&](auto JA) __attribute__((always_inline)) {
-                on_reg<R>(o.b & 0x3F, [&](auto JB) __attribute__((always_inline)) {
+    if constexpr (R >= 2) {
+        if (kb & (1u << OP_U2)) {
+            on_slot<R>(ja, [&](auto JA) __attribute__((always_inline)) {
+                on_slot<R>(jb, [&](auto JB) __attribute__((always_inline)) {
                     if constexpr (std::decay_t<decltype(JA)>::value != std::decay_t<decltype(JB)>::value)
                         g_u2<R, std::decay_t<decltype(JA)>::value, std::decay_t<decltype(JB)>::value, DAG>(a, m32);
                 });
             });
         }
-        break;
-    case OP_SWAP:
-        if constexpr (R >= 2) {
-            on_reg<R>(o.a & 0x3F, [&](auto JA) __attribute__((always_inline)) {
-                on_reg<R>(o.b & 0x3F, [&](auto JB) __attribute__((always_inline)) {
+        if (kb & (1u << OP_SWAP)) {
+            on_slot<R>(ja, [&](auto JA) __attribute__((always_inline)) {
+                on_slot<R>(jb, [&](auto JB) __attribute__((always_inline)) {
                     if constexpr (std::decay_t<decltype(JA)>::value != std::decay_t<decltype(JB)>::value)
                         g_swap<R, std::decay_t<decltype(JA)>::value, std::decay_t<decltype(JB)>::value>(a);
                 });
             });
         }
-        break;
-    default: break;
     }
 }
 
@@ -375,19 +601,7 @@ __device__ __forceinline__ void run_stages(float2 *lds, const DevStage *__restri
             float2 a[NA];
 #pragma unroll
             for (int i = 0; i < NA; ++i) a[i] = lds[toff ^ roff[i]];
-            const int k0 = S->op_begin, k1 = S->op_end;
-            if (k0 < k1) {  // the next op and its matrix are fetched while the current one runs
-                DevOp cur = ops[k0];
-                M8 mc = load_m8(pool, cur.mat);
-                for (int k = k0; k < k1; ++k) {
-                    const int kn = k + 1 < k1 ? k + 1 : k;
-                    const DevOp nxt = ops[kn];
-                    const M8 mn = load_m8(pool, nxt.mat);
-                    apply_op<R, DAG>(a, cur, mc, pool, tid, base);
-                    cur = nxt;
-                    mc = mn;
-                }
-            }
+            for (int k = S->op_begin; k < S->op_end; ++k) apply_op<R, DAG>(a, ops[k], pool, tid, base);
             asm volatile("" : "+v"(toff));  // recompute the write-back addresses instead of keeping 2^R live
 #pragma unroll
             for (int i = 0; i < NA; ++i) lds[toff ^ roff[i]] = a[i];

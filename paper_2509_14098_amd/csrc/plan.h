@@ -29,6 +29,7 @@ enum OpKind : uint8_t {
     OP_U2 = 8,   // dense 4x4 on two register qubits
     OP_SWAP = 9, // exchange of two register qubits
     OP_DREG = 10, // diagonal over the register index: 2^R complex entries, same for every thread
+    OP_LAYER = 11, // register diagonal, then real rotations on every register slot (identity where unused)
 };
 
 // Location of a qubit in a stage layout: register slot, thread-id bit, or a
@@ -74,6 +75,8 @@ struct DevPart {
 
 // Matrix pool layout: a 2x2 gate takes 8 floats (row-major re,im), a 4x4
 // gate 32 floats (local index j = b(q0) + 2 b(q1)), a register diagonal 2^R
-// complex entries; every entry starts at a multiple of 8 floats.
+// complex entries; every entry starts at a multiple of 8 floats.  OP_LAYER:
+// 2^R complex diagonal entries, then 4 floats (c00, c01, c10, c11) for every
+// register slot j at 4 j (the identity where slot j has no rotation).
 
 }  // namespace qsv

@@ -13,6 +13,7 @@
 #include <array>
 #include <cstring>
 #include <functional>
+#include <set>
 #include <stdexcept>
 
 #include "internal.h"
@@ -426,7 +427,7 @@ struct StageLowering {
         rots.clear();
         rot_mask = 0;
     }
-    // emit Dpre and the rotations; Dpost becomes the new pending Dpre
+    // emit Dpre and the rotations as one layer op; Dpost becomes the new pending Dpre
     void flush_rots(int gate)
     {
         if (rots.empty()) {
@@ -434,8 +435,27 @@ struct StageLowering {
             post = Diag(NA);
             return;
         }
-        emit_diag(pre, gate);
-        emit_rots(gate);
+        DevOp o = base_op(OP_LAYER, gate);
+        o.mat = (int32_t)P.pool.size();
+        for (auto &v : pre.d) {
+            P.pool.push_back((float)v.real());
+            P.pool.push_back((float)v.imag());
+        }
+        uint32_t mask = 0;
+        const size_t rbase = P.pool.size();
+        for (int j = 0; j < R; ++j) {  // identity on slots without a rotation
+            const float id[4] = {1.f, 0.f, 0.f, 1.f};
+            P.pool.insert(P.pool.end(), id, id + 4);
+        }
+        for (auto &r : rots) {
+            mask |= 1u << r.first;
+            for (int k = 0; k < 4; ++k) P.pool[rbase + 4 * r.first + k] = (float)r.second[k];
+        }
+        while (P.pool.size() % 8) P.pool.push_back(0.f);
+        o.a = (int32_t)mask;
+        add(o, 6.0 * rots.size() + (pre.identity() ? 0.0 : 6.0));
+        rots.clear();
+        rot_mask = 0;
         pre = post;
         post = Diag(NA);
     }
@@ -470,6 +490,28 @@ struct StageLowering {
         if ((need_reg_a && !is_reg(o.a)) || (need_reg_b && !is_reg(o.b)))
             throw std::logic_error("required qubit not in registers");
         add(o, m.flops);
+    }
+    // True if folding gate g now neither closes the pending block nor emits
+    // it: the condition under which gate() below only extends the block.
+    bool absorbs(int g) const
+    {
+        const GateMeta &m = meta[g];
+        const bool pending = !rots.empty() || !pre.identity() || !post.identity();
+        if (m.param) return !pending;
+        if (m.op == OP_D1 || m.op == OP_D2 || m.op == OP_CZ) {
+            const int32_t la = loc(m.q[0]), lb = m.nq == 2 ? loc(m.q[1]) : LOC_REG;
+            if (is_reg(la) && is_reg(lb)) return true;
+            uint32_t regs = (is_reg(la) ? 1u << (la & 0x3F) : 0u) | (m.nq == 2 && is_reg(lb) ? 1u << (lb & 0x3F) : 0u);
+            return (regs & rot_mask) == 0;
+        }
+        if ((m.op == OP_U1 || m.op == OP_R1) && is_reg(loc(m.q[0]))) {
+            const int j = loc(m.q[0]) & 0x3F;
+            cd d1a, d1b, d2b;
+            double c, sn;
+            if (split_unitary(m.m, d1a, d1b, c, sn, d2b)) return !((rot_mask >> j) & 1u) && !post.depends_on(j);
+        }
+        if ((m.op == OP_CX || m.op == OP_SWAP) && is_reg(loc(m.q[0])) && is_reg(loc(m.q[1]))) return rots.empty();
+        return !pending;
     }
     void gate(int g, bool fold)
     {
@@ -539,12 +581,55 @@ struct StageLowering {
     }
 };
 
+// Lower a stage's gates with folding, in a dependency-respecting order chosen
+// so that blocks stay open: among the gates whose predecessors (earlier gates
+// on a shared qubit) are done, the first one the pending block absorbs is
+// taken, else the first one.  Gates on disjoint qubits commute, so every such
+// order gives the same unitary.  Returns the order used.
+std::vector<int> fold_order(const std::vector<GateMeta> &meta, const std::vector<int> &gates, StageLowering &L)
+{
+    const int N = (int)gates.size();
+    std::vector<std::vector<int>> succ(N);
+    std::vector<int> npred(N, 0);
+    int last[64];
+    std::fill(last, last + 64, -1);
+    for (int i = 0; i < N; ++i) {
+        uint64_t qm = meta[gates[i]].qmask;
+        std::vector<int> pr;
+        while (qm) {
+            const int q = __builtin_ctzll(qm);
+            qm &= qm - 1;
+            if (last[q] >= 0 && std::find(pr.begin(), pr.end(), last[q]) == pr.end()) pr.push_back(last[q]);
+            last[q] = i;
+        }
+        for (int p : pr) succ[p].push_back(i);
+        npred[i] = (int)pr.size();
+    }
+    std::set<int> ready;
+    for (int i = 0; i < N; ++i)
+        if (!npred[i]) ready.insert(i);
+    std::vector<int> order;
+    order.reserve(N);
+    while (!ready.empty()) {
+        int pick = *ready.begin();
+        for (int i : ready)
+            if (L.absorbs(gates[i])) { pick = i; break; }
+        ready.erase(pick);
+        L.gate(gates[pick], true);
+        order.push_back(gates[pick]);
+        for (int v : succ[pick])
+            if (--npred[v] == 0) ready.insert(v);
+    }
+    return order;
+}
+
 // VALU instructions per amplitude of an op kind (for choosing a lowering).
 double op_cost(int kind)
 {
     switch (kind) {
     case OP_U1: return 8;
     case OP_R1: case OP_D1: case OP_D2: case OP_DREG: return 4;
+    case OP_LAYER: return 4;  // per rotation or diagonal; op_cost_of() counts them
     case OP_CU: return 9;
     case OP_U2: return 16;
     default: return 1;  // CX, CZ, SWAP: selects and moves
@@ -649,12 +734,16 @@ void build_plan(Plan &P)
                 const size_t ops0 = P.ops.size(), pool0 = P.pool.size(), grad0 = P.grad_param.size();
                 const double flops0 = P.flops;
                 double plain_cost = 0, folded_cost = 0;
-                for (int g : s.gates) plain_cost += op_cost(P.meta[g].op);
+                for (int g : s.gates) plain_cost += op_cost(P.meta[g].op) + 6;  // + dispatch
                 {
                     StageLowering L(P, mat_of, R, loc, C);
-                    for (int g : s.gates) L.gate(g, true);
+                    s.gates = fold_order(P.meta, s.gates, L);
                     L.flush_all(s.gates.empty() ? -1 : s.gates.back());
-                    for (size_t k = ops0; k < P.ops.size(); ++k) folded_cost += op_cost(P.ops[k].kind);
+                    for (size_t k = ops0; k < P.ops.size(); ++k) {
+                        const DevOp &o = P.ops[k];
+                        // a layer op always runs R rotations and the diagonal but needs no dispatch
+                        folded_cost += o.kind == OP_LAYER ? 4.0 * (R + 1) : op_cost(o.kind) + 6;
+                    }
                 }
                 if (folded_cost >= plain_cost) {
                     P.ops.resize(ops0);

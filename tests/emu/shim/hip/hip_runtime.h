@@ -16,3 +16,6 @@ struct float4 {
 inline double __shfl_xor(double v, int, int) { return v; }
 inline void __syncthreads() {}
 inline int __popcll(unsigned long long v) { return __builtin_popcountll(v); }
+#include <cstring>
+inline uint32_t __float_as_uint(float f) { uint32_t u; std::memcpy(&u, &f, 4); return u; }
+inline float __uint_as_float(uint32_t u) { float f; std::memcpy(&f, &u, 4); return f; }
