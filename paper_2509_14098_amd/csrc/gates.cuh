@@ -166,6 +166,16 @@ __device__ __forceinline__ void swap_ip(float &x, float &y)
     y = t;
 #endif
 }
+// x <- x + s y with s uniform, in place
+__device__ __forceinline__ void fmac_ip(float &x, float s, float y)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm("v_fmac_f32 %0, %1, %2" : "+v"(x) : "s"(s), "v"(y));
+#else
+    x = s * y + x;
+#endif
+}
+
 // x <- x ^ d (bit pattern), in place
 __device__ __forceinline__ void xor_ip(float &x, uint32_t d)
 {
@@ -245,52 +255,59 @@ __device__ __forceinline__ void g_r1(float2 (&a)[1 << R], const float *__restric
     }
 }
 
-// Diagonal 2x2 on a qubit anywhere (location loc).
-template <int R, bool DAG>
-__device__ __forceinline__ void g_d1(float2 (&a)[1 << R], const float *__restrict__ m, int32_t loc, uint32_t tid,
-                                     uint64_t base)
+// Diagonal 2x2 on register slot J.
+template <int R, int J, bool DAG>
+__device__ __forceinline__ void g_d1(float2 (&a)[1 << R], const float *__restrict__ m)
 {
     const C2 d0 = ld2(m, 0, DAG), d1 = ld2(m, 3, DAG);
-    if ((loc & LOC_MASK) == LOC_REG) {
-        on_slot<R>(opaque(1u << (loc & 0x3F)), [&](auto Jc) __attribute__((always_inline)) {
-            constexpr int J = std::decay_t<decltype(Jc)>::value;
 #pragma unroll
-            for (int i = 0; i < (1 << R); ++i) {
-                const C2 d = (i >> J) & 1 ? d1 : d0;
-                cmul_ip(a[i], d.r, d.i);
-            }
-        });
-    } else {  // one factor per thread
-        const bool s = lane_bit(loc, tid, base);
-        const float dr = s ? d1.r : d0.r, di = s ? d1.i : d0.i;
-#pragma unroll
-        for (int i = 0; i < (1 << R); ++i) cmul_ipv(a[i], dr, di);
+    for (int i = 0; i < (1 << R); ++i) {
+        const C2 d = (i >> J) & 1 ? d1 : d0;
+        cmul_ip(a[i], d.r, d.i);
     }
 }
 
-// Real rotation [[c00, c01], [c10, c11]] on register slot J (transposed for DAG).
-template <int R, int J, bool DAG>
-__device__ __forceinline__ void g_rot(float2 (&a)[1 << R], float c00, float c01, float c10, float c11)
+// Diagonal 2x2 on a thread or tile-index qubit whose value here is bit: one
+// factor for all of this thread's amplitudes.
+template <int R, bool DAG>
+__device__ __forceinline__ void g_d1_lane(float2 (&a)[1 << R], const float *__restrict__ m, uint32_t bit)
 {
-    const float m01 = DAG ? c10 : c01, m10 = DAG ? c01 : c10;
+    const C2 d0 = ld2(m, 0, DAG), d1 = ld2(m, 3, DAG);
+    const float dr = bit ? d1.r : d0.r, di = bit ? d1.i : d0.i;
+#pragma unroll
+    for (int i = 0; i < (1 << R); ++i) cmul_ipv(a[i], dr, di);
+}
+
+// Rotation [[c, -s], [s, c]] with c >= 0 on register slot J as three shears
+// (x += t y; y += s x; x += t y with t = -s / (1 + c)): three in-place
+// multiply-adds per pair component, |t| <= 1.  The conjugate transpose is the
+// rotation by the opposite angle: (t, s) -> (-t, -s).
+template <int R, int J, bool DAG>
+__device__ __forceinline__ void g_rot(float2 (&a)[1 << R], float t, float sn)
+{
+    if (DAG) {
+        t = -t;
+        sn = -sn;
+    }
 #pragma unroll
     for (int i = 0; i < (1 << R); ++i) {
         if (i & (1 << J)) continue;
         float2 &x = a[i], &y = a[i | (1 << J)];
-        const float tx = m01 * y.x, ty = m01 * y.y, ux = m10 * x.x, uy = m10 * x.y;
-        fma_ip(x.x, c00, tx);
-        fma_ip(x.y, c00, ty);
-        fma_ip(y.x, c11, ux);
-        fma_ip(y.y, c11, uy);
+        fmac_ip(x.x, t, y.x);
+        fmac_ip(x.y, t, y.y);
+        fmac_ip(y.x, sn, x.x);
+        fmac_ip(y.y, sn, x.y);
+        fmac_ip(x.x, t, y.x);
+        fmac_ip(x.y, t, y.y);
     }
 }
 
-// Rotations on the register slots in mask (slot J's 4 floats at r + 4 J).
+// Rotations on the register slots in mask (slot J's (t, s) at r + 2 J).
 template <int R, bool DAG, int J = 0>
 __device__ __forceinline__ void g_rot_layer(float2 (&a)[1 << R], const float *__restrict__ r, uint32_t mask)
 {
     if constexpr (J < R) {
-        if ((mask >> J) & 1u) g_rot<R, J, DAG>(a, r[4 * J], r[4 * J + 1], r[4 * J + 2], r[4 * J + 3]);
+        if ((mask >> J) & 1u) g_rot<R, J, DAG>(a, r[2 * J], r[2 * J + 1]);
         g_rot_layer<R, DAG, J + 1>(a, r, mask);
     }
 }
@@ -314,41 +331,39 @@ __device__ __forceinline__ void g_layer(float2 (&a)[1 << R], const float *__rest
     if (DAG) g_dreg<R, true>(a, p);
 }
 
-// -1 where both qubits (locations la, lb) are 1: sign-bit flips.
+// CZ as sign-bit flips.  Both qubits in register slots: the uniform pattern p
+// (bit i set where both are 1).
 template <int R>
-__device__ __forceinline__ void g_cz(float2 (&a)[1 << R], int32_t la, int32_t lb, uint32_t tid, uint64_t base)
+__device__ __forceinline__ void g_cz(float2 (&a)[1 << R], uint32_t p)
 {
-    if ((la & LOC_MASK) != LOC_REG) {  // a register qubit, if any, in la
-        const int32_t t = la;
-        la = lb;
-        lb = t;
+#pragma unroll
+    for (int i = 0; i < (1 << R); ++i) {
+        const uint32_t sg = ((p >> i) & 1u) << 31;
+        xor_ips(a[i].x, sg);
+        xor_ips(a[i].y, sg);
     }
-    if ((la & LOC_MASK) != LOC_REG) {  // neither in registers: one sign per thread
-        const uint32_t sg = (lane_bit(la, tid, base) & lane_bit(lb, tid, base)) << 31;
+}
+
+// Register slot J and a thread or tile-index qubit (sign bit sg: that qubit's value << 31).
+template <int R, int J>
+__device__ __forceinline__ void g_cz_rt(float2 (&a)[1 << R], uint32_t sg)
+{
 #pragma unroll
-        for (int i = 0; i < (1 << R); ++i) {
-            xor_ip(a[i].x, sg);
-            xor_ip(a[i].y, sg);
-        }
-    } else if ((lb & LOC_MASK) != LOC_REG) {  // register slot and thread qubit
-        const uint32_t sg = lane_bit(lb, tid, base) << 31;
-        on_slot<R>(opaque(1u << (la & 0x3F)), [&](auto Jc) __attribute__((always_inline)) {
-            constexpr int J = std::decay_t<decltype(Jc)>::value;
+    for (int i = 0; i < (1 << R); ++i) {
+        if (!((i >> J) & 1)) continue;
+        xor_ip(a[i].x, sg);
+        xor_ip(a[i].y, sg);
+    }
+}
+
+// Two thread or tile-index qubits: one sign for all of this thread's amplitudes.
+template <int R>
+__device__ __forceinline__ void g_cz_tt(float2 (&a)[1 << R], uint32_t sg)
+{
 #pragma unroll
-            for (int i = 0; i < (1 << R); ++i) {
-                if (!((i >> J) & 1)) continue;
-                xor_ip(a[i].x, sg);
-                xor_ip(a[i].y, sg);
-            }
-        });
-    } else {  // both in registers
-        const uint32_t p = reg_pattern(la & 0x3F) & reg_pattern(lb & 0x3F);
-#pragma unroll
-        for (int i = 0; i < (1 << R); ++i) {
-            const uint32_t sg = ((p >> i) & 1u) << 31;
-            xor_ips(a[i].x, sg);
-            xor_ips(a[i].y, sg);
-        }
+    for (int i = 0; i < (1 << R); ++i) {
+        xor_ip(a[i].x, sg);
+        xor_ip(a[i].y, sg);
     }
 }
 
@@ -463,21 +478,27 @@ __device__ __forceinline__ void apply_op(float2 (&a)[1 << R], const DevOp &o, co
         on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { g_u1<R, std::decay_t<decltype(J)>::value, DAG>(a, m); });
     if (kb & (1u << OP_R1))
         on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { g_r1<R, std::decay_t<decltype(J)>::value, DAG>(a, m); });
-    if (kb & (1u << OP_CZ)) g_cz<R>(a, o.a, o.b, tid, base);
-    if (kb & (1u << OP_CX)) {
-        if ((o.a & LOC_MASK) == LOC_REG) {
-            on_slot<R>(ja, [&](auto C) __attribute__((always_inline)) {
-                on_slot<R>(jb, [&](auto J) __attribute__((always_inline)) {
-                    if constexpr (std::decay_t<decltype(C)>::value != std::decay_t<decltype(J)>::value)
-                        g_cx_reg<R, std::decay_t<decltype(C)>::value, std::decay_t<decltype(J)>::value>(a);
-                });
-            });
-        } else {
-            const uint32_t mk = 0u - lane_bit(o.a, tid, base);
-            on_slot<R>(jb, [&](auto J) __attribute__((always_inline)) { g_cx_lane<R, std::decay_t<decltype(J)>::value>(a, mk); });
-        }
+    if (kb & (1u << OP_CZ)) g_cz<R>(a, reg_pattern(o.a & 0x3F) & reg_pattern(o.b & 0x3F));
+    if (kb & (1u << OP_CZ_RT)) {
+        const uint32_t sg = lane_bit(o.b, tid, base) << 31;
+        on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { g_cz_rt<R, std::decay_t<decltype(J)>::value>(a, sg); });
     }
-    if (kb & (1u << OP_D1)) g_d1<R, DAG>(a, m, o.a, tid, base);
+    if (kb & (1u << OP_CZ_TT)) g_cz_tt<R>(a, (lane_bit(o.a, tid, base) & lane_bit(o.b, tid, base)) << 31);
+    if (kb & (1u << OP_CX)) {
+        on_slot<R>(ja, [&](auto C) __attribute__((always_inline)) {
+            on_slot<R>(jb, [&](auto J) __attribute__((always_inline)) {
+                if constexpr (std::decay_t<decltype(C)>::value != std::decay_t<decltype(J)>::value)
+                    g_cx_reg<R, std::decay_t<decltype(C)>::value, std::decay_t<decltype(J)>::value>(a);
+            });
+        });
+    }
+    if (kb & (1u << OP_CX_T)) {
+        const uint32_t mk = 0u - lane_bit(o.a, tid, base);
+        on_slot<R>(jb, [&](auto J) __attribute__((always_inline)) { g_cx_lane<R, std::decay_t<decltype(J)>::value>(a, mk); });
+    }
+    if (kb & (1u << OP_D1))
+        on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { g_d1<R, std::decay_t<decltype(J)>::value, DAG>(a, m); });
+    if (kb & (1u << OP_D1_T)) g_d1_lane<R, DAG>(a, m, lane_bit(o.a, tid, base));
     if (kb & (1u << OP_D2)) g_d2<R, DAG>(a, m, loc_pattern(o.a, tid, base), loc_pattern(o.b, tid, base));
     if (kb & (1u << OP_CU)) {
         const uint32_t pc = loc_pattern(o.a, tid, base);

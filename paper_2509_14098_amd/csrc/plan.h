@@ -29,7 +29,11 @@ enum OpKind : uint8_t {
     OP_U2 = 8,   // dense 4x4 on two register qubits
     OP_SWAP = 9, // exchange of two register qubits
     OP_DREG = 10, // diagonal over the register index: 2^R complex entries, same for every thread
-    OP_LAYER = 11, // register diagonal, then real rotations on every register slot (identity where unused)
+    OP_LAYER = 11, // register diagonal, then rotations on the register slots in mask a
+    OP_CZ_RT = 12, // CZ between register slot a and thread or tile-index qubit b
+    OP_CZ_TT = 13, // CZ between two thread or tile-index qubits
+    OP_CX_T = 14,  // CX with a thread or tile-index control a, target register slot b
+    OP_D1_T = 15,  // diagonal 2x2 on a thread or tile-index qubit
 };
 
 // Location of a qubit in a stage layout: register slot, thread-id bit, or a
@@ -76,7 +80,8 @@ struct DevPart {
 // Matrix pool layout: a 2x2 gate takes 8 floats (row-major re,im), a 4x4
 // gate 32 floats (local index j = b(q0) + 2 b(q1)), a register diagonal 2^R
 // complex entries; every entry starts at a multiple of 8 floats.  OP_LAYER:
-// 2^R complex diagonal entries, then 4 floats (c00, c01, c10, c11) for every
-// register slot j at 4 j (the identity where slot j has no rotation).
+// 2^R complex diagonal entries, then the shear parameters (t, s) of the
+// rotation on every register slot j at 2 j (zero where slot j has none; the
+// op's field a holds the mask of slots with a rotation).
 
 }  // namespace qsv

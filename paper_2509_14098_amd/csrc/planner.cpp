@@ -437,19 +437,31 @@ struct StageLowering {
         }
         DevOp o = base_op(OP_LAYER, gate);
         o.mat = (int32_t)P.pool.size();
-        for (auto &v : pre.d) {
-            P.pool.push_back((float)v.real());
-            P.pool.push_back((float)v.imag());
-        }
+        // each rotation [[c, -s], [s, c]] is applied as three shears with
+        // t = -s / (1 + c); one with c < 0 is written as -1 times the rotation
+        // by the angle minus pi, and the -1 goes into the diagonal
+        double ts[2 * 5] = {0};
+        bool negate = false;
         uint32_t mask = 0;
-        const size_t rbase = P.pool.size();
-        for (int j = 0; j < R; ++j) {  // identity on slots without a rotation
-            const float id[4] = {1.f, 0.f, 0.f, 1.f};
-            P.pool.insert(P.pool.end(), id, id + 4);
-        }
         for (auto &r : rots) {
+            double c = r.second[0], sn = r.second[2];
+            if (c < 0) {
+                c = -c;
+                sn = -sn;
+                negate = !negate;
+            }
+            ts[2 * r.first] = -sn / (1.0 + c);
+            ts[2 * r.first + 1] = sn;
             mask |= 1u << r.first;
-            for (int k = 0; k < 4; ++k) P.pool[rbase + 4 * r.first + k] = (float)r.second[k];
+        }
+        for (auto &v : pre.d) {
+            const cd w = negate ? -v : v;
+            P.pool.push_back((float)w.real());
+            P.pool.push_back((float)w.imag());
+        }
+        for (int j = 0; j < R; ++j) {
+            P.pool.push_back((float)ts[2 * j]);
+            P.pool.push_back((float)ts[2 * j + 1]);
         }
         while (P.pool.size() % 8) P.pool.push_back(0.f);
         o.a = (int32_t)mask;
@@ -489,6 +501,16 @@ struct StageLowering {
         bool need_reg_b = m.op == OP_CX || m.op == OP_CU || m.op == OP_U2 || m.op == OP_SWAP;
         if ((need_reg_a && !is_reg(o.a)) || (need_reg_b && !is_reg(o.b)))
             throw std::logic_error("required qubit not in registers");
+        // kinds by where the qubits are (each has its own code path in the kernel)
+        if (m.op == OP_CZ) {
+            if (!is_reg(o.a)) std::swap(o.a, o.b);
+            if (!is_reg(o.a)) o.kind = OP_CZ_TT;
+            else if (!is_reg(o.b)) o.kind = OP_CZ_RT;
+        } else if (m.op == OP_CX && !is_reg(o.a)) {
+            o.kind = OP_CX_T;
+        } else if (m.op == OP_D1 && !is_reg(o.a)) {
+            o.kind = OP_D1_T;
+        }
         add(o, m.flops);
     }
     // True if folding gate g now neither closes the pending block nor emits
@@ -628,7 +650,7 @@ double op_cost(int kind)
 {
     switch (kind) {
     case OP_U1: return 8;
-    case OP_R1: case OP_D1: case OP_D2: case OP_DREG: return 4;
+    case OP_R1: case OP_D1: case OP_D1_T: case OP_D2: case OP_DREG: return 4;
     case OP_LAYER: return 4;  // per rotation or diagonal; op_cost_of() counts them
     case OP_CU: return 9;
     case OP_U2: return 16;
@@ -734,15 +756,15 @@ void build_plan(Plan &P)
                 const size_t ops0 = P.ops.size(), pool0 = P.pool.size(), grad0 = P.grad_param.size();
                 const double flops0 = P.flops;
                 double plain_cost = 0, folded_cost = 0;
-                for (int g : s.gates) plain_cost += op_cost(P.meta[g].op) + 6;  // + dispatch
+                for (int g : s.gates) plain_cost += op_cost(P.meta[g].op) + 2;  // + dispatch
                 {
                     StageLowering L(P, mat_of, R, loc, C);
                     s.gates = fold_order(P.meta, s.gates, L);
                     L.flush_all(s.gates.empty() ? -1 : s.gates.back());
                     for (size_t k = ops0; k < P.ops.size(); ++k) {
                         const DevOp &o = P.ops[k];
-                        // a layer op always runs R rotations and the diagonal but needs no dispatch
-                        folded_cost += o.kind == OP_LAYER ? 4.0 * (R + 1) : op_cost(o.kind) + 6;
+                        // a layer op: 3 per rotation and 4 for the diagonal
+                        folded_cost += (o.kind == OP_LAYER ? 3.0 * __builtin_popcount(o.a) + 4 : op_cost(o.kind)) + 2;
                     }
                 }
                 if (folded_cost >= plain_cost) {
