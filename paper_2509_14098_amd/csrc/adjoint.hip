@@ -72,9 +72,10 @@ __global__ __launch_bounds__(1 << LW) void reverse_kernel(const float2 *__restri
     const uint32_t tid = threadIdx.x;
     const int t = P->t;
     float2 *lds_psi = lds, *lds_lam = lds + (1u << t);
+    const uint64_t tile = xcd_tile(blockIdx.x, gridDim.x, P);
     uint64_t base = 0;
     for (int b = 0; b < P->n_glb; ++b)
-        if (((uint64_t)blockIdx.x >> b) & 1ull) base |= 1ull << P->gq[b];
+        if ((tile >> b) & 1ull) base |= 1ull << P->gq[b];
     load_pairs<LW>(psi_src, lds_psi, P, base, tid);
     load_pairs<LW>(lam, lds_lam, P, base, tid);
     __syncthreads();

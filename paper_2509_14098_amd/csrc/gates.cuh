@@ -574,6 +574,21 @@ __device__ __forceinline__ double grad_term(const float2 (&a)[1 << R], const flo
     return acc;
 }
 
+// Tile handled by workgroup b of nblk.  Workgroups are handed to the chip's 8
+// XCDs round-robin (b mod 8) and each XCD has its own L2.  The 2^g tiles that
+// differ only in global qubits below 4 (g = number of such qubits) share
+// 128-byte lines of the state, so they are given to consecutive workgroups of
+// one XCD: each line is then fetched from HBM once instead of once per XCD.
+__device__ __forceinline__ uint64_t xcd_tile(uint32_t b, uint32_t nblk, const DevPart *__restrict__ P)
+{
+    int g = 0;
+    while (g < P->n_glb && P->gq[g] < 4) ++g;
+    const uint32_t G = 1u << g;
+    if (g == 0 || nblk % (8u * G)) return b;
+    const uint32_t x = b & 7u, j = b >> 3;
+    return ((uint64_t)((j >> g) * 8u + x) << g) | (j & (G - 1u));
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll

@@ -135,7 +135,7 @@ __global__ __launch_bounds__(1 << LW) void sweep_kernel(float2 *__restrict__ psi
     extern __shared__ float2 lds[];
     const DevPart *__restrict__ P = parts + pidx;
     const uint32_t tid = threadIdx.x;
-    const uint64_t base = tile_base<R, LW>(P, blockIdx.x);
+    const uint64_t base = tile_base<R, LW>(P, xcd_tile(blockIdx.x, gridDim.x, P));
     load_tile<R, LW>(psi, lds, P, base, tid);
     __syncthreads();
     run_stages<R, false>(lds, stages, ops, pool, P->stage_begin, P->stage_end, P->t - R, tid, base);
