@@ -202,11 +202,12 @@ qsv_status qsv_expect(qsv_ctx *ctx, const qsv_pauli_term *H, int32_t n_terms, in
  * (parameters used by several rotations receive the sum of their terms).
  * Single-circuit plans: psi_final_dev is the state qsv_apply produced and
  * ckpt_dev the checkpoints it wrote; the plan must carry QSV_PLAN_GRAD.
- * Batched plans (n_circuits > 1): forward, energy and adjoint run in one
- * persistent launch from |0..0> (longest circuits first); ckpt_dev is
- * ignored, psi_final_dev may be NULL or receive the final states
- * (complex64[n_circuits][2^n]).  grad_dev: float64[n_params], energy_dev:
- * float64[n_circuits].
+ * Batched plans (n_circuits > 1): energy and adjoint of every circuit run in
+ * one persistent launch (longest circuits first); ckpt_dev is ignored.
+ * psi_final_dev is either the final states qsv_apply wrote for this plan and
+ * theta (complex64[n_circuits][2^n], read only) or NULL, in which case the
+ * same launch first runs each circuit forward from |0..0>.
+ * grad_dev: float64[n_params], energy_dev: float64[n_circuits].
  * Errors: QSV_E_STATE (no QSV_PLAN_GRAD or missing checkpoints), QSV_E_ARG.
  */
 qsv_status qsv_adjoint_grad(qsv_ctx *ctx, const qsv_plan *plan, const qsv_pauli_term *H, int32_t n_terms,

@@ -99,8 +99,7 @@ __global__ __launch_bounds__(1 << LW) void reverse_kernel(const float2 *__restri
                 const double v = wave_sum(grad_term<R>(a, l, o, tid, base));
                 if ((tid & 63) == 0) gpart[(int64_t)o.grad_slot * slot_stride + part_index] = v;
             }
-            apply_op<R, true>(a, o, pool, tid, base);
-            apply_op<R, true>(l, o, pool, tid, base);
+            apply_op_dag2<R>(a, l, o, pool, tid, base);
         }
         if (active) {
             asm volatile("" : "+v"(toff));  // recompute the write-back addresses instead of keeping 2^R live

@@ -30,7 +30,8 @@ struct BatchArgs {
     int n_groups;
     int n_circuits;
     int n;
-    float2 *psi_out;            // may be null
+    float2 *psi_out;            // forward only: final states (may be null)
+    const float2 *psi_in;       // adjoint only: final states of the forward (null: recompute them)
     double *energy;             // [n_circuits] (adjoint only)
     double *grad;               // [n_params]   (adjoint only)
     double *gpart;              // [n_slots][waves] scratch
@@ -81,10 +82,15 @@ __global__ __launch_bounds__(1 << LW) void batched_kernel(
         const int t = P->t, w = t - R;
         const bool active = tid < (1u << w);
         const uint32_t dim = 1u << t;
-        // forward from |0..0>
-        for (uint32_t x = tid; x < dim; x += (1u << LW)) lds[swz(x)] = float2{x == 0 ? 1.f : 0.f, 0.f};
-        __syncthreads();
-        run_stages<R, false>(lds, stages, ops, pool, P->stage_begin, P->stage_end, w, tid, 0);
+        if (A.psi_in) {  // the forward's final state (positions are the qubits in order)
+            const float2 *src = A.psi_in + (uint64_t)c * dim;
+            for (uint32_t x = tid; x < dim; x += (1u << LW)) lds[swz(x)] = src[x];
+            __syncthreads();
+        } else {  // forward from |0..0>
+            for (uint32_t x = tid; x < dim; x += (1u << LW)) lds[swz(x)] = float2{x == 0 ? 1.f : 0.f, 0.f};
+            __syncthreads();
+            run_stages<R, false>(lds, stages, ops, pool, P->stage_begin, P->stage_end, w, tid, 0);
+        }
         if (A.psi_out) {  // the tile is the whole state and its positions are the qubits in order
             float2 *dst = A.psi_out + (uint64_t)c * dim;
             for (uint32_t x = tid; x < dim; x += (1u << LW)) dst[x] = lds[swz(x)];
@@ -151,6 +157,8 @@ __global__ __launch_bounds__(1 << LW) void batched_kernel(
                     const double v = wave_sum(grad_term<R>(a, l, o, tid, 0));
                     if ((tid & 63) == 0) A.gpart[(int64_t)o.grad_slot * WAVES + wave] = v;
                 }
+                // one array at a time: with 1024 threads a lane has 128 VGPRs, too
+                // few to update psi and lambda together without spilling
                 apply_op<R, true>(a, o, pool, tid, 0);
                 apply_op<R, true>(l, o, pool, tid, 0);
             }
@@ -176,9 +184,21 @@ __global__ void reset_counter_kernel(int *q)
 
 constexpr int BATCH_R = 4, BATCH_LW = 10;
 
+template <int R, int LW>
+static void set_lds_attr()
+{
+    static bool done = false;
+    if (!done) {
+        (void)hipFuncSetAttribute((const void *)batched_kernel<R, LW>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024);
+        (void)hipGetLastError();
+        done = true;
+    }
+}
+
 hipError_t launch_batched(const Plan &plan, const DevGroup *groups, int n_groups, const DevTerm *terms,
-                          const double *theta, float2 *psi_out, double *energy, double *grad, double *gpart,
-                          int *queue, bool adjoint, int grid, hipStream_t s)
+                          const double *theta, float2 *psi_out, const float2 *psi_in, double *energy, double *grad,
+                          double *gpart, int *queue, bool adjoint, int grid, hipStream_t s)
 {
     if (plan.R != BATCH_R || plan.LW != BATCH_LW) return hipErrorInvalidValue;
     hipError_t e = launch_materialize(plan, theta, s);
@@ -191,19 +211,14 @@ hipError_t launch_batched(const Plan &plan, const DevGroup *groups, int n_groups
     A.n_circuits = plan.n_circuits;
     A.n = plan.n;
     A.psi_out = psi_out;
+    A.psi_in = adjoint ? psi_in : nullptr;
     A.energy = energy;
     A.grad = grad;
     A.gpart = gpart;
     A.queue = queue;
     A.adjoint = adjoint ? 1 : 0;
-    static bool attr = false;
-    if (!attr) {
-        (void)hipFuncSetAttribute((const void *)batched_kernel<BATCH_R, BATCH_LW>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        (void)hipGetLastError();
-        attr = true;
-    }
     const size_t lds = (size_t)8 << plan.t;
+    set_lds_attr<BATCH_R, BATCH_LW>();
     hipLaunchKernelGGL((batched_kernel<BATCH_R, BATCH_LW>), dim3(grid), dim3(1 << BATCH_LW), lds, s, plan.d_parts,
                        plan.d_stages, plan.d_ops, plan.d_pool, plan.d_batch_order, plan.d_circ_part,
                        plan.d_circ_theta, plan.d_circ_npar, plan.d_param_off, plan.d_param_slots, groups, terms, A);

@@ -432,7 +432,7 @@ qsv_status qsv_partition(qsv_ctx *ctx, int32_t n_qubits, const qsv_gate *gates, 
         }
         if (n_circuits > 1) {
             if (n_qubits < 4) fail(QSV_E_UNSUPPORTED, "batched plans need n_qubits >= 4");
-            R = 4;
+            R = 4;  // the batched kernel's shape: 4 register qubits x 1024 threads
             LW = 10;
         }
         if ((flags & QSV_PLAN_GRAD) && n_circuits == 1 && R + LW > 13 && n_qubits > 13)
@@ -564,7 +564,7 @@ qsv_status qsv_apply(qsv_ctx *ctx, const qsv_plan *plan, const double *theta_dev
         if (plan->n_params > 0 && !theta_dev) fail(QSV_E_ARG, "theta is null");
         hip_check(hipSetDevice(ctx->device), "hipSetDevice");
         if (plan->n_circuits > 1) {
-            hip_check(launch_batched(*plan, nullptr, 0, nullptr, theta_dev, (float2 *)psi_dev, nullptr, nullptr,
+            hip_check(launch_batched(*plan, nullptr, 0, nullptr, theta_dev, (float2 *)psi_dev, nullptr, nullptr, nullptr,
                                      nullptr, ctx->ensure_queue(), false, ctx->grid_batched(plan->n_circuits),
                                      ctx->stream),
                       "batched launch");
@@ -632,7 +632,7 @@ qsv_status qsv_adjoint_grad(qsv_ctx *ctx, const qsv_plan *plan, const qsv_pauli_
             DevGroup *dg = nullptr;
             DevTerm *dt = nullptr;
             if (!g.groups.empty()) upload_groups(ctx, g, dg, dt);
-            hip_check(launch_batched(*plan, dg, (int)g.groups.size(), dt, theta_dev, (float2 *)psi_final_dev,
+            hip_check(launch_batched(*plan, dg, (int)g.groups.size(), dt, theta_dev, nullptr, (const float2 *)psi_final_dev,
                                      energy_dev, grad_dev, gpart, ctx->ensure_queue(), true,
                                      ctx->grid_batched(plan->n_circuits), ctx->stream),
                       "batched launch");

@@ -460,95 +460,152 @@ __device__ __forceinline__ void g_swap(float2 (&a)[1 << R])
     }
 }
 
-// Apply one op (or its conjugate transpose) to a thread's amplitudes.
+// Apply one op (or its conjugate transpose) to one or more amplitude arrays of
+// a thread (the adjoint walk applies each op to psi and lambda in one pass).
 // mm holds the op's 8 leading matrix floats (load_m8); layer, register
 // diagonal and dense 4x4 ops read theirs from the pool.  The op kind and the
 // register slots are tested bit by bit on opaque one-hot masks (see opaque()).
-template <int R, bool DAG>
-__device__ __forceinline__ void apply_op(float2 (&a)[1 << R], const DevOp &o, const M8 &mm,
-                                         const float *__restrict__ pool, uint32_t tid, uint64_t base)
+template <int R, bool DAG, typename... Arr>
+__device__ __forceinline__ void apply_ops(const DevOp &o, const M8 &mm, const float *__restrict__ pool, uint32_t tid,
+                                          uint64_t base, Arr &...as)
 {
     const float *m = mm.v;
     const float *__restrict__ m32 = pool + (o.mat < 0 ? 0 : o.mat);
     const uint32_t kb = opaque(1u << o.kind);
     const uint32_t ja = opaque(1u << (o.a & 0x3F)), jb = opaque(1u << (o.b & 0x3F));
-    if (kb & (1u << OP_LAYER)) g_layer<R, DAG>(a, m32, (uint32_t)o.a);
-    if (kb & (1u << OP_DREG)) g_dreg<R, DAG>(a, m32);
+#define QSV_J(x) std::decay_t<decltype(x)>::value
+    if (kb & (1u << OP_LAYER)) (g_layer<R, DAG>(as, m32, (uint32_t)o.a), ...);
+    if (kb & (1u << OP_DREG)) (g_dreg<R, DAG>(as, m32), ...);
     if (kb & (1u << OP_U1))
-        on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { g_u1<R, std::decay_t<decltype(J)>::value, DAG>(a, m); });
+        on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { (g_u1<R, QSV_J(J), DAG>(as, m), ...); });
     if (kb & (1u << OP_R1))
-        on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { g_r1<R, std::decay_t<decltype(J)>::value, DAG>(a, m); });
-    if (kb & (1u << OP_CZ)) g_cz<R>(a, reg_pattern(o.a & 0x3F) & reg_pattern(o.b & 0x3F));
+        on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { (g_r1<R, QSV_J(J), DAG>(as, m), ...); });
+    if (kb & (1u << OP_CZ)) {
+        const uint32_t p = reg_pattern(o.a & 0x3F) & reg_pattern(o.b & 0x3F);
+        (g_cz<R>(as, p), ...);
+    }
     if (kb & (1u << OP_CZ_RT)) {
         const uint32_t sg = lane_bit(o.b, tid, base) << 31;
-        on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { g_cz_rt<R, std::decay_t<decltype(J)>::value>(a, sg); });
+        on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { (g_cz_rt<R, QSV_J(J)>(as, sg), ...); });
     }
-    if (kb & (1u << OP_CZ_TT)) g_cz_tt<R>(a, (lane_bit(o.a, tid, base) & lane_bit(o.b, tid, base)) << 31);
+    if (kb & (1u << OP_CZ_TT)) {
+        const uint32_t sg = (lane_bit(o.a, tid, base) & lane_bit(o.b, tid, base)) << 31;
+        (g_cz_tt<R>(as, sg), ...);
+    }
     if (kb & (1u << OP_CX)) {
         on_slot<R>(ja, [&](auto C) __attribute__((always_inline)) {
             on_slot<R>(jb, [&](auto J) __attribute__((always_inline)) {
-                if constexpr (std::decay_t<decltype(C)>::value != std::decay_t<decltype(J)>::value)
-                    g_cx_reg<R, std::decay_t<decltype(C)>::value, std::decay_t<decltype(J)>::value>(a);
+                if constexpr (QSV_J(C) != QSV_J(J)) (g_cx_reg<R, QSV_J(C), QSV_J(J)>(as), ...);
             });
         });
     }
     if (kb & (1u << OP_CX_T)) {
         const uint32_t mk = 0u - lane_bit(o.a, tid, base);
-        on_slot<R>(jb, [&](auto J) __attribute__((always_inline)) { g_cx_lane<R, std::decay_t<decltype(J)>::value>(a, mk); });
+        on_slot<R>(jb, [&](auto J) __attribute__((always_inline)) { (g_cx_lane<R, QSV_J(J)>(as, mk), ...); });
     }
     if (kb & (1u << OP_D1))
-        on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { g_d1<R, std::decay_t<decltype(J)>::value, DAG>(a, m); });
-    if (kb & (1u << OP_D1_T)) g_d1_lane<R, DAG>(a, m, lane_bit(o.a, tid, base));
-    if (kb & (1u << OP_D2)) g_d2<R, DAG>(a, m, loc_pattern(o.a, tid, base), loc_pattern(o.b, tid, base));
+        on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { (g_d1<R, QSV_J(J), DAG>(as, m), ...); });
+    if (kb & (1u << OP_D1_T)) {
+        const uint32_t bit = lane_bit(o.a, tid, base);
+        (g_d1_lane<R, DAG>(as, m, bit), ...);
+    }
+    if (kb & (1u << OP_D2)) {
+        const uint32_t pa = loc_pattern(o.a, tid, base), pb = loc_pattern(o.b, tid, base);
+        (g_d2<R, DAG>(as, m, pa, pb), ...);
+    }
     if (kb & (1u << OP_CU)) {
         const uint32_t pc = loc_pattern(o.a, tid, base);
-        on_slot<R>(jb, [&](auto J) __attribute__((always_inline)) { g_cu<R, std::decay_t<decltype(J)>::value, DAG>(a, m, pc); });
+        on_slot<R>(jb, [&](auto J) __attribute__((always_inline)) { (g_cu<R, QSV_J(J), DAG>(as, m, pc), ...); });
     }
     if constexpr (R >= 2) {
         if (kb & (1u << OP_U2)) {
             on_slot<R>(ja, [&](auto JA) __attribute__((always_inline)) {
                 on_slot<R>(jb, [&](auto JB) __attribute__((always_inline)) {
-                    if constexpr (std::decay_t<decltype(JA)>::value != std::decay_t<decltype(JB)>::value)
-                        g_u2<R, std::decay_t<decltype(JA)>::value, std::decay_t<decltype(JB)>::value, DAG>(a, m32);
+                    if constexpr (QSV_J(JA) != QSV_J(JB)) (g_u2<R, QSV_J(JA), QSV_J(JB), DAG>(as, m32), ...);
                 });
             });
         }
         if (kb & (1u << OP_SWAP)) {
             on_slot<R>(ja, [&](auto JA) __attribute__((always_inline)) {
                 on_slot<R>(jb, [&](auto JB) __attribute__((always_inline)) {
-                    if constexpr (std::decay_t<decltype(JA)>::value != std::decay_t<decltype(JB)>::value)
-                        g_swap<R, std::decay_t<decltype(JA)>::value, std::decay_t<decltype(JB)>::value>(a);
+                    if constexpr (QSV_J(JA) != QSV_J(JB)) (g_swap<R, QSV_J(JA), QSV_J(JB)>(as), ...);
                 });
             });
         }
     }
+#undef QSV_J
 }
 
 template <int R, bool DAG>
 __device__ __forceinline__ void apply_op(float2 (&a)[1 << R], const DevOp &o, const float *__restrict__ pool,
                                          uint32_t tid, uint64_t base)
 {
-    apply_op<R, DAG>(a, o, load_m8(pool, o.mat), pool, tid, base);
+    apply_ops<R, DAG>(o, load_m8(pool, o.mat), pool, tid, base, a);
+}
+
+// The op's conjugate transpose on psi and lambda together (adjoint walk).
+template <int R>
+__device__ __forceinline__ void apply_op_dag2(float2 (&a)[1 << R], float2 (&l)[1 << R], const DevOp &o,
+                                              const float *__restrict__ pool, uint32_t tid, uint64_t base)
+{
+    apply_ops<R, true>(o, load_m8(pool, o.mat), pool, tid, base, a, l);
 }
 
 // ---------------------------------------------------------------------------
 // Adjoint helpers: Im <lambda|P|psi> for the generator P of a rotation
 // exp(-i a P / 2), over one thread's amplitudes, in float64.
-__device__ __forceinline__ double im_conj_mul(float2 l, float2 a) { return (double)l.x * a.y - (double)l.y * a.x; }
-__device__ __forceinline__ double re_conj_mul(float2 l, float2 a) { return (double)l.x * a.x + (double)l.y * a.y; }
+// float -> double conversion ordered after acc has been computed (keeps the
+// converted values of later terms from all being live at once)
+__device__ __forceinline__ double cvt_after(float f, double acc)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double d;
+    asm("v_cvt_f64_f32 %0, %1" : "=v"(d) : "v"(f), "v"(acc));
+    return d;
+#else
+    (void)acc;
+    return (double)f;
+#endif
+}
+// acc + Im(conj(l) a), acc + Re(conj(l) a): exact products in float64
+__device__ __forceinline__ double acc_im(double acc, float2 l, float2 a)
+{
+    acc = __builtin_fma(cvt_after(l.x, acc), cvt_after(a.y, acc), acc);
+    return __builtin_fma(-cvt_after(l.y, acc), cvt_after(a.x, acc), acc);
+}
+__device__ __forceinline__ double acc_re(double acc, float2 l, float2 a)
+{
+    acc = __builtin_fma(cvt_after(l.x, acc), cvt_after(a.x, acc), acc);
+    return __builtin_fma(cvt_after(l.y, acc), cvt_after(a.y, acc), acc);
+}
 
-template <int R, int J>
-__device__ __forceinline__ double grad_pairs(const float2 (&a)[1 << R], const float2 (&l)[1 << R], bool y_gen)
+template <int R, int J, bool Y>
+__device__ __forceinline__ double grad_pairs(const float2 (&a)[1 << R], const float2 (&l)[1 << R])
 {
     double acc = 0.0;
 #pragma unroll
     for (int i = 0; i < (1 << R); ++i) {
         if (i & (1 << J)) continue;
         const float2 a0 = a[i], a1 = a[i | (1 << J)], l0 = l[i], l1 = l[i | (1 << J)];
-        if (y_gen)  // Y: (Y psi)_0 = -i psi_1, (Y psi)_1 = i psi_0
-            acc += re_conj_mul(l1, a0) - re_conj_mul(l0, a1);
-        else        // X: (X psi)_0 = psi_1, (X psi)_1 = psi_0
-            acc += im_conj_mul(l0, a1) + im_conj_mul(l1, a0);
+        if (Y) {  // Y: (Y psi)_0 = -i psi_1, (Y psi)_1 = i psi_0
+            acc = acc_re(acc, l1, a0);
+            acc = acc_re(acc, float2{-l0.x, -l0.y}, a1);
+        } else {  // X: (X psi)_0 = psi_1, (X psi)_1 = psi_0
+            acc = acc_im(acc, l0, a1);
+            acc = acc_im(acc, l1, a0);
+        }
+    }
+    return acc;
+}
+
+// Z on register slot J: the sign of each term is fixed by the register index.
+template <int R, int J>
+__device__ __forceinline__ double grad_z_reg(const float2 (&a)[1 << R], const float2 (&l)[1 << R])
+{
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < (1 << R); ++i) {
+        acc = acc_im(acc, ((i >> J) & 1) ? float2{-l[i].x, -l[i].y} : l[i], a[i]);
     }
     return acc;
 }
@@ -559,17 +616,20 @@ __device__ __forceinline__ double grad_term(const float2 (&a)[1 << R], const flo
                                             uint32_t tid, uint64_t base)
 {
     double acc = 0.0;
-    if (o.gen == GEN_Z || o.gen == GEN_ZZ) {
+    const uint32_t ja = opaque(1u << (o.a & 0x3F));
+    if (o.gen == GEN_Z && (o.a & LOC_MASK) == LOC_REG) {
+        on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { acc = grad_z_reg<R, std::decay_t<decltype(J)>::value>(a, l); });
+    } else if (o.gen == GEN_Z || o.gen == GEN_ZZ) {
         uint32_t p = loc_pattern(o.a, tid, base);
         if (o.gen == GEN_ZZ) p ^= loc_pattern(o.b, tid, base);
 #pragma unroll
         for (int i = 0; i < (1 << R); ++i) {
-            const double v = im_conj_mul(l[i], a[i]);
-            acc += ((p >> i) & 1u) ? -v : v;
+            acc = acc_im(acc, ((p >> i) & 1u) ? float2{-l[i].x, -l[i].y} : l[i], a[i]);
         }
+    } else if (o.gen == GEN_Y) {
+        on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { acc = grad_pairs<R, std::decay_t<decltype(J)>::value, true>(a, l); });
     } else {
-        const bool y = o.gen == GEN_Y;
-        on_reg<R>(o.a & 0x3F, [&](auto J) __attribute__((always_inline)) { acc = grad_pairs<R, std::decay_t<decltype(J)>::value>(a, l, y); });
+        on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { acc = grad_pairs<R, std::decay_t<decltype(J)>::value, false>(a, l); });
     }
     return acc;
 }

@@ -34,8 +34,8 @@ hipError_t launch_grad_reduce(const Plan &plan, const double *gpart, int64_t n_s
 
 // batched.hip
 hipError_t launch_batched(const Plan &plan, const DevGroup *groups, int n_groups, const DevTerm *terms,
-                          const double *theta, float2 *psi_out, double *energy, double *grad, double *gpart,
-                          int *queue, bool adjoint, int grid, hipStream_t s);
+                          const double *theta, float2 *psi_out, const float2 *psi_in, double *energy, double *grad,
+                          double *gpart, int *queue, bool adjoint, int grid, hipStream_t s);
 int batched_waves();
 
 }  // namespace qsv

@@ -300,15 +300,16 @@ def test_batched_energy_gradient_and_states(sim, n, B, seed):
     try:
         assert plan.n_params == len(theta)
         psi = torch.empty((B, 1 << n), dtype=torch.complex64, device="cuda")
-        energy, grad = sim.adjoint_grad(plan, H, theta, psi)
-        torch.cuda.synchronize()
-        psi2 = torch.empty_like(psi)
-        sim.apply(plan, psi2, theta)
+        sim.apply(plan, psi, theta)
+        energy, grad = sim.adjoint_grad(plan, H, theta, psi)      # from the forward's final states
+        energy2, grad2 = sim.adjoint_grad(plan, H, theta)         # forward recomputed in the same launch
         torch.cuda.synchronize()
     finally:
         plan.close()
-    energy, grad, psi, psi2 = energy.cpu().numpy(), grad.cpu().numpy(), psi.cpu().numpy(), psi2.cpu().numpy()
-    assert np.array_equal(psi, psi2)  # forward-only launch gives the same states
+    energy, grad, psi = energy.cpu().numpy(), grad.cpu().numpy(), psi.cpu().numpy()
+    # same kernel code on the same states: identical results either way
+    assert np.array_equal(energy, energy2.cpu().numpy())
+    assert np.array_equal(grad, grad2.cpu().numpy())
     for b in range(B):
         o0, o1 = off[b], off[b + 1]
         p0 = sum(len(t) for t in thetas[:b])
@@ -350,6 +351,7 @@ def test_batched_with_empty_circuit(sim):
     H = W.zz_chain_plus_x(n, 0.5)
     plan = sim.partition(n, gates, 0, Q.PLAN_GRAD, None, circ_offsets=off)
     psi = torch.empty((3, 1 << n), dtype=torch.complex64, device="cuda")
+    sim.apply(plan, psi, theta)
     e, g = sim.adjoint_grad(plan, H, theta, psi)
     plan.close()
     assert abs(float(e[1]) - oracle.expect(n, H, oracle.zero_state(n))) < 1e-6
