@@ -476,14 +476,6 @@ __device__ __forceinline__ void apply_ops(const DevOp &o, const M8 &mm, const fl
 #define QSV_J(x) std::decay_t<decltype(x)>::value
     if (kb & (1u << OP_LAYER)) (g_layer<R, DAG>(as, m32, (uint32_t)o.a), ...);
     if (kb & (1u << OP_DREG)) (g_dreg<R, DAG>(as, m32), ...);
-    if (kb & (1u << OP_U1))
-        on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { (g_u1<R, QSV_J(J), DAG>(as, m), ...); });
-    if (kb & (1u << OP_R1))
-        on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { (g_r1<R, QSV_J(J), DAG>(as, m), ...); });
-    if (kb & (1u << OP_CZ)) {
-        const uint32_t p = reg_pattern(o.a & 0x3F) & reg_pattern(o.b & 0x3F);
-        (g_cz<R>(as, p), ...);
-    }
     if (kb & (1u << OP_CZ_RT)) {
         const uint32_t sg = lane_bit(o.b, tid, base) << 31;
         on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { (g_cz_rt<R, QSV_J(J)>(as, sg), ...); });
@@ -502,6 +494,18 @@ __device__ __forceinline__ void apply_ops(const DevOp &o, const M8 &mm, const fl
     if (kb & (1u << OP_CX_T)) {
         const uint32_t mk = 0u - lane_bit(o.a, tid, base);
         on_slot<R>(jb, [&](auto J) __attribute__((always_inline)) { (g_cx_lane<R, QSV_J(J)>(as, mk), ...); });
+    }
+    // the kinds that fused stages use least are tested only when one of them is present
+    constexpr uint32_t RARE = (1u << OP_U1) | (1u << OP_R1) | (1u << OP_CZ) | (1u << OP_D1) | (1u << OP_D1_T) |
+                              (1u << OP_D2) | (1u << OP_CU) | (1u << OP_U2) | (1u << OP_SWAP);
+    if (!(kb & RARE)) return;
+    if (kb & (1u << OP_U1))
+        on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { (g_u1<R, QSV_J(J), DAG>(as, m), ...); });
+    if (kb & (1u << OP_R1))
+        on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { (g_r1<R, QSV_J(J), DAG>(as, m), ...); });
+    if (kb & (1u << OP_CZ)) {
+        const uint32_t p = reg_pattern(o.a & 0x3F) & reg_pattern(o.b & 0x3F);
+        (g_cz<R>(as, p), ...);
     }
     if (kb & (1u << OP_D1))
         on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { (g_d1<R, QSV_J(J), DAG>(as, m), ...); });
