@@ -92,7 +92,7 @@ __device__ __forceinline__ uint32_t lane_bit(int32_t loc, uint32_t tid, uint64_t
 }
 
 // The 8 floats of a 2x2 gate matrix (or 4 diagonal entries), loaded as one
-// scalar block so the next op's matrix can be fetched while this one runs.
+// scalar block.
 struct M8 {
     float v[8];
 };
@@ -462,14 +462,12 @@ __device__ __forceinline__ void g_swap(float2 (&a)[1 << R])
 
 // Apply one op (or its conjugate transpose) to one or more amplitude arrays of
 // a thread (the adjoint walk applies each op to psi and lambda in one pass).
-// mm holds the op's 8 leading matrix floats (load_m8); layer, register
-// diagonal and dense 4x4 ops read theirs from the pool.  The op kind and the
-// register slots are tested bit by bit on opaque one-hot masks (see opaque()).
+// The op kind and the register slots are tested bit by bit on opaque one-hot
+// masks (see opaque()).
 template <int R, bool DAG, typename... Arr>
-__device__ __forceinline__ void apply_ops(const DevOp &o, const M8 &mm, const float *__restrict__ pool, uint32_t tid,
+__device__ __forceinline__ void apply_ops(const DevOp &o, const float *__restrict__ pool, uint32_t tid,
                                           uint64_t base, Arr &...as)
 {
-    const float *m = mm.v;
     const float *__restrict__ m32 = pool + (o.mat < 0 ? 0 : o.mat);
     const uint32_t kb = opaque(1u << o.kind);
     const uint32_t ja = opaque(1u << (o.a & 0x3F)), jb = opaque(1u << (o.b & 0x3F));
@@ -499,6 +497,8 @@ __device__ __forceinline__ void apply_ops(const DevOp &o, const M8 &mm, const fl
     constexpr uint32_t RARE = (1u << OP_U1) | (1u << OP_R1) | (1u << OP_CZ) | (1u << OP_D1) | (1u << OP_D1_T) |
                               (1u << OP_D2) | (1u << OP_CU) | (1u << OP_U2) | (1u << OP_SWAP);
     if (!(kb & RARE)) return;
+    const M8 mm = load_m8(pool, o.mat);  // the 8 leading matrix floats, one scalar load
+    const float *m = mm.v;
     if (kb & (1u << OP_U1))
         on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { (g_u1<R, QSV_J(J), DAG>(as, m), ...); });
     if (kb & (1u << OP_R1))
@@ -544,7 +544,7 @@ template <int R, bool DAG>
 __device__ __forceinline__ void apply_op(float2 (&a)[1 << R], const DevOp &o, const float *__restrict__ pool,
                                          uint32_t tid, uint64_t base)
 {
-    apply_ops<R, DAG>(o, load_m8(pool, o.mat), pool, tid, base, a);
+    apply_ops<R, DAG>(o, pool, tid, base, a);
 }
 
 // The op's conjugate transpose on psi and lambda together (adjoint walk).
@@ -552,7 +552,7 @@ template <int R>
 __device__ __forceinline__ void apply_op_dag2(float2 (&a)[1 << R], float2 (&l)[1 << R], const DevOp &o,
                                               const float *__restrict__ pool, uint32_t tid, uint64_t base)
 {
-    apply_ops<R, true>(o, load_m8(pool, o.mat), pool, tid, base, a, l);
+    apply_ops<R, true>(o, pool, tid, base, a, l);
 }
 
 // ---------------------------------------------------------------------------
