@@ -34,6 +34,41 @@ import workloads as W
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
 FP32_VECTOR_PEAK = 157.3     # TFLOP/s (packed FP32 VALU; unpacked issue gives half)
+HERE = os.path.dirname(os.path.abspath(__file__))
+# HBM traffic of the sweep kernel measured with rocprofv3 counters (FETCH_SIZE,
+# WRITE_SIZE) on this workload, and the same counters for a plain 2 GiB copy
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "sweep_kernel_traffic_c2_28q.txt")
+SWEEP_SOURCES = ["sweep.hip", "gates.cuh", "plan.h"]
+
+
+def sweep_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in SWEEP_SOURCES:
+        with open(os.path.join(HERE, "paper_2509_14098_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per sweep launch from the committed counter summary, scaled by
+    the copy calibration; None if it is missing or was taken on other kernel
+    sources."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("kernel_sources_sha256") != sweep_sources_sha256():
+            return None
+        copy_bytes = float(kv["copy_bytes"])
+        fetch = float(kv["sweep_fetch_kib_per_dispatch"]) * copy_bytes / float(kv["copy_fetch_kib_per_dispatch"])
+        write = float(kv["sweep_write_kib_per_dispatch"]) * copy_bytes / float(kv["copy_write_kib_per_dispatch"])
+        return fetch + write
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def sync():
@@ -214,7 +249,13 @@ def main():
         for _ in range(5):
             dst.copy_(src)
         sync()
-        print(json.dumps(dict(copy_bytes_read=8 << 28, copy_bytes_written=8 << 28, launches=5)))
+        t0 = time.perf_counter()
+        for _ in range(5):
+            dst.copy_(src)
+        sync()
+        dt = (time.perf_counter() - t0) / 5
+        print(json.dumps(dict(copy_bytes_read=8 << 28, copy_bytes_written=8 << 28, launches=10,
+                              copy_gbs=round(2 * (8 << 28) / dt / 1e9, 1), sources_sha256=sweep_sources_sha256())))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU path is not part of this "
@@ -231,12 +272,14 @@ def main():
     ridge = FP32_VECTOR_PEAK * 1e12 / (HBM_PEAK_GBS * 1e9)
     achieved_gbs = sweep_bytes / (avg_launch_ms * 1e-3) / 1e9
     achieved_tf = sweep_flops / (avg_launch_ms * 1e-3) / 1e12
+    traffic = measured_traffic()
+    traffic = None if traffic is None else round(traffic)
     if intensity > ridge:
         roof = dict(bound="alu", achieved=round(achieved_tf, 3), peak=FP32_VECTOR_PEAK, unit="TFLOP/s",
-                    frac=round(achieved_tf / FP32_VECTOR_PEAK, 4), traffic=None)
+                    frac=round(achieved_tf / FP32_VECTOR_PEAK, 4), traffic=traffic)
     else:
         roof = dict(bound="hbm", achieved=round(achieved_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved_gbs / HBM_PEAK_GBS, 4), traffic=None)
+                    frac=round(achieved_gbs / HBM_PEAK_GBS, 4), traffic=traffic)
     line = dict(
         metric="state-vector sweep GB/s (% HBM peak); adjoint grad time / forward; fused vs gate-by-gate",
         value=round(value, 2), unit="GB/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
@@ -251,7 +294,8 @@ def main():
         hbm_frac=round(value / HBM_PEAK_GBS, 4),
         roofline=roof,
         roofline_hbm=dict(achieved=round(achieved_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                          frac=round(achieved_gbs / HBM_PEAK_GBS, 4)),
+                          frac=round(achieved_gbs / HBM_PEAK_GBS, 4),
+                          traffic_over_algorithmic=None if traffic is None else round(traffic / sweep_bytes, 4)),
         sweep=dict(avg_launch_ms=round(avg_launch_ms, 4), bytes_per_launch=sweep_bytes,
                    flops_per_launch=sweep_flops, flops_per_byte=round(intensity, 2), ridge_flops_per_byte=round(ridge, 2),
                    tflops=round(achieved_tf, 3)),
