@@ -208,6 +208,34 @@ def bench_batched(sim, args):
                 instances_per_s=round(B / dt, 1), register_stages=info["n_stages"], plan_seconds=round(plan_s, 3))
 
 
+def bench_c3(sim, args):
+    """32-qubit local share (60 layers of U3 + random CX matchings): the
+    autotuner chooses k and the tile shape, then one apply and <sum Z_i Z_i+1>."""
+    n = 32
+    gates = W.brickwork_c3()
+    t0 = time.perf_counter()
+    plan = sim.partition(n, gates, 0)
+    plan_s = time.perf_counter() - t0
+    info = plan.info
+    psi = sim.zero_state(n)
+    H = W.zz_chain(n)
+    out = torch.empty(1, dtype=torch.float64, device=sim.device)
+    sync()
+    t0 = time.perf_counter()
+    sim.apply(plan, psi)
+    Q.qsv_expect(sim.ctx, H, n, 1, psi, out)
+    sync()
+    dt = time.perf_counter() - t0
+    plan.close()
+    del psi
+    torch.cuda.empty_cache()
+    return dict(n_qubits=n, n_gates=int(len(gates)), k_local=info["k_local"], reg_qubits=info["reg_qubits"],
+                log_threads=info["log_threads"], partitions=info["n_partitions"],
+                plan_and_tune_s=round(plan_s, 2), candidates=[list(c) for c in Q.qsv_last_autotune()],
+                apply_expect_ms=round(dt * 1e3, 1),
+                gbs=round((info["bytes_per_apply"] + 8.0 * (1 << n)) / dt / 1e9, 1), zz=float(out[0]))
+
+
 def bench_oracle(args, gpu_bytes_per_apply, n_gates_total):
     """The oracle on a bounded prefix of the headline circuit (~10-30 s)."""
     import oracle
@@ -239,6 +267,7 @@ def main():
     ap.add_argument("--skip-grad", action="store_true")
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-c3", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy 5 times (reference for HBM traffic counters)")
@@ -308,6 +337,8 @@ def main():
         line["adjoint"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in bench_gradient(sim, args).items()}
     if not args.skip_batched:
         line["batched"] = bench_batched(sim, args)
+    if not args.skip_c3:
+        line["c3_autotuned"] = bench_c3(sim, args)
     if not args.skip_cpu:
         line["cpu_baseline"] = bench_oracle(args, info["bytes_per_apply"], info["n_gates"])
     else:

@@ -146,7 +146,11 @@ qsv_status qsv_set_stream(qsv_ctx *ctx, void *hip_stream);
  * result to device tables (uploaded when ctx is non-NULL; ctx == NULL gives a
  * host-only plan usable with the introspection calls only).
  * k_local == 0 chooses k and the tile shape by timing candidates on the
- * device (autotuner, needs ctx).  tile may be NULL (default shape).
+ * device (autotuner, needs ctx; n_qubits above the default tile): k in
+ * {8, 10, 12} below the tile size, five tile shapes; each candidate's time is
+ * an evenly spaced sample of at most 8 of its partition sweeps on a scratch
+ * state (2^n x 8 bytes, freed afterwards) scaled to all partitions.  The
+ * choice is cached per device and circuit.  tile may be NULL (default shape).
  * The gate array is copied; it is not retained.  The plan is freed by
  * qsv_plan_destroy.
  * Batched plans (n_circuits > 1) keep each whole state on chip: 4 <= n <= 14.
@@ -216,8 +220,8 @@ qsv_status qsv_adjoint_grad(qsv_ctx *ctx, const qsv_plan *plan, const qsv_pauli_
 
 /* Candidates timed by the last autotuning run in this process (k_local == 0
  * on a context): writes up to cap records of 4 int32 (k, reg_qubits,
- * log_threads, microseconds for the whole circuit) and returns the number of
- * candidates. */
+ * log_threads, estimated microseconds for the whole circuit) and returns the
+ * number of candidates. */
 int32_t qsv_last_autotune(int32_t *out, int32_t cap);
 
 /* Time-stamped launch counters of the last call on ctx (for benchmarks):

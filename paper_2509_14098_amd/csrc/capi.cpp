@@ -373,15 +373,20 @@ static TuneChoice autotune(qsv_ctx *ctx, int n, const qsv_gate *gates, const std
         for (int k : {8, 10, 12}) {
             if (k >= t || k > n) continue;
             qsv_plan *P = make_plan(ctx, n, gates, off, flags, k, R, LW);
+            // time an evenly spaced sample of at most 8 partition sweeps (after one warm-up
+            // sweep) and scale it to the whole circuit
+            const int np = (int)P->parts.size(), ns = std::min(np, 8);
             float ms = 0;
-            for (int rep = 0; rep < 2; ++rep) {  // first run warms up
-                hip_check(hipEventRecord(e0, ctx->stream), "hipEventRecord");
-                for (int p = 0; p < (int)P->parts.size(); ++p)
-                    hip_check(launch_sweep(*P, P->R, P->LW, p, (float2 *)psi, nullptr, ctx->stream), "sweep");
-                hip_check(hipEventRecord(e1, ctx->stream), "hipEventRecord");
-                hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
-                hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            hip_check(launch_sweep(*P, P->R, P->LW, 0, (float2 *)psi, nullptr, ctx->stream), "sweep");
+            hip_check(hipEventRecord(e0, ctx->stream), "hipEventRecord");
+            for (int i = 0; i < ns; ++i) {
+                const int p = (int)(((int64_t)2 * i + 1) * np / (2 * ns));
+                hip_check(launch_sweep(*P, P->R, P->LW, p, (float2 *)psi, nullptr, ctx->stream), "sweep");
             }
+            hip_check(hipEventRecord(e1, ctx->stream), "hipEventRecord");
+            hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+            hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            ms *= (float)np / (float)ns;
             qsv_plan_destroy(P);
             g_last_tune.push_back(TuneChoice{k, R, LW, ms});
             if (best.ms < 0 || ms < best.ms) best = TuneChoice{k, R, LW, ms};
