@@ -47,7 +47,8 @@ __global__ __launch_bounds__(RED_THREADS) void expect_kernel(const DevGroup *__r
     const uint64_t stride = (uint64_t)gridDim.x * RED_THREADS;
     double acc = 0.0;
     if (G.x_mask == 0) {
-        // diagonal group: amplitudes read as 16-byte pairs, four pairs in flight per thread
+        // diagonal group: amplitudes read as 16-byte pairs, eight pairs in flight per
+        // thread, with non-temporal loads (the state is read once)
         auto weight = [&](uint64_t x) __attribute__((always_inline)) {
             double w = 0.0;
             for (int t = G.term_begin; t < G.term_end; ++t) w += terms[t].cre * parity_sign(x & terms[t].z_mask);
@@ -63,9 +64,14 @@ __global__ __launch_bounds__(RED_THREADS) void expect_kernel(const DevGroup *__r
             const uint64_t n2 = 1ull << (n - 1);
             const float4 *__restrict__ s4 = reinterpret_cast<const float4 *>(s);
             uint64_t i = (uint64_t)blockIdx.x * RED_THREADS + threadIdx.x;
-            for (; i + 3 * stride < n2; i += 4 * stride) {
-                const float4 v0 = s4[i], v1 = s4[i + stride], v2 = s4[i + 2 * stride], v3 = s4[i + 3 * stride];
-                acc += pair(i, v0) + pair(i + stride, v1) + pair(i + 2 * stride, v2) + pair(i + 3 * stride, v3);
+            for (; i + 7 * stride < n2; i += 8 * stride) {
+                typedef float nf4 __attribute__((ext_vector_type(4)));  // a vector type the builtin accepts
+                const nf4 *__restrict__ n4 = reinterpret_cast<const nf4 *>(s4);
+                nf4 v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = __builtin_nontemporal_load(n4 + i + u * stride);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc += pair(i + u * stride, float4{v[u].x, v[u].y, v[u].z, v[u].w});
             }
             for (; i < n2; i += stride) acc += pair(i, s4[i]);
         }
