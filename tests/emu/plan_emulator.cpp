@@ -50,6 +50,18 @@ static void run_part(const Plan &P, int pidx, std::vector<float2> &psi, const st
     }
 }
 
+// Op kinds executed by the emulator since the last reset (which op kinds the
+// test circuits exercise).
+static int64_t g_kind_counts[32];
+
+extern "C" void emu_kind_counts(int64_t *out, int reset)
+{
+    for (int i = 0; i < 32; ++i) {
+        out[i] = g_kind_counts[i];
+        if (reset) g_kind_counts[i] = 0;
+    }
+}
+
 // Build a plan with the given shape and run it on |0..0> (inverse = 0) or run
 // its conjugate transpose on the given state (inverse = 1).  Rotation
 // parameters are taken from theta (float64) the way the device forms them.
@@ -86,6 +98,7 @@ extern "C" int emu_run(int n, const qsv_gate *gates, int ng, const double *theta
         else if (g.kind == QSV_RZ) { m[0] = (float)c; m[1] = (float)-s; m[6] = (float)c; m[7] = (float)s; }
         else { m[0] = (float)c; m[1] = (float)-s; m[2] = (float)c; m[3] = (float)s; m[4] = (float)c; m[5] = (float)s; m[6] = (float)c; m[7] = (float)-s; }
     }
+    for (const DevOp &o : P.ops) g_kind_counts[o.kind & 31]++;
     std::vector<float2> psi(size_t(1) << n);
     std::memcpy(psi.data(), state, psi.size() * sizeof(float2));
     const int np = (int)P.parts.size();

@@ -28,6 +28,7 @@ def emu(tmp_path_factory):
     V = ctypes.c_void_p
     L.emu_run.argtypes = [ctypes.c_int, V, ctypes.c_int, V, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                           ctypes.c_int, ctypes.c_int, V]
+    L.emu_kind_counts.argtypes = [V, ctypes.c_int]
 
     def run(n, gates, k, R, LW, theta=None, flags=0, inverse=False, state=None):
         g = np.ascontiguousarray(gates)
@@ -40,6 +41,12 @@ def emu(tmp_path_factory):
         L.emu_run(n, g.ctypes.data_as(V), len(g), th.ctypes.data_as(V), 0 if theta is None else len(theta), k, R,
                   LW, flags, int(inverse), st.ctypes.data_as(V))
         return st
+
+    def kind_counts(reset=True):
+        out = np.zeros(32, dtype=np.int64)
+        L.emu_kind_counts(out.ctypes.data_as(V), int(reset))
+        return out
+    run.kind_counts = kind_counts
     return run
 
 
@@ -82,3 +89,25 @@ def test_gate_by_gate_plan(emu):
     n = 11
     gates = W.random_circuit(n, 80, seed=5)
     assert np.max(np.abs(emu(n, gates, 8, 4, 6, flags=1) - oracle.apply(n, gates))) < 1e-5
+
+
+# op kinds of the lowered plans (csrc/plan.h OpKind)
+OP_KINDS = dict(U1=1, R1=2, D1=3, CX=4, CU=5, CZ=6, D2=7, U2=8, SWAP=9, DREG=10, LAYER=11, CZ_RT=12, CZ_TT=13,
+                CX_T=14, D1_T=15)
+
+
+def test_every_op_kind_is_exercised(emu):
+    """The random circuits, fused and gate by gate, lower to every op kind the
+    kernels implement, so the emulation tests above cover each code path."""
+    emu.kind_counts(reset=True)
+    for R, LW in ((4, 8), (3, 6), (5, 8)):
+        for n in (9, 13):
+            theta = np.random.default_rng(n).uniform(-3, 3, size=4)
+            gates = W.random_circuit(n, 150, seed=70 + n + R, n_params=4)
+            ref = oracle.apply(n, gates, theta)
+            for flags in (0, 1):
+                out = emu(n, gates, min(n, R + LW - 1, 9), R, LW, theta, flags=flags)
+                assert np.max(np.abs(out - ref)) < 1e-5, (R, LW, n, flags)
+    counts = emu.kind_counts(reset=True)
+    missing = [k for k, v in OP_KINDS.items() if counts[v] == 0]
+    assert not missing, missing
