@@ -48,6 +48,10 @@ __device__ __forceinline__ void row_offsets(const DevPart *__restrict__ P, uint6
 // Load the tile HBM -> LDS.  Pair p covers canonical positions 2p, 2p+1 (an
 // aligned 16-byte pair in HBM, since tile position 0 is qubit 0).  A full
 // tile (t = R + LW) issues all of a thread's loads before the LDS writes.
+// Tiles that share no 128-byte line with another tile (every qubit below 4 is
+// a tile qubit) are read with non-temporal loads: nothing else will use those
+// lines.  Tiles that do share lines read through L2, where the neighbouring
+// tiles (same XCD, see xcd_tile) find them.
 template <int R, int LW>
 __device__ __forceinline__ void load_tile(const float2 *__restrict__ psi, float2 *lds, const DevPart *__restrict__ P,
                                           uint64_t base, uint32_t tid)
@@ -60,8 +64,17 @@ __device__ __forceinline__ void load_tile(const float2 *__restrict__ psi, float2
         uint64_t g[ITER];
         row_offsets<ITER, LW>(P, g);
         float4 v[ITER];
+        if (P->n_glb == 0 || P->gq[0] >= 4) {
+            typedef float nf4 __attribute__((ext_vector_type(4)));  // a vector type the builtin accepts
 #pragma unroll
-        for (int it = 0; it < ITER; ++it) v[it] = *reinterpret_cast<const float4 *>(psi + (gthr | g[it]));
+            for (int it = 0; it < ITER; ++it) {
+                const nf4 w = __builtin_nontemporal_load(reinterpret_cast<const nf4 *>(psi + (gthr | g[it])));
+                v[it] = float4{w.x, w.y, w.z, w.w};
+            }
+        } else {
+#pragma unroll
+            for (int it = 0; it < ITER; ++it) v[it] = *reinterpret_cast<const float4 *>(psi + (gthr | g[it]));
+        }
         const uint32_t st = swz(2u * tid);  // swz is linear and leaves bit 0 alone
 #pragma unroll
         for (int it = 0; it < ITER; ++it) {
@@ -103,8 +116,16 @@ __device__ __forceinline__ void store_tile(float2 *__restrict__ psi, float2 *__r
             const float2 x = lds[sc], y = lds[sc ^ 1u];
             v[it] = float4{x.x, x.y, y.x, y.y};
         }
+        if (P->n_glb == 0 || P->gq[0] >= 4) {  // no shared lines: non-temporal stores too
+            typedef float nf4 __attribute__((ext_vector_type(4)));
 #pragma unroll
-        for (int it = 0; it < ITER; ++it) *reinterpret_cast<float4 *>(psi + (gthr | g[it])) = v[it];
+            for (int it = 0; it < ITER; ++it)
+                __builtin_nontemporal_store(nf4{v[it].x, v[it].y, v[it].z, v[it].w},
+                                            reinterpret_cast<nf4 *>(psi + (gthr | g[it])));
+        } else {
+#pragma unroll
+            for (int it = 0; it < ITER; ++it) *reinterpret_cast<float4 *>(psi + (gthr | g[it])) = v[it];
+        }
         if (ckpt) {
 #pragma unroll
             for (int it = 0; it < ITER; ++it) *reinterpret_cast<float4 *>(ckpt + (gthr | g[it])) = v[it];
