@@ -5,8 +5,13 @@
 // are thread-id bits (lanes and waves); qubits outside the tile are bits of
 // the tile index.  A gate whose qubits that must be local (Section 4.2) are
 // register slots is applied entirely in registers; diagonal factors and
-// controls may sit anywhere and are evaluated per amplitude from a 32-bit
-// pattern: bit i of the pattern is the qubit's value for register index i.
+// controls may sit anywhere: on a register slot they select amplitudes by
+// register index, on a thread or tile-index qubit they are one value per
+// thread.  Every gate body updates the amplitudes in place (see fma_ip).
+//
+// The device code paths guarded by __HIP_DEVICE_COMPILE__ are the gfx950
+// instructions; the other branch is the same arithmetic in plain C++, used
+// only when the test emulator compiles this header for the host.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -18,20 +23,6 @@ namespace qsv {
 
 template <int J>
 using IC = std::integral_constant<int, J>;
-
-// Call f(IC<j>) for a runtime register slot j < R.
-template <int R, typename F>
-__device__ __forceinline__ void on_reg(int j, F &&f)
-{
-    switch (j) {
-    case 0: f(IC<0>{}); break;
-    case 1: if constexpr (R > 1) f(IC<1>{}); break;
-    case 2: if constexpr (R > 2) f(IC<2>{}); break;
-    case 3: if constexpr (R > 3) f(IC<3>{}); break;
-    case 4: if constexpr (R > 4) f(IC<4>{}); break;
-    default: break;
-    }
-}
 
 // A uniform value whose derivation the compiler cannot see.  Op dispatch tests
 // single bits of such values, so each op body becomes a two-way branch that
@@ -211,10 +202,6 @@ __device__ __forceinline__ void cmul_ip(float2 &a, float dr, float di)
     fma_ip(a.y, dr, u);
 }
 
-__device__ __forceinline__ float2 cmul(float2 a, C2 d)
-{
-    return float2{a.x * d.r - a.y * d.i, a.x * d.i + a.y * d.r};
-}
 
 // ---------------------------------------------------------------------------
 // Dense 2x2 on register slot J.  DAG applies the conjugate transpose.
