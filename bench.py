@@ -10,6 +10,9 @@ expectation) / step time, in GB/s.
 
 Side measurements (separate timed regions, not in `value`):
   * the same circuit gate by gate (one sweep per gate) -> fused speed-up;
+  * the 28-qubit QFT (diagonal-heavy), fused and gate by gate;
+  * the 32-qubit, 60-layer U3 + random-matching CX circuit with k and the tile
+    shape chosen by the autotuner, plus <sum Z_i Z_i+1>;
   * the 20-qubit RY.RZ + CX-ladder ansatz (400 parameters): adjoint gradient
     time / forward time;
   * 2048 x 14-qubit ansatz instances (depths 4..16): energy + gradient of all
@@ -208,6 +211,30 @@ def bench_batched(sim, args):
                 instances_per_s=round(B / dt, 1), register_stages=info["n_stages"], plan_seconds=round(plan_s, 3))
 
 
+def bench_qft(sim, args):
+    """28-qubit textbook QFT (28 H, 378 controlled phases, 14 SWAP): a
+    diagonal-heavy circuit, fused at k = 10 against gate by gate."""
+    n = 28
+    gates = W.qft(n)
+    psi = sim.zero_state(n)
+    res = dict(n_qubits=n, n_gates=int(len(gates)))
+    for flags, key in ((0, "fused"), (Q.PLAN_GATE_BY_GATE, "gate_by_gate")):
+        plan = sim.partition(n, gates, 10, flags, None)
+        sim.apply(plan, psi)
+        sync()
+        t0 = time.perf_counter()
+        sim.apply(plan, psi)
+        sync()
+        dt = time.perf_counter() - t0
+        sweeps = plan.info["n_partitions"]
+        res[key] = dict(ms=round(dt * 1e3, 2), sweeps=sweeps, gbs=round(16.0 * (1 << n) * sweeps / dt / 1e9, 1))
+        plan.close()
+    res["fused_speedup"] = round(res["gate_by_gate"]["ms"] / res["fused"]["ms"], 2)
+    del psi
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_c3(sim, args):
     """32-qubit local share (60 layers of U3 + random CX matchings): the
     autotuner chooses k and the tile shape, then one apply and <sum Z_i Z_i+1>."""
@@ -337,6 +364,8 @@ def main():
         line["adjoint"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in bench_gradient(sim, args).items()}
     if not args.skip_batched:
         line["batched"] = bench_batched(sim, args)
+    if not args.skip_gbg:
+        line["qft"] = bench_qft(sim, args)
     if not args.skip_c3:
         line["c3_autotuned"] = bench_c3(sim, args)
     if not args.skip_cpu:

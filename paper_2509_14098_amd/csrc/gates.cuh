@@ -368,6 +368,35 @@ __device__ __forceinline__ void g_d2(float2 (&a)[1 << R], const float *__restric
     }
 }
 
+// Diagonal 4x4 on register slot J (a) and a thread or tile-index qubit (b)
+// whose value here is bit: two factors per thread, picked by the slot's bit.
+template <int R, int J, bool DAG>
+__device__ __forceinline__ void g_d2_rt(float2 (&a)[1 << R], const float *__restrict__ m, uint32_t bit, bool lo_one)
+{
+    const C2 d0 = ld2(m, 0, DAG), d1 = ld2(m, 1, DAG), d2 = ld2(m, 2, DAG), d3 = ld2(m, 3, DAG);
+    const float hr = bit ? d3.r : d1.r, hi = bit ? d3.i : d1.i;  // slot bit 1
+#pragma unroll
+    for (int i = 0; i < (1 << R); ++i)
+        if ((i >> J) & 1) cmul_ipv(a[i], hr, hi);
+    if (!lo_one) {  // slot bit 0 (skipped for controlled phases, whose factors there are 1)
+        const float lr = bit ? d2.r : d0.r, li = bit ? d2.i : d0.i;
+#pragma unroll
+        for (int i = 0; i < (1 << R); ++i)
+            if (!((i >> J) & 1)) cmul_ipv(a[i], lr, li);
+    }
+}
+
+// Diagonal 4x4 on two thread or tile-index qubits: one factor per thread.
+template <int R, bool DAG>
+__device__ __forceinline__ void g_d2_tt(float2 (&a)[1 << R], const float *__restrict__ m, uint32_t j)
+{
+    const C2 d0 = ld2(m, 0, DAG), d1 = ld2(m, 1, DAG), d2 = ld2(m, 2, DAG), d3 = ld2(m, 3, DAG);
+    const float r = j == 0 ? d0.r : j == 1 ? d1.r : j == 2 ? d2.r : d3.r;
+    const float im = j == 0 ? d0.i : j == 1 ? d1.i : j == 2 ? d2.i : d3.i;
+#pragma unroll
+    for (int i = 0; i < (1 << R); ++i) cmul_ipv(a[i], r, im);
+}
+
 // X on register slot J controlled by register slot C: a fixed permutation.
 template <int R, int C, int J>
 __device__ __forceinline__ void g_cx_reg(float2 (&a)[1 << R])
@@ -482,7 +511,8 @@ __device__ __forceinline__ void apply_ops(const DevOp &o, const float *__restric
     }
     // the kinds that fused stages use least are tested only when one of them is present
     constexpr uint32_t RARE = (1u << OP_U1) | (1u << OP_R1) | (1u << OP_CZ) | (1u << OP_D1) | (1u << OP_D1_T) |
-                              (1u << OP_D2) | (1u << OP_CU) | (1u << OP_U2) | (1u << OP_SWAP);
+                              (1u << OP_D2) | (1u << OP_D2_RT) | (1u << OP_D2_TT) | (1u << OP_CU) | (1u << OP_U2) |
+                              (1u << OP_SWAP);
     if (!(kb & RARE)) return;
     const M8 mm = load_m8(pool, o.mat);  // the 8 leading matrix floats, one scalar load
     const float *m = mm.v;
@@ -503,6 +533,15 @@ __device__ __forceinline__ void apply_ops(const DevOp &o, const float *__restric
     if (kb & (1u << OP_D2)) {
         const uint32_t pa = loc_pattern(o.a, tid, base), pb = loc_pattern(o.b, tid, base);
         (g_d2<R, DAG>(as, m, pa, pb), ...);
+    }
+    if (kb & (1u << OP_D2_RT)) {
+        const uint32_t bit = lane_bit(o.b, tid, base);
+        const bool lo_one = o.flags & 1;
+        on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { (g_d2_rt<R, QSV_J(J), DAG>(as, m, bit, lo_one), ...); });
+    }
+    if (kb & (1u << OP_D2_TT)) {
+        const uint32_t j = lane_bit(o.a, tid, base) + 2u * lane_bit(o.b, tid, base);
+        (g_d2_tt<R, DAG>(as, m, j), ...);
     }
     if (kb & (1u << OP_CU)) {
         const uint32_t pc = loc_pattern(o.a, tid, base);

@@ -34,6 +34,8 @@ enum OpKind : uint8_t {
     OP_CZ_TT = 13, // CZ between two thread or tile-index qubits
     OP_CX_T = 14,  // CX with a thread or tile-index control a, target register slot b
     OP_D1_T = 15,  // diagonal 2x2 on a thread or tile-index qubit
+    OP_D2_RT = 16, // diagonal 4x4 on register slot a and thread or tile-index qubit b
+    OP_D2_TT = 17, // diagonal 4x4 on two thread or tile-index qubits
 };
 
 // Location of a qubit in a stage layout: register slot, thread-id bit, or a
@@ -55,7 +57,7 @@ struct DevOp {            // 32 bytes
     int32_t mat;          // float offset of the gate matrix in the matrix pool
     int32_t grad_slot;    // slot of this gate's gradient partial, -1 if none
     int32_t gate;         // gate index in the circuit
-    int32_t pad;
+    int32_t flags;        // OP_D2_RT: 1 if the entries with slot bit 0 are exactly 1 (only bit-1 amplitudes change)
 };
 
 constexpr int MAX_R = 5;       // register qubits per thread (2^5 amplitudes)

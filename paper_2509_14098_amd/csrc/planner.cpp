@@ -510,6 +510,24 @@ struct StageLowering {
             o.kind = OP_CX_T;
         } else if (m.op == OP_D1 && !is_reg(o.a)) {
             o.kind = OP_D1_T;
+        } else if (m.op == OP_D2 && !(is_reg(o.a) && is_reg(o.b))) {
+            if (!is_reg(o.a) && !is_reg(o.b)) {
+                o.kind = OP_D2_TT;
+            } else {
+                o.kind = OP_D2_RT;
+                if (!is_reg(o.a)) {  // the register qubit goes first: entries j = 1 and 2 trade places
+                    std::swap(o.a, o.b);
+                    const float *d = &P.pool[o.mat];
+                    if (d[2] != d[4] || d[3] != d[5]) {
+                        if (m.param) throw std::logic_error("parameterised diagonal 4x4 must be symmetric");
+                        const float e[8] = {d[0], d[1], d[4], d[5], d[2], d[3], d[6], d[7]};
+                        o.mat = (int32_t)P.pool.size();
+                        P.pool.insert(P.pool.end(), e, e + 8);
+                    }
+                }
+                const float *d = &P.pool[o.mat];  // entries with the register bit 0: j = 0 and 2
+                if (!m.param && d[0] == 1.f && d[1] == 0.f && d[4] == 1.f && d[5] == 0.f) o.flags = 1;
+            }
         }
         add(o, m.flops);
     }
@@ -650,7 +668,7 @@ double op_cost(int kind)
 {
     switch (kind) {
     case OP_U1: return 8;
-    case OP_R1: case OP_D1: case OP_D1_T: case OP_D2: case OP_DREG: return 4;
+    case OP_R1: case OP_D1: case OP_D1_T: case OP_D2: case OP_D2_RT: case OP_D2_TT: case OP_DREG: return 4;
     case OP_LAYER: return 4;  // per rotation or diagonal; op_cost_of() counts them
     case OP_CU: return 9;
     case OP_U2: return 16;

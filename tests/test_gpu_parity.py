@@ -111,6 +111,23 @@ def test_every_gate_kind_in_every_position(sim, n):
         assert_close(psi.cpu().numpy(), ref)
 
 
+@pytest.mark.parametrize("n,k", [(12, 8), (20, 10), (24, 10)])
+def test_qft_of_basis_state_closed_form(sim, n, k):
+    """Diagonal-heavy workload: the QFT of a basis state |x> against its closed
+    form, fused and gate by gate (controlled phases are not counted against k,
+    so partitions are long)."""
+    N = 1 << n
+    x = (5 * N) // 7
+    ref = np.exp(2j * np.pi * x * np.arange(N) / N) / np.sqrt(N)
+    for flags in (0, Q.PLAN_GATE_BY_GATE):
+        psi = torch.zeros(N, dtype=torch.complex64, device="cuda")
+        psi[x] = 1
+        out, info = run(sim, n, W.qft(n), k=k, flags=flags, psi=psi)
+        assert_close(out.cpu().numpy(), ref)
+        if flags == 0 and n == 20:
+            assert info["n_partitions"] < len(W.qft(n)) // 10
+
+
 # ---------------------------------------------------------------- benchmark workloads
 
 def test_c1_full(sim):

@@ -49,10 +49,10 @@ def test_worked_example_ghz3():
 
 
 @pytest.mark.parametrize("name,n,k", [("c1", 12, 6), ("c1", 12, 8), ("c2", 28, 10), ("c3", 32, 8), ("c3", 32, 10),
-                                      ("c3", 32, 12), ("c4", 20, 10)])
+                                      ("c3", 32, 12), ("c4", 20, 10), ("qft", 28, 10), ("qft", 20, 6)])
 def test_partition_matches_oracle_on_workloads(name, n, k):
     gates = {"c1": W.brickwork_c1, "c2": W.brickwork_c2, "c3": W.brickwork_c3,
-             "c4": lambda: W.ansatz(20, 10)[0]}[name]()
+             "c4": lambda: W.ansatz(20, 10)[0], "qft": lambda: W.qft(n)}[name]()
     tile = (5, 8) if k < 13 else (5, 9)
     plan = _compare(n, gates, k, tile=tile)
     info = Q.qsv_plan_info(plan)

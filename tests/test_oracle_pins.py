@@ -314,3 +314,18 @@ def test_central_fd_matches_sinc_bias():
         tm[j] -= h
         fd = (_energy(n, gates, tp, H) - _energy(n, gates, tm, H)) / (2 * h)
         assert abs(fd - grad[j] * np.sin(h) / h) < 1e-10
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 9])
+def test_qft_of_basis_states_closed_form(n):
+    """The textbook QFT circuit (H, controlled phases, SWAPs) maps |x> to
+    2^(-n/2) sum_y exp(2 pi i x y / 2^n) |y>: pins the oracle's H, CP and SWAP
+    at many angles and the workload generator's bit order."""
+    N = 1 << n
+    gates = W.qft(n)
+    for x in sorted({0, 1, N - 1, N // 3}):
+        psi = np.zeros(N, complex)
+        psi[x] = 1
+        out = oracle.apply(n, gates, None, psi)
+        ref = np.exp(2j * np.pi * x * np.arange(N) / N) / np.sqrt(N)
+        assert np.max(np.abs(out - ref)) < 1e-12, x

@@ -67,7 +67,8 @@ def test_random_circuits_every_shape(emu, R, LW):
 
 @pytest.mark.parametrize("name,n,gen", [("c1", 12, W.brickwork_c1),
                                         ("c2-16", 16, lambda: W.brickwork_c2(n=16, layers=12)),
-                                        ("c3-16", 16, lambda: W.brickwork_c3(n=16, layers=12))])
+                                        ("c3-16", 16, lambda: W.brickwork_c3(n=16, layers=12)),
+                                        ("qft-15", 15, lambda: W.qft(15))])
 def test_benchmark_shapes(emu, name, n, gen):
     gates = gen()
     ref = oracle.apply(n, gates)
@@ -93,7 +94,7 @@ def test_gate_by_gate_plan(emu):
 
 # op kinds of the lowered plans (csrc/plan.h OpKind)
 OP_KINDS = dict(U1=1, R1=2, D1=3, CX=4, CU=5, CZ=6, D2=7, U2=8, SWAP=9, DREG=10, LAYER=11, CZ_RT=12, CZ_TT=13,
-                CX_T=14, D1_T=15)
+                CX_T=14, D1_T=15, D2_RT=16, D2_TT=17)
 
 
 def test_every_op_kind_is_exercised(emu):

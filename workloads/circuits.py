@@ -98,6 +98,24 @@ def u3_layer(n: int, seed: int):
     return make_gates([("U3", (q,), tuple(ang[q])) for q in range(n)]), ang
 
 
+def qft(n: int) -> np.ndarray:
+    """Quantum Fourier transform from its textbook circuit, for the bit order
+    used here (qubit q is bit q of the index): qubits from the highest down,
+    each gets H and then controlled phases 2 pi / 2^(d+1) from every lower
+    qubit at distance d; finally the qubit order is reversed with SWAPs.  It
+    maps |x> to 2^(-n/2) sum_y exp(2 pi i x y / 2^n) |y>.  A diagonal-heavy
+    workload: n(n-1)/2 of its gates are controlled phases, which the
+    partitioner does not count against k."""
+    specs = []
+    for j in range(n - 1, -1, -1):
+        specs.append(("H", (j,)))
+        for m in range(j - 1, -1, -1):
+            specs.append(("CP", (m, j), (np.pi / 2 ** (j - m),)))
+    for i in range(n // 2):
+        specs.append(("SWAP", (i, n - 1 - i)))
+    return make_gates(specs)
+
+
 # ---------------------------------------------------------------- benchmark workloads
 
 def brickwork_c1(n: int = 12, layers: int = 20, seed: int = 1) -> np.ndarray:
