@@ -11,6 +11,8 @@ expectation) / step time, in GB/s.
 Side measurements (separate timed regions, not in `value`):
   * the same circuit gate by gate (one sweep per gate) -> fused speed-up;
   * the 28-qubit QFT (diagonal-heavy), fused and gate by gate;
+  * the headline circuit with the distributed level (4 and 16 emulated ranks,
+    remaps as SWAP sweeps);
   * the 32-qubit, 60-layer U3 + random-matching CX circuit with k and the tile
     shape chosen by the autotuner, plus <sum Z_i Z_i+1>;
   * the 20-qubit RY.RZ + CX-ladder ansatz (400 parameters): adjoint gradient
@@ -235,6 +237,34 @@ def bench_qft(sim, args):
     return res
 
 
+def bench_distributed(sim, args):
+    """The headline circuit with the distributed level: 2^g emulated ranks of
+    2^(28-g) amplitudes, remaps between distributed partitions done as SWAP
+    sweeps on this GPU, against the plain plan (same k)."""
+    n = 28
+    gates = W.brickwork_c2()
+    psi = sim.zero_state(n)
+    res = {}
+    for g in (2, 4):
+        plan = sim.partition_distributed(n, gates, g, args.k)
+        di = Q.qsv_plan_distributed_info(plan.handle)
+        parts = plan.partitions()
+        remap_sweeps = sum(1 for _, gl in parts if gl and gl[0] < 0)
+        sim.apply(plan, psi)
+        sync()
+        t0 = time.perf_counter()
+        sim.apply(plan, psi)
+        sync()
+        dt = time.perf_counter() - t0
+        res[f"g{g}"] = dict(ranks=1 << g, dist_partitions=di["n_dist_partitions"], exchange_swaps=di["exchange_swaps"],
+                            remap_swaps=di["remap_swaps"], sweeps=plan.info["n_partitions"], remap_sweeps=remap_sweeps,
+                            ms=round(dt * 1e3, 2))
+        plan.close()
+    del psi
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_c3(sim, args):
     """32-qubit local share (60 layers of U3 + random CX matchings): the
     autotuner chooses k and the tile shape, then one apply and <sum Z_i Z_i+1>."""
@@ -366,6 +396,7 @@ def main():
         line["batched"] = bench_batched(sim, args)
     if not args.skip_gbg:
         line["qft"] = bench_qft(sim, args)
+        line["distributed"] = bench_distributed(sim, args)
     if not args.skip_c3:
         line["c3_autotuned"] = bench_c3(sim, args)
     if not args.skip_cpu:

@@ -111,7 +111,7 @@ typedef struct qsv_plan_info {
     int32_t tile_qubits;     /* qubits per on-chip tile */
     int32_t reg_qubits;
     int32_t log_threads;
-    int64_t n_gates;
+    int64_t n_gates;         /* gates in the plan (distributed plans: with the remap SWAPs) */
     int64_t n_params;        /* total theta entries over all circuits */
     int64_t n_partitions;    /* total over circuits */
     int64_t n_stages;        /* register-level stages, total */
@@ -171,7 +171,40 @@ qsv_status qsv_plan_params(const qsv_plan *plan, int32_t circuit, int64_t *offse
  * indices in execution order (at most cap written; *n_gates = the count).
  * level 0 = the partition level, level 1 = the register stages of all
  * partitions of circuit c in order (local_mask = the stage's register qubits).
+ * Distributed plans: level -1 = the distributed partitions (local_mask = the
+ * n - n_global logical qubits local to every rank); at levels 0 and 1 the
+ * masks are physical bit positions and a remap SWAP's gate index is -1.
  */
+/*
+ * Distributed level (Section 4.2 with the memory of one rank as the local
+ * size, Section 4.3's data reshaping between partitions), emulated on one
+ * GPU.  2^n_global ranks each own the 2^(n - n_global) amplitudes whose
+ * n_global highest bit positions equal the rank.  The greedy of
+ * qsv_partition cuts the circuit (gates[0..n_gates), one circuit) into
+ * distributed partitions of at most n - n_global local qubits; the local set
+ * is padded with qubits that are already local.  Each distributed partition
+ * runs with its local qubits at the low positions (tiles of k local qubits as
+ * in qsv_partition, never spanning ranks).  Between partitions every qubit
+ * that becomes local trades positions with one that stops being local: one
+ * SWAP of a low and a high position, the exchange between the ranks that
+ * differ in that high bit.  On one GPU these SWAPs run as sweeps of the same
+ * kernels; a final set of SWAPs restores the logical order, so qsv_apply,
+ * qsv_expect and qsv_adjoint_grad see the state in logical order.
+ * k_local == 0 gives the default k; tile as in qsv_partition.
+ * Errors: QSV_E_ARG (n_global < 1, fewer than tile-size qubits left local,
+ * invalid gates, k_local not below the tile size), QSV_E_RANGE,
+ * QSV_E_UNSUPPORTED (gradient plans with tiles over 13 qubits), QSV_E_NOMEM,
+ * QSV_E_DEVICE.
+ */
+qsv_status qsv_partition_distributed(qsv_ctx *ctx, int32_t n_qubits, const qsv_gate *gates, int64_t n_gates,
+                                     int32_t n_global, int32_t k_local, uint32_t flags, const qsv_tile_config *tile,
+                                     qsv_plan **out);
+/* Distributed level of a plan: n_global (0 for other plans), the number of
+ * distributed partitions, the remap SWAPs that move data between ranks (one
+ * low and one high position) and all remap SWAPs (with the final return to
+ * logical order). */
+qsv_status qsv_plan_distributed_info(const qsv_plan *plan, int32_t *n_global, int64_t *n_dist_partitions,
+                                     int64_t *exchange_swaps, int64_t *remap_swaps);
 qsv_status qsv_plan_partition(const qsv_plan *plan, int32_t circuit, int32_t level, int64_t p,
                               uint64_t *local_mask, int32_t *gates, int64_t cap, int64_t *n_gates);
 

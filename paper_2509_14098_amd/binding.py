@@ -48,7 +48,8 @@ class _PlanInfo(ctypes.Structure):
 _lib = None
 EXPORTS = ["qsv_last_error", "qsv_create", "qsv_destroy", "qsv_set_stream", "qsv_partition", "qsv_plan_destroy",
            "qsv_plan_get_info", "qsv_plan_params", "qsv_plan_partition", "qsv_apply", "qsv_expect",
-           "qsv_adjoint_grad", "qsv_set_timing", "qsv_last_sweep_ms", "qsv_last_autotune"]
+           "qsv_adjoint_grad", "qsv_set_timing", "qsv_last_sweep_ms", "qsv_last_autotune",
+           "qsv_partition_distributed", "qsv_plan_distributed_info"]
 
 
 def library_path() -> str:
@@ -73,6 +74,8 @@ def load_library():
         "qsv_apply": [V, V, V, V, V], "qsv_expect": [V, V, I32, I32, I64, V, V],
         "qsv_adjoint_grad": [V, V, V, I32, V, V, V, V, V],
         "qsv_set_timing": [V, I32], "qsv_last_sweep_ms": [V, V, V], "qsv_last_autotune": [V, I32],
+        "qsv_partition_distributed": [V, I32, V, I64, I32, I32, U32, V, V],
+        "qsv_plan_distributed_info": [V, V, V, V, V],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -141,6 +144,26 @@ def qsv_partition(ctx, n_qubits: int, gates, circ_offsets=None, k_local: int = 0
                                          off.ctypes.data_as(ctypes.c_void_p), len(off) - 1, k_local, flags,
                                          ctypes.byref(tc), ctypes.byref(h)))
     return h
+
+
+def qsv_partition_distributed(ctx, n_qubits: int, gates, n_global: int, k_local: int = 0, flags: int = 0, tile=None):
+    """Distributed-level plan of one circuit for 2^n_global emulated ranks."""
+    g = np.ascontiguousarray(gates)
+    if g.dtype.itemsize != GATE_DTYPE.itemsize:
+        raise QsvError(-1, "gate records must have the qsv_gate layout")
+    tc = _TileConfig(*(tile or (0, 0)))
+    h = ctypes.c_void_p()
+    _check(load_library().qsv_partition_distributed(ctx, n_qubits, g.ctypes.data_as(ctypes.c_void_p) if len(g) else None,
+                                                    len(g), n_global, k_local, flags, ctypes.byref(tc),
+                                                    ctypes.byref(h)))
+    return h
+
+
+def qsv_plan_distributed_info(plan) -> dict:
+    ng, nd, ex, rs = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(load_library().qsv_plan_distributed_info(plan, ctypes.byref(ng), ctypes.byref(nd), ctypes.byref(ex),
+                                                    ctypes.byref(rs)))
+    return dict(n_global=ng.value, n_dist_partitions=nd.value, exchange_swaps=ex.value, remap_swaps=rs.value)
 
 
 def qsv_last_autotune():

@@ -271,7 +271,7 @@ qsv_status qsv_last_sweep_ms(qsv_ctx *ctx, double *total_ms, int64_t *n_launches
 
 // Build (and, with a context, upload) a plan for validated input.
 static qsv_plan *make_plan(qsv_ctx *ctx, int n_qubits, const qsv_gate *gates, const std::vector<int64_t> &off,
-                           uint32_t flags, int k, int R, int LW)
+                           uint32_t flags, int k, int R, int LW, int n_global = 0)
 {
     const int n_circuits = (int)off.size() - 1;
     auto P = new qsv_plan();
@@ -290,12 +290,19 @@ static qsv_plan *make_plan(qsv_ctx *ctx, int n_qubits, const qsv_gate *gates, co
         choose_shape(n_qubits, std::max(R, std::min(need_r, n_qubits)), LW, P->R, P->LW, P->t);
     }
     P->k = std::min(k, n_qubits);
-    P->gates.assign(gates, gates + off[n_circuits]);
+    std::vector<int64_t> offs = off;
+    if (n_global > 0) {  // one circuit: its physical gate list (relabelled, with remap SWAPs)
+        P->n_global = n_global;
+        distribute(*P, gates, off[1], n_global);
+        offs = {0, (int64_t)P->gates.size()};
+    } else {
+        P->gates.assign(gates, gates + off[n_circuits]);
+    }
     int64_t theta_off = 0;
     for (int c = 0; c < n_circuits; ++c) {
         CircuitPlan C;
-        C.g0 = off[c];
-        C.g1 = off[c + 1];
+        C.g0 = offs[c];
+        C.g1 = offs[c + 1];
         int64_t np = 0;
         for (int64_t g = C.g0; g < C.g1; ++g) np = std::max<int64_t>(np, (int64_t)P->gates[g].param + 1);
         C.theta_off = theta_off;
@@ -539,6 +546,15 @@ qsv_status qsv_plan_partition(const qsv_plan *plan, int32_t circuit, int32_t lev
         if (circuit < 0 || circuit >= plan->n_circuits) fail(QSV_E_ARG, "circuit out of range");
         const CircuitPlan &C = plan->circ[circuit];
         const Part *part = nullptr;
+        if (level == -1) {  // distributed partitions: logical local set and logical gate indices
+            if (plan->n_global == 0) fail(QSV_E_ARG, "level -1 needs a distributed plan");
+            if (p < 0 || p >= (int64_t)plan->dist_parts.size()) fail(QSV_E_ARG, "partition out of range");
+            const Part &dp = plan->dist_parts[p];
+            *local_mask = dp.S;
+            *n_gates = (int64_t)dp.gates.size();
+            for (int64_t i = 0; gates && i < std::min<int64_t>(cap, *n_gates); ++i) gates[i] = (int32_t)dp.gates[i];
+            return;
+        }
         if (level == 0) {
             if (p < 0 || p >= (int64_t)C.parts.size()) fail(QSV_E_ARG, "partition out of range");
             part = &C.parts[p];
@@ -550,12 +566,62 @@ qsv_status qsv_plan_partition(const qsv_plan *plan, int32_t circuit, int32_t lev
             }
             if (!part || p < 0) fail(QSV_E_ARG, "stage out of range");
         } else {
-            fail(QSV_E_ARG, "level must be 0 or 1");
+            fail(QSV_E_ARG, "level must be -1, 0 or 1");
         }
         *local_mask = part->S;
         *n_gates = (int64_t)part->gates.size();
-        for (int64_t i = 0; gates && i < std::min<int64_t>(cap, *n_gates); ++i)
-            gates[i] = (int32_t)(part->gates[i] - C.g0);
+        for (int64_t i = 0; gates && i < std::min<int64_t>(cap, *n_gates); ++i) {
+            const int64_t g = part->gates[i] - C.g0;
+            gates[i] = (int32_t)(plan->n_global ? plan->phys_logical[g] : g);
+        }
+    });
+}
+
+qsv_status qsv_partition_distributed(qsv_ctx *ctx, int32_t n_qubits, const qsv_gate *gates, int64_t n_gates,
+                                     int32_t n_global, int32_t k_local, uint32_t flags, const qsv_tile_config *tile,
+                                     qsv_plan **out)
+{
+    return guarded([&] {
+        auto t0 = std::chrono::steady_clock::now();
+        if (!out) fail(QSV_E_ARG, "out is null");
+        if (n_qubits < 2 || n_qubits > 34) fail(QSV_E_ARG, "n_qubits must be in [2, 34]");
+        if (n_gates < 0 || (n_gates > 0 && !gates)) fail(QSV_E_ARG, "bad gate array");
+        if (flags & ~(QSV_PLAN_GATE_BY_GATE | QSV_PLAN_GRAD)) fail(QSV_E_ARG, "unknown flag");
+        for (int64_t g = 0; g < n_gates; ++g) {
+            std::string e = validate_gate(gates[g], n_qubits, 0);
+            if (!e.empty()) {
+                bool range = e.find("param") != std::string::npos;
+                fail(range ? QSV_E_RANGE : QSV_E_ARG, "gate " + std::to_string(g) + ": " + e);
+            }
+        }
+        int R = 4, LW = 8;
+        if (tile && (tile->reg_qubits || tile->log_threads)) {
+            R = tile->reg_qubits;
+            LW = tile->log_threads;
+            if (!kernel_shape_supported(R, LW)) fail(QSV_E_ARG, "unsupported tile shape");
+        }
+        if ((flags & QSV_PLAN_GRAD) && R + LW > 13) fail(QSV_E_UNSUPPORTED, "gradient plans need a tile of at most 13 qubits");
+        if (n_global < 1 || n_qubits - n_global < R + LW)
+            fail(QSV_E_ARG, "n_global must be >= 1 and leave at least a tile (" + std::to_string(R + LW) +
+                                " qubits) local to each rank");
+        const int k = k_local == 0 ? R + LW - 3 : k_local;
+        if (k >= R + LW) fail(QSV_E_ARG, "k_local must be below the tile size");
+        const std::vector<int64_t> off = {0, n_gates};
+        qsv_plan *P = make_plan(ctx, n_qubits, gates, off, flags, k, R, LW, n_global);
+        P->plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        *out = P;
+    });
+}
+
+qsv_status qsv_plan_distributed_info(const qsv_plan *plan, int32_t *n_global, int64_t *n_dist_partitions,
+                                     int64_t *exchange_swaps, int64_t *remap_swaps)
+{
+    return guarded([&] {
+        if (!plan || !n_global || !n_dist_partitions || !exchange_swaps || !remap_swaps) fail(QSV_E_ARG, "null argument");
+        *n_global = plan->n_global;
+        *n_dist_partitions = (int64_t)plan->dist_parts.size();
+        *exchange_swaps = plan->remap_exchange_swaps;
+        *remap_swaps = plan->remap_swaps;
     });
 }
 

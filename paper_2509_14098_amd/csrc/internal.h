@@ -39,6 +39,16 @@ struct CircuitPlan {
     int32_t part_begin = 0;           // index of its first DevPart
 };
 
+// A run of the plan's gate list partitioned on its own at the tile level:
+// the gates of one distributed partition (qubits relabelled to physical bit
+// positions, tiles restricted to the rank-local positions in allowed) or the
+// SWAPs of one remap between distributed partitions (any positions).
+struct Segment {
+    int64_t g0 = 0, g1 = 0;
+    uint64_t allowed = ~0ull;
+    bool remap = false;
+};
+
 struct ParamGate {                    // a rotation whose matrix is formed from theta on the device
     int32_t mat;                      // pool offset
     int32_t kind;
@@ -65,6 +75,13 @@ struct Plan {
     std::vector<int32_t> param_off, param_slots;  // theta index -> its grad slots (CSR, slot order)
     // batched plans: per-circuit stage ranges (single tile per circuit)
     std::vector<int32_t> batch_order; // circuits sorted by decreasing op count
+    // distributed plans (n_global > 0): the circuit's level above the tile
+    int n_global = 0;
+    std::vector<Part> dist_parts;     // distributed partitions: local set (logical qubits) and logical gates
+    std::vector<Segment> segments;    // how the physical gate list is cut at the tile level
+    std::vector<int64_t> phys_logical;  // physical gate -> logical gate index, -1 for a remap SWAP
+    int64_t remap_exchange_swaps = 0; // remap SWAPs between a rank-local and a global position
+    int64_t remap_swaps = 0;          // all remap SWAPs (including the final return to logical order)
 
     // device copies (null for host-only plans)
     int device = -1;
@@ -88,5 +105,9 @@ GateMeta classify(const qsv_gate &g);
 std::vector<Part> greedy_partition(int n, const std::vector<GateMeta> &meta, const std::vector<int> &sub, int k,
                                    uint64_t allowed);
 void build_plan(Plan &plan);
+// Distributed level: sets plan.gates to the physical gate list of the logical
+// circuit gates[0..G) for 2^n_global ranks (plan.n set), and the segments,
+// distributed partitions and gate map.
+void distribute(Plan &plan, const qsv_gate *gates, int64_t G, int n_global);
 
 }  // namespace qsv

@@ -678,6 +678,91 @@ double op_cost(int kind)
 
 }  // namespace
 
+// Distributed level (Section 4.2 applied to the memory of one rank, Section
+// 4.3's data reshaping between partitions).  2^g ranks each hold the 2^(n-g)
+// amplitudes whose g highest bit positions equal the rank.  The greedy cuts
+// the circuit into partitions of at most n - g local qubits; each partition
+// runs with its local qubits at the low n - g positions.  Between partitions
+// the qubits that become local trade positions with qubits that stop being
+// local: each trade is a SWAP of a low and a high position, i.e. the
+// exchange between ranks that differ in that high bit.  On one GPU the SWAPs
+// run as ordinary gates; a last set of SWAPs restores the logical order.
+void distribute(Plan &P, const qsv_gate *gates, int64_t G, int g)
+{
+    const int n = P.n, L = n - g;
+    std::vector<GateMeta> meta((size_t)G);
+    std::vector<int> all((size_t)G);
+    for (int64_t i = 0; i < G; ++i) {
+        meta[i] = classify(gates[i]);
+        all[i] = (int)i;
+    }
+    P.dist_parts = greedy_partition(n, meta, all, L, ~0ull);
+    if (P.dist_parts.empty()) P.dist_parts.push_back(Part());
+    std::vector<int> pos(n), at(n);  // logical qubit -> position, position -> logical qubit
+    for (int q = 0; q < n; ++q) pos[q] = at[q] = q;
+    P.gates.clear();
+    P.phys_logical.clear();
+    P.segments.clear();
+    P.remap_exchange_swaps = P.remap_swaps = 0;
+    auto swap_positions = [&](int pa, int pb) {
+        qsv_gate s;
+        std::memset(&s, 0, sizeof(s));
+        s.kind = QSV_SWAP;
+        s.q0 = pa;
+        s.q1 = pb;
+        s.param = -1;
+        P.gates.push_back(s);
+        P.phys_logical.push_back(-1);
+        std::swap(at[pa], at[pb]);
+        pos[at[pa]] = pa;
+        pos[at[pb]] = pb;
+        ++P.remap_swaps;
+        if ((pa < L) != (pb < L)) ++P.remap_exchange_swaps;
+    };
+    auto open_segment = [&](bool remap, uint64_t allowed) {
+        Segment sg;
+        sg.g0 = sg.g1 = (int64_t)P.gates.size();
+        sg.remap = remap;
+        sg.allowed = allowed;
+        P.segments.push_back(sg);
+    };
+    auto close_segment = [&]() {
+        P.segments.back().g1 = (int64_t)P.gates.size();
+        if (P.segments.back().g1 == P.segments.back().g0) P.segments.pop_back();
+    };
+    const uint64_t low = L >= 64 ? ~0ull : (1ull << L) - 1;
+    for (Part &part : P.dist_parts) {
+        // pad the local set to n - g qubits with qubits that are already local (no data moves)
+        uint64_t S = part.S;
+        for (int p = 0; p < L && popc(S) < L; ++p) S |= 1ull << at[p];
+        part.S = S;
+        // remap: each qubit entering the local set (at a high position) trades
+        // places with one leaving it (at a low position)
+        std::vector<int> enter, leave;
+        for (int p = L; p < n; ++p)
+            if ((S >> at[p]) & 1) enter.push_back(p);
+        for (int p = 0; p < L; ++p)
+            if (!((S >> at[p]) & 1)) leave.push_back(p);
+        if (enter.size() != leave.size()) throw std::logic_error("distributed local set has the wrong size");
+        open_segment(true, ~0ull);
+        for (size_t j = 0; j < enter.size(); ++j) swap_positions(leave[j], enter[j]);
+        close_segment();
+        open_segment(false, low);
+        for (int gi : part.gates) {
+            qsv_gate x = gates[gi];
+            x.q0 = pos[x.q0];
+            if (x.q1 >= 0) x.q1 = pos[x.q1];
+            P.gates.push_back(x);
+            P.phys_logical.push_back(gi);
+        }
+        close_segment();
+    }
+    open_segment(true, ~0ull);  // back to the logical order
+    for (int p = 0; p < n; ++p)
+        if (at[p] != p) swap_positions(p, pos[p]);
+    close_segment();
+}
+
 void build_plan(Plan &P)
 {
     const int n = P.n;
@@ -721,16 +806,29 @@ void build_plan(Plan &P)
         const int R = std::min(P.R, t);
         const int w = t - R;
         const int k = std::min(P.k, n);
-        // level 1: partitions of at most k local qubits (padded to min(k, n))
-        if (P.flags & QSV_PLAN_GATE_BY_GATE) {
-            for (int g : all) {
-                Part p;
-                p.S = P.meta[g].qmask;
-                p.gates.push_back(g);
-                C.parts.push_back(p);
+        // level 1: partitions of at most k local qubits (padded to min(k, n)); a
+        // distributed plan partitions each of its segments on its own
+        std::vector<Segment> segs = P.segments;
+        if (segs.empty()) {
+            Segment whole;
+            whole.g0 = C.g0;
+            whole.g1 = C.g1;
+            segs.push_back(whole);
+        }
+        for (const Segment &sg : segs) {
+            std::vector<int> sub;
+            for (int64_t g = sg.g0; g < sg.g1; ++g) sub.push_back((int)g);
+            if (P.flags & QSV_PLAN_GATE_BY_GATE) {
+                for (int g : sub) {
+                    Part p;
+                    p.S = P.meta[g].qmask;
+                    p.gates.push_back(g);
+                    C.parts.push_back(p);
+                }
+            } else {
+                std::vector<Part> ps = greedy_partition(n, P.meta, sub, k, sg.allowed);
+                C.parts.insert(C.parts.end(), ps.begin(), ps.end());
             }
-        } else {
-            C.parts = greedy_partition(n, P.meta, all, k, ~0ull);
         }
         if (C.parts.empty()) C.parts.push_back(Part());  // an empty circuit still gets one (empty) sweep
         C.part_begin = (int32_t)P.parts.size();

@@ -51,6 +51,10 @@ class Simulator:
     def partition(self, n_qubits, gates, k=0, flags=0, tile=None, circ_offsets=None) -> Plan:
         return Plan(B.qsv_partition(self.ctx, n_qubits, gates, circ_offsets, k, flags, tile), n_qubits)
 
+    def partition_distributed(self, n_qubits, gates, n_global, k=0, flags=0, tile=None) -> Plan:
+        """Plan with the distributed level: 2^n_global emulated ranks."""
+        return Plan(B.qsv_partition_distributed(self.ctx, n_qubits, gates, n_global, k, flags, tile), n_qubits)
+
     def zero_state(self, n_qubits, batch=1):
         psi = torch.zeros((batch, 1 << n_qubits) if batch > 1 else (1 << n_qubits,), dtype=torch.complex64,
                           device=self.device)

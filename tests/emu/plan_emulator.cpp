@@ -65,8 +65,8 @@ extern "C" void emu_kind_counts(int64_t *out, int reset)
 // Build a plan with the given shape and run it on |0..0> (inverse = 0) or run
 // its conjugate transpose on the given state (inverse = 1).  Rotation
 // parameters are taken from theta (float64) the way the device forms them.
-extern "C" int emu_run(int n, const qsv_gate *gates, int ng, const double *theta, int n_params, int k, int R, int LW,
-                       int flags, int inverse, float *state)
+extern "C" int emu_run_dist(int n, const qsv_gate *gates, int ng, const double *theta, int n_params, int k, int R,
+                            int LW, int flags, int inverse, int n_global, float *state)
 {
     Plan P;
     P.n = n;
@@ -78,10 +78,15 @@ extern "C" int emu_run(int n, const qsv_gate *gates, int ng, const double *theta
     P.R = std::min(std::max(R, need_r), P.t);
     P.LW = LW;
     P.flags = (uint32_t)flags;
-    P.gates.assign(gates, gates + ng);
+    if (n_global > 0) {
+        P.n_global = n_global;
+        distribute(P, gates, ng, n_global);
+    } else {
+        P.gates.assign(gates, gates + ng);
+    }
     CircuitPlan C;
     C.g0 = 0;
-    C.g1 = ng;
+    C.g1 = (int64_t)P.gates.size();
     C.theta_off = 0;
     C.n_params = n_params;
     P.circ.push_back(C);
@@ -114,4 +119,10 @@ extern "C" int emu_run(int n, const qsv_gate *gates, int ng, const double *theta
     }
     std::memcpy(state, psi.data(), psi.size() * sizeof(float2));
     return np;
+}
+
+extern "C" int emu_run(int n, const qsv_gate *gates, int ng, const double *theta, int n_params, int k, int R, int LW,
+                       int flags, int inverse, float *state)
+{
+    return emu_run_dist(n, gates, ng, theta, n_params, k, R, LW, flags, inverse, 0, state);
 }

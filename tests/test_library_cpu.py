@@ -151,3 +151,47 @@ def test_invalid_input_rejected(case, code):
     with pytest.raises(Q.QsvError) as e:
         Q.qsv_partition(None, n, g, off, k, 0, (5, 8))
     assert e.value.code == code
+
+
+@pytest.mark.parametrize("name,n,g", [("c2", 28, 4), ("c3", 32, 8), ("qft", 24, 4), ("rand", 18, 3)])
+def test_distributed_level_matches_oracle(name, n, g):
+    """The distributed level is the same greedy with n - g local qubits (exact
+    gate lists against the oracle's); every distributed partition's local set
+    holds n - g qubits including its gates' required ones; the tile-level
+    partitions under it keep every gate in order, with tiles inside one rank
+    (low positions) except for the remap SWAPs."""
+    gates = {"c2": W.brickwork_c2, "c3": W.brickwork_c3, "qft": lambda: W.qft(n),
+             "rand": lambda: W.random_circuit(n, 300, seed=123)}[name]()
+    plan = Q.qsv_partition_distributed(None, n, gates, g)
+    try:
+        info = Q.qsv_plan_distributed_info(plan)
+        assert info["n_global"] == g
+        dist = [Q.qsv_plan_partition(plan, 0, -1, p) for p in range(info["n_dist_partitions"])]
+        ref = C.greedy_partition(n, gates, n - g)
+        assert [gl for _, gl in dist] == [list(p) for _, p in ref]
+        prev, moved = set(range(n - g)), 0
+        for S, gl in dist:
+            assert len(S) == n - g
+            for gi in gl:
+                assert set(C.required_local(gates[gi])) <= set(S)
+            moved += len(set(S) - prev)
+            prev = set(S)
+        assert moved <= info["exchange_swaps"] <= info["remap_swaps"]
+        order = []
+        for S, gl in _plan_parts(plan):
+            logical = [x for x in gl if x >= 0]
+            if logical:  # a compute partition: its tile stays inside a rank
+                assert len(logical) == len(gl) and max(S) < n - g
+            order += logical
+        assert sorted(order) == list(range(len(gates)))  # every gate once (the greedy orders them)
+        # and each distributed partition's gates run before the next one's
+        where = {gi: i for i, (_, gl) in enumerate(dist) for gi in gl}
+        assert [where[x] for x in order] == sorted(where[x] for x in order)
+    finally:
+        Q.qsv_plan_destroy(plan)
+
+
+def test_distributed_rejects_too_many_global_qubits():
+    with pytest.raises(Q.QsvError) as e:
+        Q.qsv_partition_distributed(None, 14, W.ghz(14), 3)  # 11 local qubits < default 12-qubit tile
+    assert e.value.code == -1
