@@ -15,6 +15,7 @@ Side measurements (separate timed regions, not in `value`):
     remaps as SWAP sweeps);
   * the 32-qubit, 60-layer U3 + random-matching CX circuit with k and the tile
     shape chosen by the autotuner, plus <sum Z_i Z_i+1>;
+  * host planning time for 34-qubit circuits of 20 400 and 51 000 gates;
   * the 20-qubit RY.RZ + CX-ladder ansatz (400 parameters): adjoint gradient
     time / forward time;
   * 2048 x 14-qubit ansatz instances (depths 4..16): energy + gradient of all
@@ -265,6 +266,23 @@ def bench_distributed(sim, args):
     return res
 
 
+def bench_planner(args):
+    """Host planning time (contraction graph, closeness, both partition levels,
+    lowering; no device upload) for 34-qubit U3 + random-matching CX circuits
+    of 20 400 and 51 000 gates."""
+    res = []
+    for layers in (400, 1000):
+        gates = W.brickwork_c3(n=34, layers=layers, seed=7)
+        t0 = time.perf_counter()
+        plan = Q.qsv_partition(None, 34, gates, None, args.k, 0, None)
+        dt = time.perf_counter() - t0
+        info = Q.qsv_plan_info(plan)
+        Q.qsv_plan_destroy(plan)
+        res.append(dict(n_qubits=34, n_gates=int(len(gates)), seconds=round(dt, 3), partitions=info["n_partitions"],
+                        register_stages=info["n_stages"]))
+    return res
+
+
 def bench_c3(sim, args):
     """32-qubit local share (60 layers of U3 + random CX matchings): the
     autotuner chooses k and the tile shape, then one apply and <sum Z_i Z_i+1>."""
@@ -399,6 +417,7 @@ def main():
         line["distributed"] = bench_distributed(sim, args)
     if not args.skip_c3:
         line["c3_autotuned"] = bench_c3(sim, args)
+        line["planner"] = bench_planner(args)
     if not args.skip_cpu:
         line["cpu_baseline"] = bench_oracle(args, info["bytes_per_apply"], info["n_gates"])
     else:

@@ -200,10 +200,19 @@ std::vector<Part> greedy_partition(int n, const std::vector<GateMeta> &meta, con
         last[g.q[0]] = v;
         if (g.nq == 2) last[g.q[1]] = v;
     }
-    // reachable sets as bitsets, filled from the last node backwards
+    // reachable sets as bitsets, filled from the last node backwards.  The sum
+    // of l over a set is taken bit plane by bit plane: sum_w l_w =
+    // sum_b 2^b |RN(v) & {w : bit b of l_w set}|, so no set bit is visited.
     const int words = (N + 63) / 64;
     std::vector<uint64_t> rn((size_t)N * words, 0);
     std::vector<int64_t> size(N, 0), dist(N, 0);
+    int planes = 1;
+    for (int v = 0; v < N; ++v)
+        while ((l[v] >> planes) != 0) ++planes;
+    std::vector<uint64_t> plane((size_t)planes * words, 0);
+    for (int v = 0; v < N; ++v)
+        for (int b = 0; b < planes; ++b)
+            if ((l[v] >> b) & 1) plane[(size_t)b * words + (v >> 6)] |= 1ull << (v & 63);
     for (int v = N - 1; v >= 0; --v) {
         uint64_t *rv = &rn[(size_t)v * words];
         for (int c : succ[v]) {
@@ -211,15 +220,16 @@ std::vector<Part> greedy_partition(int n, const std::vector<GateMeta> &meta, con
             for (int w = 0; w < words; ++w) rv[w] |= rc[w];
             rv[c >> 6] |= 1ull << (c & 63);
         }
+    }
+    for (int v = 0; v < N; ++v) {
+        const uint64_t *rv = &rn[(size_t)v * words];
         int64_t cnt = 0, suml = 0;
-        for (int w = 0; w < words; ++w) {
-            uint64_t x = rv[w];
-            cnt += popc(x);
-            while (x) {
-                int b = __builtin_ctzll(x);
-                suml += l[w * 64 + b];
-                x &= x - 1;
-            }
+        for (int w = 0; w < words; ++w) cnt += popc(rv[w]);
+        for (int b = 0; b < planes; ++b) {
+            const uint64_t *pb = &plane[(size_t)b * words];
+            int64_t c = 0;
+            for (int w = 0; w < words; ++w) c += popc(rv[w] & pb[w]);
+            suml += c << b;
         }
         size[v] = cnt;
         dist[v] = suml - cnt * (int64_t)l[v];
