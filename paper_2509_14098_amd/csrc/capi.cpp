@@ -673,8 +673,9 @@ qsv_status qsv_expect(qsv_ctx *ctx, const qsv_pauli_term *H, int32_t n_terms, in
         if (batch < 1) fail(QSV_E_ARG, "batch must be >= 1");
         HostGroups g = group_terms(H, n_terms, n_qubits);
         hip_check(hipSetDevice(ctx->device), "hipSetDevice");
-        const int n_blocks = 4096;  // partials below are sized for this cap
-        size_t need = sizeof(double) * (size_t)n_blocks * std::max<size_t>(1, g.groups.size()) * (size_t)batch;
+        const int n_blocks = 4096;  // cap on the blocks per (batch entry, group)
+        size_t need = sizeof(double) * (size_t)expect_blocks(n_qubits, n_blocks) *
+                      std::max<size_t>(1, g.groups.size()) * (size_t)batch;
         double *partials = (double *)ctx->ensure(ctx->scratch, ctx->scratch_bytes, need);
         DevGroup *dg = nullptr;
         DevTerm *dt = nullptr;

@@ -149,6 +149,8 @@ static int blocks_for(uint64_t work, int cap)
     return (int)std::max<uint64_t>(1, std::min<uint64_t>(b, (uint64_t)cap));
 }
 
+int expect_blocks(int n, int cap) { return blocks_for(1ull << n, cap); }
+
 hipError_t launch_expect(const DevGroup *groups, int n_groups, const DevTerm *terms, int n, int64_t batch,
                          const float2 *psi, double *partials, int n_blocks, double *out, hipStream_t s)
 {

@@ -21,6 +21,8 @@ struct DevGroup {
 };
 
 // expect.hip
+// Blocks per (batch entry, Pauli group) that launch_expect uses for 2^n amplitudes and a cap.
+int expect_blocks(int n, int cap);
 hipError_t launch_expect(const DevGroup *groups, int n_groups, const DevTerm *terms, int n, int64_t batch,
                          const float2 *psi, double *partials, int n_blocks, double *out, hipStream_t s);
 hipError_t launch_apply_h(const DevGroup *groups, int n_groups, const DevTerm *terms, int n, const float2 *psi,
