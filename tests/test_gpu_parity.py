@@ -212,6 +212,30 @@ def test_c3_full_size_properties(sim):
     torch.cuda.empty_cache()
 
 
+def test_maximum_size_34_qubits(sim):
+    """The largest state the interface accepts, 34 qubits (128 GiB): a U3
+    layer matches its product-state closed form on sampled amplitudes, and
+    a short brickwork followed by its inverse returns to the U3 state."""
+    n = 34
+    torch.cuda.empty_cache()
+    layer, ang = W.u3_layer(n, seed=11)
+    psi, _ = run(sim, n, layer, k=10)
+    idx = np.random.default_rng(5).integers(0, 1 << n, size=1024)
+    got = psi[torch.as_tensor(idx, device=psi.device)].cpu().numpy()
+    ref = np.ones(len(idx), complex)
+    for q in range(n):
+        b = (idx >> q) & 1
+        ref *= np.where(b == 0, np.cos(ang[q, 0] / 2), np.exp(1j * ang[q, 1]) * np.sin(ang[q, 0] / 2))
+    assert np.max(np.abs(got - ref)) < 1e-7
+    body = W.brickwork_c3(n=n, layers=3, seed=12)
+    run(sim, n, body, k=10, psi=psi)
+    run(sim, n, W.inverse_circuit(body), k=10, psi=psi)
+    back = psi[torch.as_tensor(idx, device=psi.device)].cpu().numpy()
+    assert np.max(np.abs(back - ref)) < 1e-6
+    del psi
+    torch.cuda.empty_cache()
+
+
 # ---------------------------------------------------------------- expectation values
 
 @pytest.mark.parametrize("n,seed", [(1, 1), (3, 2), (8, 3), (15, 4)])
