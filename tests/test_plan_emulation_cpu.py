@@ -135,3 +135,17 @@ def test_distributed_plans(emu, n, g, R, LW, k):
     out = emu(n, q, k, R, LW, state=psi, n_global=g)
     refq = np.exp(2j * np.pi * x * np.arange(1 << n) / (1 << n)) / np.sqrt(1 << n)
     assert np.max(np.abs(out - refq)) < 1e-5
+
+
+@pytest.mark.parametrize("R,LW", [(4, 8), (2, 6)])
+def test_parameterised_rotations_large_angles(emu, R, LW):
+    """Parameterised rotations with angles spanning (-2 pi, 2 pi), forward and
+    conjugate walk."""
+    n = 11
+    theta = np.linspace(-6.2, 6.2, 8)
+    gates = W.random_circuit(n, 200, seed=31 + R, n_params=8, kinds=["RY", "RZ", "RX", "H", "CX", "CZ", "U3"])
+    ref = oracle.apply(n, gates, theta)
+    out = emu(n, gates, 8, R, LW, theta)
+    assert np.max(np.abs(out - ref)) < 1e-5
+    back = emu(n, gates, 8, R, LW, theta, inverse=True, state=out)
+    assert abs(back[0] - 1) < 1e-5 and np.max(np.abs(back[1:])) < 1e-5
