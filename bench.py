@@ -325,10 +325,31 @@ def bench_oracle(args, gpu_bytes_per_apply, n_gates_total):
         t_total += time.perf_counter() - t0
         done = min(done + chunk, len(gates))
     frac = done / n_gates_total
-    return dict(value=gpu_bytes_per_apply * frac / t_total / 1e9, unit="GB/s", cores=oracle.threads(), kind="oracle",
-                sample=f"first {done} of {n_gates_total} gates of the 28-qubit headline circuit, complex128 gate by "
-                       f"gate, {t_total:.1f} s; rate expressed as the fused circuit's algorithmic bytes x fraction "
-                       f"of gates done / time")
+    res = dict(value=gpu_bytes_per_apply * frac / t_total / 1e9, unit="GB/s", cores=oracle.threads(), kind="oracle",
+               sample=f"first {done} of {n_gates_total} gates of the 28-qubit headline circuit, complex128 gate by "
+                      f"gate, {t_total:.1f} s; rate expressed as the fused circuit's algorithmic bytes x fraction "
+                      f"of gates done / time")
+    # the same oracle on the smaller workloads, in full or on a stated sample
+    t0 = time.perf_counter()
+    oracle.apply(12, W.brickwork_c1())
+    res["c1_full_s"] = round(time.perf_counter() - t0, 4)
+    g4, np4 = W.ansatz(20, 10)
+    th4 = W.ansatz_params(np4, seed=4)
+    H = W.zz_chain_plus_x(20, 0.5)
+    t0 = time.perf_counter()
+    oracle.apply(20, g4, th4)
+    res["c4_forward_s"] = round(time.perf_counter() - t0, 3)
+    t0 = time.perf_counter()
+    oracle.adjoint(20, g4, th4, H)
+    res["c4_energy_gradient_s"] = round(time.perf_counter() - t0, 3)
+    circs, _, thetas = W.ansatz_batch(2048, 14, 4, 16, seed=5)
+    H14 = W.zz_chain_plus_x(14, 0.5)
+    t0 = time.perf_counter()
+    for b in range(64):
+        oracle.adjoint(14, circs[b], thetas[b], H14)
+    res["c5_energy_gradient_instances_per_s"] = round(64 / (time.perf_counter() - t0), 1)
+    res["c5_sample"] = "first 64 of the 2048 14-qubit instances"
+    return res
 
 
 def main():
