@@ -195,3 +195,22 @@ def test_distributed_rejects_too_many_global_qubits():
     with pytest.raises(Q.QsvError) as e:
         Q.qsv_partition_distributed(None, 14, W.ghz(14), 3)  # 11 local qubits < default 12-qubit tile
     assert e.value.code == -1
+
+
+def test_distributed_edge_cases():
+    empty = Q.qsv_partition_distributed(None, 16, W.ghz(16)[:0], 2)
+    try:
+        assert Q.qsv_plan_distributed_info(empty) == dict(n_global=2, n_dist_partitions=1, exchange_swaps=0,
+                                                          remap_swaps=0)
+        assert Q.qsv_plan_info(empty)["n_partitions"] == 1  # one empty sweep
+    finally:
+        Q.qsv_plan_destroy(empty)
+    gbg = Q.qsv_partition_distributed(None, 16, W.ghz(16), 2, 0, Q.PLAN_GATE_BY_GATE)
+    try:
+        info = Q.qsv_plan_distributed_info(gbg)
+        assert Q.qsv_plan_info(gbg)["n_partitions"] == 16 + info["remap_swaps"]  # one sweep per gate or SWAP
+    finally:
+        Q.qsv_plan_destroy(gbg)
+    for n, g in ((16, 0), (16, 5), (2, 1)):
+        with pytest.raises(Q.QsvError):
+            Q.qsv_partition_distributed(None, n, W.ghz(n), g)
