@@ -119,6 +119,9 @@ typedef struct qsv_plan_info {
     double flops_per_apply;  /* algorithmic flops of one qsv_apply */
     double bytes_per_apply;  /* algorithmic HBM bytes of one qsv_apply (16 B/amplitude/sweep) */
     double plan_seconds;     /* host time spent in qsv_partition */
+    double specialise_seconds; /* host time of qsv_plan_specialise (compile and load), 0 if not specialised */
+    int32_t specialised;     /* 1 once qsv_plan_specialise has loaded kernels for this plan */
+    int32_t reserved;
 } qsv_plan_info;
 
 /* Last error message of the calling thread ("" if none). */
@@ -163,6 +166,30 @@ qsv_status qsv_partition(qsv_ctx *ctx, int32_t n_qubits, const qsv_gate *gates, 
                          qsv_plan **out);
 qsv_status qsv_plan_destroy(qsv_plan *plan);
 qsv_status qsv_plan_get_info(const qsv_plan *plan, qsv_plan_info *out);
+
+/*
+ * Specialise a plan's partition sweeps (paper Section 4.3, Step D: the
+ * computation of each partition is generated as code).  For every partition
+ * a kernel is generated with the partition's tile qubits, register stages,
+ * lowered ops and constant gate matrices as compile-time constants. The
+ * kernels are compiled for gfx950 with hipRTC on up to 16 host threads and
+ * loaded on the context's device.  Afterwards qsv_apply on this plan
+ * launches them instead of the table-driven sweep kernel.  The ops, their
+ * order and their arithmetic are the same; only the compiler's choice of
+ * fused multiply-adds may differ in the last bits.  Matrices of
+ * parameterised rotations are still formed from theta at every qsv_apply.
+ * The reverse walk of qsv_adjoint_grad keeps the table-driven kernels; the
+ * forward it starts from (qsv_apply with checkpoints) uses the specialised
+ * ones.
+ * ctx NULL: generate and compile only, load nothing (a check that needs no
+ * GPU); the plan is unchanged.  A plan that is already specialised is left
+ * as it is.  seconds_out (may be NULL) receives the host time taken.
+ * Errors: QSV_E_ARG (plan null), QSV_E_UNSUPPORTED (a plan of several
+ * circuits, or tiles above 13 qubits, i.e. beyond 64 KiB of LDS), QSV_E_STATE
+ * (plan without device tables on the context's device), QSV_E_DEVICE (the
+ * compile or the load failed: qsv_last_error() holds the compiler log).
+ */
+qsv_status qsv_plan_specialise(qsv_ctx *ctx, qsv_plan *plan, double *seconds_out);
 /* Number of theta entries of circuit c and its offset in the packed theta array. */
 qsv_status qsv_plan_params(const qsv_plan *plan, int32_t circuit, int64_t *offset, int64_t *count);
 /*

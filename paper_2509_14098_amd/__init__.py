@@ -12,6 +12,6 @@ from .binding import (  # noqa: F401
     qsv_create, qsv_destroy, qsv_set_stream, qsv_partition, qsv_plan_destroy, qsv_plan_info,
     qsv_plan_params, qsv_plan_partition, qsv_apply, qsv_expect, qsv_adjoint_grad,
     qsv_set_timing, qsv_last_sweep_ms, qsv_last_autotune, library_path, load_library,
-    qsv_partition_distributed, qsv_plan_distributed_info,
+    qsv_partition_distributed, qsv_plan_distributed_info, qsv_plan_specialise,
 )
 from .sim import Simulator, Plan, Energy  # noqa: F401

@@ -42,14 +42,15 @@ class _PlanInfo(ctypes.Structure):
                 ("tile_qubits", ctypes.c_int32), ("reg_qubits", ctypes.c_int32), ("log_threads", ctypes.c_int32),
                 ("n_gates", ctypes.c_int64), ("n_params", ctypes.c_int64), ("n_partitions", ctypes.c_int64),
                 ("n_stages", ctypes.c_int64), ("ckpt_bytes", ctypes.c_int64), ("flops_per_apply", ctypes.c_double),
-                ("bytes_per_apply", ctypes.c_double), ("plan_seconds", ctypes.c_double)]
+                ("bytes_per_apply", ctypes.c_double), ("plan_seconds", ctypes.c_double),
+                ("specialise_seconds", ctypes.c_double), ("specialised", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _lib = None
 EXPORTS = ["qsv_last_error", "qsv_create", "qsv_destroy", "qsv_set_stream", "qsv_partition", "qsv_plan_destroy",
            "qsv_plan_get_info", "qsv_plan_params", "qsv_plan_partition", "qsv_apply", "qsv_expect",
            "qsv_adjoint_grad", "qsv_set_timing", "qsv_last_sweep_ms", "qsv_last_autotune",
-           "qsv_partition_distributed", "qsv_plan_distributed_info"]
+           "qsv_partition_distributed", "qsv_plan_distributed_info", "qsv_plan_specialise"]
 
 
 def library_path() -> str:
@@ -69,7 +70,7 @@ def load_library():
     sigs = {
         "qsv_create": [I32, V, V], "qsv_destroy": [V], "qsv_set_stream": [V, V],
         "qsv_partition": [V, I32, V, V, I32, I32, U32, V, V], "qsv_plan_destroy": [V],
-        "qsv_plan_get_info": [V, V], "qsv_plan_params": [V, I32, V, V],
+        "qsv_plan_get_info": [V, V], "qsv_plan_specialise": [V, V, V], "qsv_plan_params": [V, I32, V, V],
         "qsv_plan_partition": [V, I32, I32, I64, V, V, I64, V],
         "qsv_apply": [V, V, V, V, V], "qsv_expect": [V, V, I32, I32, I64, V, V],
         "qsv_adjoint_grad": [V, V, V, I32, V, V, V, V, V],
@@ -182,6 +183,14 @@ def qsv_plan_info(plan) -> dict:
     i = _PlanInfo()
     _check(load_library().qsv_plan_get_info(plan, ctypes.byref(i)))
     return {f: getattr(i, f) for f, _ in _PlanInfo._fields_}
+
+
+def qsv_plan_specialise(ctx, plan) -> float:
+    """Generate, compile and (with a context) load the plan's specialised
+    sweep kernels; returns the host seconds taken."""
+    secs = ctypes.c_double(0.0)
+    _check(load_library().qsv_plan_specialise(ctx, plan, ctypes.byref(secs)))
+    return secs.value
 
 
 def qsv_plan_params(plan, circuit: int = 0):

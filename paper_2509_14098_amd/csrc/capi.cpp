@@ -497,6 +497,7 @@ qsv_status qsv_plan_destroy(qsv_plan *plan)
         dev_free(plan->d_circ_part);
         dev_free(plan->d_circ_theta);
         dev_free(plan->d_circ_npar);
+        for (void *m : plan->spec_modules) (void)hipModuleUnload((hipModule_t)m);
         delete plan;
     });
 }
@@ -524,7 +525,59 @@ qsv_status qsv_plan_get_info(const qsv_plan *plan, qsv_plan_info *out)
         i.flops_per_apply = plan->flops;
         i.bytes_per_apply = plan->bytes;
         i.plan_seconds = plan->plan_seconds;
+        i.specialised = plan->specialised ? 1 : 0;
+        i.specialise_seconds = plan->specialise_seconds;
         *out = i;
+    });
+}
+
+qsv_status qsv_plan_specialise(qsv_ctx *ctx, qsv_plan *plan, double *seconds_out)
+{
+    return guarded([&] {
+        if (!plan) fail(QSV_E_ARG, "null plan");
+        if (plan->specialised && ctx) {
+            if (seconds_out) *seconds_out = plan->specialise_seconds;
+            return;
+        }
+        if (plan->n_circuits != 1) fail(QSV_E_UNSUPPORTED, "only single-circuit plans are specialised");
+        if (((size_t)8 << plan->t) > (size_t)64 * 1024)
+            fail(QSV_E_UNSUPPORTED, "specialised sweeps take tiles of at most 64 KiB of LDS (13 qubits)");
+        if (ctx && plan->device != ctx->device) fail(QSV_E_STATE, "plan has no device tables on this context's device");
+        const auto t0 = std::chrono::steady_clock::now();
+        std::vector<SpecChunk> chunks;
+        const std::string err = specialise_compile(*plan, chunks, 16);
+        if (!err.empty()) fail(QSV_E_DEVICE, err);
+        const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (seconds_out) *seconds_out = secs;
+        if (!ctx) return;  // compile only
+        hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+        std::vector<void *> fn(plan->parts.size(), nullptr), mods;
+        std::string lerr;
+        for (const SpecChunk &c : chunks) {
+            hipModule_t m = nullptr;
+            if (hipModuleLoadData(&m, c.code.data()) != hipSuccess) {
+                lerr = "hipModuleLoadData failed";
+                break;
+            }
+            mods.push_back((void *)m);
+            for (int p = c.p0; p < c.p1 && lerr.empty(); ++p) {
+                hipFunction_t f = nullptr;
+                const std::string name = "qsv_spec_" + std::to_string(p);
+                if (hipModuleGetFunction(&f, m, name.c_str()) != hipSuccess) lerr = "hipModuleGetFunction " + name;
+                fn[p] = (void *)f;
+            }
+            if (!lerr.empty()) break;
+        }
+        if (!lerr.empty()) {
+            (void)hipGetLastError();
+            for (void *m : mods) (void)hipModuleUnload((hipModule_t)m);
+            fail(QSV_E_DEVICE, lerr);
+        }
+        plan->spec_fn = std::move(fn);
+        plan->spec_modules = std::move(mods);
+        plan->specialised = true;
+        plan->specialise_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (seconds_out) *seconds_out = plan->specialise_seconds;
     });
 }
 

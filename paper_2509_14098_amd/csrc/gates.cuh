@@ -9,11 +9,14 @@
 // register index, on a thread or tile-index qubit they are one value per
 // thread.  Every gate body updates the amplitudes in place (see fma_ip).
 //
-// The device code paths guarded by __HIP_DEVICE_COMPILE__ are the gfx950
-// instructions; the other branch is the same arithmetic in plain C++, used
-// only when the test emulator compiles this header for the host.
+// The in-place bodies have two forms of the same arithmetic: gfx950
+// instructions with tied registers (QSV_INPLACE_ASM, for the table-driven
+// kernels) and plain C++, used by the specialised kernels and when the test
+// emulator compiles this header for the host.
 #pragma once
+#ifndef __HIPCC_RTC__  // hipRTC provides the runtime declarations itself
 #include <hip/hip_runtime.h>
+#endif
 
 #include <type_traits>
 
@@ -107,6 +110,16 @@ __device__ __forceinline__ float2 cmac2(C2 u0, float2 x, C2 u1, float2 y)
     return o;
 }
 
+// The in-place instruction forms below are used in the table-driven kernels.
+// Specialised kernels (straight-line code, no dispatch merges) define
+// QSV_PLAIN_ARITH and get the plain expressions, which the compiler schedules
+// and contracts freely.
+#if defined(__HIP_DEVICE_COMPILE__) && !defined(QSV_PLAIN_ARITH)
+#define QSV_INPLACE_ASM 1
+#else
+#define QSV_INPLACE_ASM 0
+#endif
+
 // In-place updates x <- s x + t and x <- s x - t with s uniform.  Written as
 // instructions whose result is tied to x's register so that an op's outputs
 // stay in the registers its inputs came from: the op dispatch loop then needs
@@ -114,7 +127,7 @@ __device__ __forceinline__ float2 cmac2(C2 u0, float2 x, C2 u1, float2 y)
 // same expressions for the host.)
 __device__ __forceinline__ void fma_ip(float &x, float s, float t)
 {
-#if defined(__HIP_DEVICE_COMPILE__)
+#if QSV_INPLACE_ASM
     asm("v_fma_f32 %0, %1, %0, %2" : "+v"(x) : "s"(s), "v"(t));
 #else
     x = s * x + t;
@@ -122,7 +135,7 @@ __device__ __forceinline__ void fma_ip(float &x, float s, float t)
 }
 __device__ __forceinline__ void fms_ip(float &x, float s, float t)
 {
-#if defined(__HIP_DEVICE_COMPILE__)
+#if QSV_INPLACE_ASM
     asm("v_fma_f32 %0, %1, %0, -%2" : "+v"(x) : "s"(s), "v"(t));
 #else
     x = s * x - t;
@@ -132,7 +145,7 @@ __device__ __forceinline__ void fms_ip(float &x, float s, float t)
 // x <- s x + t with s per lane
 __device__ __forceinline__ void fma_ipv(float &x, float s, float t)
 {
-#if defined(__HIP_DEVICE_COMPILE__)
+#if QSV_INPLACE_ASM
     asm("v_fma_f32 %0, %1, %0, %2" : "+v"(x) : "v"(s), "v"(t));
 #else
     x = s * x + t;
@@ -140,7 +153,7 @@ __device__ __forceinline__ void fma_ipv(float &x, float s, float t)
 }
 __device__ __forceinline__ void fms_ipv(float &x, float s, float t)
 {
-#if defined(__HIP_DEVICE_COMPILE__)
+#if QSV_INPLACE_ASM
     asm("v_fma_f32 %0, %1, %0, -%2" : "+v"(x) : "v"(s), "v"(t));
 #else
     x = s * x - t;
@@ -149,7 +162,7 @@ __device__ __forceinline__ void fms_ipv(float &x, float s, float t)
 // exchange two registers
 __device__ __forceinline__ void swap_ip(float &x, float &y)
 {
-#if defined(__HIP_DEVICE_COMPILE__)
+#if QSV_INPLACE_ASM
     asm("v_swap_b32 %0, %1" : "+v"(x), "+v"(y));
 #else
     const float t = x;
@@ -160,7 +173,7 @@ __device__ __forceinline__ void swap_ip(float &x, float &y)
 // x <- x + s y with s uniform, in place
 __device__ __forceinline__ void fmac_ip(float &x, float s, float y)
 {
-#if defined(__HIP_DEVICE_COMPILE__)
+#if QSV_INPLACE_ASM
     asm("v_fmac_f32 %0, %1, %2" : "+v"(x) : "s"(s), "v"(y));
 #else
     x = s * y + x;
@@ -170,7 +183,7 @@ __device__ __forceinline__ void fmac_ip(float &x, float s, float y)
 // x <- x ^ d (bit pattern), in place
 __device__ __forceinline__ void xor_ip(float &x, uint32_t d)
 {
-#if defined(__HIP_DEVICE_COMPILE__)
+#if QSV_INPLACE_ASM
     asm("v_xor_b32 %0, %0, %1" : "+v"(x) : "v"(d));
 #else
     x = __uint_as_float(__float_as_uint(x) ^ d);
@@ -179,7 +192,7 @@ __device__ __forceinline__ void xor_ip(float &x, uint32_t d)
 // x <- x ^ d with d uniform
 __device__ __forceinline__ void xor_ips(float &x, uint32_t d)
 {
-#if defined(__HIP_DEVICE_COMPILE__)
+#if QSV_INPLACE_ASM
     asm("v_xor_b32 %0, %1, %0" : "+v"(x) : "s"(d));
 #else
     x = __uint_as_float(__float_as_uint(x) ^ d);

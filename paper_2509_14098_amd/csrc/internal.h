@@ -82,6 +82,11 @@ struct Plan {
     std::vector<int64_t> phys_logical;  // physical gate -> logical gate index, -1 for a remap SWAP
     int64_t remap_exchange_swaps = 0; // remap SWAPs between a rank-local and a global position
     int64_t remap_swaps = 0;          // all remap SWAPs (including the final return to logical order)
+    // specialised sweeps (qsv_plan_specialise): per partition a hipFunction_t, null for none
+    std::vector<void *> spec_fn;
+    std::vector<void *> spec_modules; // hipModule_t, unloaded with the plan
+    bool specialised = false;
+    double specialise_seconds = 0;
 
     // device copies (null for host-only plans)
     int device = -1;
@@ -109,5 +114,16 @@ void build_plan(Plan &plan);
 // circuit gates[0..G) for 2^n_global ranks (plan.n set), and the segments,
 // distributed partitions and gate map.
 void distribute(Plan &plan, const qsv_gate *gates, int64_t G, int n_global);
+
+// specialise.cpp: generated sweep kernels, one per partition, compiled with
+// hipRTC.  Partitions [p0, p1) share one program and code object.
+struct SpecChunk {
+    int p0 = 0, p1 = 0;
+    std::vector<char> code;
+};
+std::string specialise_source(const Plan &plan, int p0, int p1);
+// Compiles every partition of a single-circuit plan on up to max_threads host
+// threads; returns "" or the error (with the compiler log).
+std::string specialise_compile(const Plan &plan, std::vector<SpecChunk> &chunks, int max_threads);
 
 }  // namespace qsv

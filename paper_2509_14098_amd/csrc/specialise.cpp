@@ -1,0 +1,277 @@
+// Plan specialisation (paper Section 4.3, Step D: the computation of every
+// partition is generated as code).  For each partition the lowered tables of
+// the plan (its DevPart, register stages, ops and constant matrices) are
+// written out as compile-time constants of a table type, followed by one
+// kernel that instantiates spec_sweep (spec.cuh) for it.  The programs are
+// compiled for gfx950 by the helper executable qsv_rtc (hipRTC), which sits
+// beside the library; hipRTC serialises compiles within one process, so up to
+// 16 helpers run at once as child processes.  The caller loads the code
+// objects.
+#include <dlfcn.h>
+#include <spawn.h>
+#include <sys/stat.h>
+#include <sys/wait.h>
+#include <unistd.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <deque>
+#include <fstream>
+#include <iterator>
+#include <set>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "internal.h"
+
+extern char **environ;
+
+namespace qsv {
+
+namespace {
+
+// Floats of the matrix pool that an op of this kind reads.
+int pool_floats(int kind, int R)
+{
+    switch (kind) {
+    case OP_LAYER: return 2 * (1 << R) + 2 * R;
+    case OP_DREG: return 2 * (1 << R);
+    case OP_U2: return 32;
+    default: return 8;
+    }
+}
+
+void put_ints(std::string &s, const int32_t *v, int n)
+{
+    char b[16];
+    s += '{';
+    for (int i = 0; i < n; ++i) {
+        std::snprintf(b, sizeof b, "%d,", v[i]);
+        s += b;
+    }
+    s += '}';
+}
+
+void put_stage(std::string &s, const DevStage &st)
+{
+    char b[48];
+    std::snprintf(b, sizeof b, "{%d,%d,", st.op_begin, st.op_end);
+    s += b;
+    put_ints(s, st.regpos, 8);
+    s += ',';
+    put_ints(s, st.thrpos, 16);
+    s += "},\n";
+}
+
+void put_op(std::string &s, const DevOp &o)
+{
+    char b[160];
+    std::snprintf(b, sizeof b, "{%d,%d,%d,%d,%d,%d,%d,%d},\n", o.kind, o.a, o.b, o.gen, o.mat, o.grad_slot, o.gate,
+                  o.flags);
+    s += b;
+}
+
+}  // namespace
+
+// Source of the program holding the specialised kernels qsv_spec_<p> of
+// partitions [p0, p1).  Every float is written as an exact hexadecimal literal.
+std::string specialise_source(const Plan &plan, int p0, int p1)
+{
+    std::set<int32_t> dyn_mats;  // pool entries written from theta at apply time
+    for (const ParamGate &g : plan.pgates) dyn_mats.insert(g.mat);
+    // straight-line code: the gate bodies' plain arithmetic (see gates.cuh)
+    std::string s = "#define QSV_PLAIN_ARITH 1\n#include \"spec.cuh\"\n";
+    char b[1024];
+    for (int p = p0; p < p1; ++p) {
+        const DevPart &P = plan.parts[p];
+        DevPart lp = P;
+        lp.stage_begin = 0;
+        lp.stage_end = P.stage_end - P.stage_begin;
+        std::vector<DevStage> stages;
+        std::vector<DevOp> ops;
+        std::vector<int> dyn;
+        std::vector<float> pool;
+        for (int si = P.stage_begin; si < P.stage_end; ++si) {
+            DevStage st = plan.stages[si];
+            const int k0 = st.op_begin, k1 = st.op_end;
+            st.op_begin = (int32_t)ops.size();
+            for (int k = k0; k < k1; ++k) {
+                DevOp o = plan.ops[k];
+                const bool d = o.mat >= 0 && dyn_mats.count(o.mat) > 0;
+                if (o.mat >= 0 && !d) {
+                    const int nf = pool_floats(o.kind, plan.R);
+                    const int off = (int)pool.size();
+                    for (int i = 0; i < nf; ++i)
+                        pool.push_back((size_t)o.mat + i < plan.pool.size() ? plan.pool[o.mat + i] : 0.f);
+                    o.mat = off;
+                }
+                ops.push_back(o);
+                dyn.push_back(d ? 1 : 0);
+            }
+            st.op_end = (int32_t)ops.size();
+            stages.push_back(st);
+        }
+        // Namespace-scope constexpr arrays have internal linkage, so the compiler
+        // folds every read of them into the code; static data members of the table
+        // type would be inline (weak) symbols that it must load at run time.
+        std::snprintf(b, sizeof b, "namespace qsv_gen {\nconstexpr qsv::DevPart part%d = {%d,%d,%d,%d,", p,
+                      lp.stage_begin, lp.stage_end, lp.t, lp.n_glb);
+        s += b;
+        put_ints(s, lp.tq, 16);
+        s += ',';
+        put_ints(s, lp.gq, 48);
+        std::snprintf(b, sizeof b, "};\nconstexpr qsv::DevStage stages%d[] = {\n", p);
+        s += b;
+        for (const DevStage &st : stages) put_stage(s, st);
+        std::snprintf(b, sizeof b, "{}};\nconstexpr qsv::DevOp ops%d[] = {\n", p);  // arrays end in an unused entry
+        s += b;
+        for (const DevOp &o : ops) put_op(s, o);
+        std::snprintf(b, sizeof b, "{}};\nconstexpr bool dyn%d[] = {", p);
+        s += b;
+        for (int d : dyn) s += d ? "1," : "0,";
+        std::snprintf(b, sizeof b, "0};\nconstexpr float pool%d[] = {\n", p);
+        s += b;
+        for (size_t i = 0; i < pool.size(); ++i) {
+            std::snprintf(b, sizeof b, "%af,%s", (double)pool[i], (i % 8 == 7) ? "\n" : "");
+            s += b;
+        }
+        std::snprintf(b, sizeof b,
+                      "0.f};\nstruct P%d {\n    static constexpr int R = %d, LW = %d;\n"
+                      "    static constexpr const qsv::DevPart &part = part%d;\n"
+                      "    static constexpr const qsv::DevStage *stages = stages%d;\n"
+                      "    static constexpr const qsv::DevOp *ops = ops%d;\n"
+                      "    static constexpr const bool *dyn = dyn%d;\n"
+                      "    static constexpr const float *pool = pool%d;\n};\n}  // namespace qsv_gen\n",
+                      p, plan.R, plan.LW, p, p, p, p, p);
+        s += b;
+        std::snprintf(b, sizeof b,
+                      "extern \"C\" __global__ __launch_bounds__(%d) void qsv_spec_%d(float2 *__restrict__ psi, "
+                      "float2 *__restrict__ ckpt, const float *__restrict__ pool)\n"
+                      "{\n    qsv::spec_sweep<qsv_gen::P%d>(psi, ckpt, pool);\n}\n",
+                      1 << plan.LW, p, p);
+        s += b;
+    }
+    return s;
+}
+
+namespace {
+
+std::string read_file(const std::string &path)
+{
+    std::ifstream f(path, std::ios::binary);
+    return std::string(std::istreambuf_iterator<char>(f), std::istreambuf_iterator<char>());
+}
+
+// The helper executable next to this library.
+std::string helper_path()
+{
+    Dl_info info;
+    if (!dladdr((void *)&helper_path, &info) || !info.dli_fname) return "qsv_rtc";
+    std::string lib = info.dli_fname;
+    const size_t slash = lib.rfind('/');
+    return (slash == std::string::npos ? std::string(".") : lib.substr(0, slash)) + "/qsv_rtc";
+}
+
+struct TempDir {
+    std::string path;
+    std::vector<std::string> files;
+    ~TempDir()
+    {
+        for (const std::string &f : files) std::remove(f.c_str());
+        if (!path.empty()) rmdir(path.c_str());
+    }
+};
+
+}  // namespace
+
+std::string specialise_compile(const Plan &plan, std::vector<SpecChunk> &chunks, int max_procs)
+{
+    const int np = (int)plan.parts.size();
+    chunks.clear();
+    if (np == 0) return "";
+    const std::string helper = helper_path();
+    if (access(helper.c_str(), X_OK) != 0) return "compiler helper not found: " + helper;
+    unsigned hw = std::thread::hardware_concurrency();
+    const int nc = std::max(1, std::min({np, max_procs, hw ? (int)hw : 1}));
+    // contiguous partition ranges of near-equal op counts
+    std::vector<int64_t> cum(np + 1, 0);
+    for (int p = 0; p < np; ++p) {
+        const DevPart &P = plan.parts[p];
+        int64_t n = 1;
+        for (int s = P.stage_begin; s < P.stage_end; ++s) n += plan.stages[s].op_end - plan.stages[s].op_begin;
+        cum[p + 1] = cum[p] + n;
+    }
+    int p = 0;
+    for (int c = 0; c < nc && p < np; ++c) {
+        SpecChunk ch;
+        ch.p0 = p;
+        const int64_t target = cum[np] * (c + 1) / nc;
+        do ++p;
+        while (p < np && cum[p + 1] <= target);
+        if (c == nc - 1) p = np;
+        ch.p1 = p;
+        chunks.push_back(ch);
+    }
+
+    TempDir tmp;
+    const char *td = std::getenv("TMPDIR");
+    std::string tmpl = std::string(td && *td ? td : "/tmp") + "/qsv_rtc_XXXXXX";
+    std::vector<char> tb(tmpl.begin(), tmpl.end());
+    tb.push_back('\0');
+    if (!mkdtemp(tb.data())) return "cannot create a temporary directory for the generated kernels";
+    tmp.path = tb.data();
+    const size_t n = chunks.size();
+    std::vector<std::string> src(n), out(n), log(n);
+    for (size_t c = 0; c < n; ++c) {
+        src[c] = tmp.path + "/p" + std::to_string(c) + ".hip";
+        out[c] = tmp.path + "/p" + std::to_string(c) + ".co";
+        log[c] = tmp.path + "/p" + std::to_string(c) + ".log";
+        tmp.files.insert(tmp.files.end(), {src[c], out[c], log[c]});
+        std::ofstream f(src[c], std::ios::binary);
+        f << specialise_source(plan, chunks[c].p0, chunks[c].p1);
+        if (!f) return "cannot write " + src[c];
+    }
+    // run the helpers, at most nc at a time; wait only for our own children
+    std::string err;
+    std::vector<pid_t> pid(n, -1);
+    std::deque<size_t> running;
+    size_t next = 0;
+    for (;;) {
+        while (err.empty() && next < n && (int)running.size() < nc) {
+            std::string a0 = helper;
+            char *argv[] = {&a0[0], &src[next][0], &out[next][0], &log[next][0], nullptr};
+            pid_t child;
+            if (posix_spawn(&child, helper.c_str(), nullptr, nullptr, argv, environ) != 0) {
+                err = "cannot start " + helper;
+                break;
+            }
+            pid[next] = child;
+            running.push_back(next++);
+        }
+        if (running.empty()) break;
+        const size_t c = running.front();
+        running.pop_front();
+        int st = 0;
+        if (waitpid(pid[c], &st, 0) != pid[c]) {
+            if (err.empty()) err = "waitpid failed";
+            continue;
+        }
+        if (!(WIFEXITED(st) && WEXITSTATUS(st) == 0) && err.empty()) {
+            std::string l = read_file(log[c]);
+            if (l.size() > 4000) l.resize(4000);
+            err = "kernel compile failed for partitions " + std::to_string(chunks[c].p0) + ".." +
+                  std::to_string(chunks[c].p1 - 1) + ": " + l;
+        }
+    }
+    if (!err.empty()) return err;
+    for (size_t c = 0; c < n; ++c) {
+        const std::string code = read_file(out[c]);
+        if (code.empty()) return "no code object from the compiler helper for chunk " + std::to_string(c);
+        chunks[c].code.assign(code.begin(), code.end());
+    }
+    return "";
+}
+
+}  // namespace qsv

@@ -55,6 +55,12 @@ class Simulator:
         """Plan with the distributed level: 2^n_global emulated ranks."""
         return Plan(B.qsv_partition_distributed(self.ctx, n_qubits, gates, n_global, k, flags, tile), n_qubits)
 
+    def specialise(self, plan: Plan) -> float:
+        """Compile and load the plan's specialised sweep kernels (host seconds)."""
+        secs = B.qsv_plan_specialise(self.ctx, plan.handle)
+        plan.info = B.qsv_plan_info(plan.handle)
+        return secs
+
     def zero_state(self, n_qubits, batch=1):
         psi = torch.zeros((batch, 1 << n_qubits) if batch > 1 else (1 << n_qubits,), dtype=torch.complex64,
                           device=self.device)

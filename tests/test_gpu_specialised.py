@@ -1,0 +1,198 @@
+"""GPU parity of specialised plans (qsv_plan_specialise: one generated kernel
+per partition, Section 4.3 Step D) against the complex128 oracle, and against
+the table-driven sweep on the same plan.  Both paths run the same ops in the
+same order with the same gate bodies; only the compiler's fused
+multiply-adds may differ, so the two agree far inside the oracle tolerance."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2509_14098_amd as Q
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+TOL = 1e-5          # max-abs amplitude error against the oracle
+SAME = 2e-6         # max-abs difference between the specialised and the table-driven sweep
+
+
+@pytest.fixture(scope="module")
+def sim():
+    s = Q.Simulator(0)
+    yield s
+    s.close()
+
+
+def both(sim, n, gates, k, tile=None, theta=None, flags=0, psi0=None):
+    """Apply the plan table-driven, then specialised; returns both states."""
+    plan = sim.partition(n, gates, k, flags, tile)
+    try:
+        out = []
+        for spec in (False, True):
+            if spec:
+                secs = sim.specialise(plan)
+                assert plan.info["specialised"] == 1 and secs > 0
+            psi = sim.zero_state(n) if psi0 is None else psi0.clone()
+            sim.apply(plan, psi, theta)
+            torch.cuda.synchronize()
+            out.append(psi.cpu().numpy())
+        return out[0], out[1], plan.info
+    finally:
+        plan.close()
+
+
+def maxabs(a, b):
+    return float(np.max(np.abs(np.asarray(a, np.complex128) - np.asarray(b, np.complex128))))
+
+
+@pytest.mark.parametrize("n,ng,k,tile", [(3, 60, 2, (3, 6)), (7, 100, 5, (4, 6)), (11, 200, 7, (4, 8)),
+                                         (13, 250, 10, (5, 8)), (16, 300, 12, (4, 9)), (20, 300, 12, (5, 8))])
+def test_specialised_random_circuits(sim, n, ng, k, tile):
+    """Every gate kind (fixed and parameterised) at random positions."""
+    theta = np.random.default_rng(n).uniform(-3, 3, size=5)
+    gates = W.random_circuit(n, ng, seed=5000 + n, n_params=5)
+    ref = oracle.apply(n, gates, theta)
+    a, b, info = both(sim, n, gates, k, tile, theta)
+    assert info["n_partitions"] >= 1
+    assert maxabs(b, ref) <= TOL
+    assert maxabs(a, b) <= SAME
+
+
+def test_specialised_c2_full(sim):
+    """28-qubit brickwork at k = 10 (the benchmark plan): specialised against
+    the table-driven sweep on the whole state and against the oracle's stored
+    amplitudes."""
+    g = np.load(os.path.join(GOLDEN, "c2.npz"))
+    gates = W.brickwork_c2()
+    assert W.circuit_hash(gates, 28) == g["circuit_sha256"].item().decode()
+    plan = sim.partition(28, gates, 10)
+    try:
+        ref = sim.zero_state(28)
+        sim.apply(plan, ref)
+        sim.specialise(plan)
+        psi = sim.zero_state(28)
+        sim.apply(plan, psi)
+        torch.cuda.synchronize()
+        assert float((psi - ref).abs().max()) <= SAME
+        del ref
+        got = psi[torch.as_tensor(g["idx"], device=psi.device)].cpu().numpy()
+        assert np.max(np.abs(got - g["amp"])) <= TOL
+        z0 = float(sim.expect(W.z_on(0), psi, 28)[0])
+        assert abs(z0 - float(g["z0"])) < 1e-5
+    finally:
+        plan.close()
+        torch.cuda.empty_cache()
+
+
+def test_specialised_reads_theta_at_apply_time(sim):
+    """Parameterised rotations keep their matrices in device memory: one
+    specialised plan, two parameter vectors, both against the oracle."""
+    n = 14
+    gates, npar = W.ansatz(n, 4)
+    plan = sim.partition(n, gates, 10, 0, (4, 8))
+    try:
+        sim.specialise(plan)
+        for seed in (1, 2):
+            theta = W.ansatz_params(npar, seed=seed)
+            psi = sim.zero_state(n)
+            sim.apply(plan, psi, theta)
+            torch.cuda.synchronize()
+            assert maxabs(psi.cpu().numpy(), oracle.apply(n, gates, theta)) <= TOL
+    finally:
+        plan.close()
+
+
+def test_specialised_forward_feeds_the_adjoint(sim):
+    """Checkpoints written by the specialised sweeps equal the table-driven
+    ones, and the gradient from them matches the oracle's adjoint."""
+    n, npar = 16, 6
+    theta = np.random.default_rng(7).uniform(-3, 3, size=npar)
+    gates = W.random_circuit(n, 200, seed=3107, n_params=npar)
+    H = W.zz_chain_plus_x(n, 0.5)
+    e_ref, g_ref = oracle.adjoint(n, gates, theta, H)
+    plan = sim.partition(n, gates, 9, Q.PLAN_GRAD, (4, 8))
+    try:
+        res = []
+        for spec in (False, True):
+            if spec:
+                sim.specialise(plan)
+            psi = sim.zero_state(n)
+            ckpt = sim.checkpoints(plan)
+            sim.apply(plan, psi, theta, ckpt)
+            e, g = sim.adjoint_grad(plan, H, theta, psi, ckpt)
+            torch.cuda.synchronize()
+            res.append((ckpt.cpu().numpy(), float(e[0]), g.cpu().numpy()))
+    finally:
+        plan.close()
+    assert maxabs(res[0][0], res[1][0]) <= SAME
+    e, g = res[1][1], res[1][2]
+    assert abs(e - e_ref) < 1e-4
+    assert np.max(np.abs(g - g_ref[:len(g)])) < 1e-4
+
+
+def test_specialised_distributed_plan(sim):
+    """A plan with the distributed level (remap SWAP partitions included)."""
+    n, gl = 16, 2
+    gates = W.random_circuit(n, 250, seed=611)
+    ref = oracle.apply(n, gates)
+    plan = sim.partition_distributed(n, gates, gl, 8, 0, (4, 8))
+    try:
+        sim.specialise(plan)
+        psi = sim.zero_state(n)
+        sim.apply(plan, psi)
+        torch.cuda.synchronize()
+        assert maxabs(psi.cpu().numpy(), ref) <= TOL
+    finally:
+        plan.close()
+
+
+def test_specialised_qft_and_empty_circuit(sim):
+    """Diagonal-heavy partitions (QFT of a basis state against its closed
+    form) and a circuit with no gates (the state is left as it is)."""
+    n = 16
+    N = 1 << n
+    x = (5 * N) // 7
+    psi0 = torch.zeros(N, dtype=torch.complex64, device="cuda")
+    psi0[x] = 1
+    a, b, _ = both(sim, n, W.qft(n), 10, (4, 8), psi0=psi0)
+    ref = np.exp(2j * np.pi * x * np.arange(N) / N) / np.sqrt(N)
+    assert maxabs(b, ref) <= TOL and maxabs(a, b) <= SAME
+    rnd = torch.randn(1 << 10, dtype=torch.complex64, device="cuda")
+    a, b, info = both(sim, 10, W.ghz(10)[:0], 6, psi0=rnd)
+    assert np.array_equal(b, rnd.cpu().numpy()) and np.array_equal(a, b)
+
+
+def test_specialise_errors(sim):
+    """Batched plans and tiles above 64 KiB of LDS are not specialised; a
+    host-only plan has nothing to load on a device.  Each error leaves the
+    plan usable by the table-driven sweep."""
+    gates, npar = W.ansatz(6, 2)
+    batch = np.concatenate([gates, gates])
+    bp = sim.partition(6, batch, 0, 0, None, [0, len(gates), 2 * len(gates)])
+    try:
+        with pytest.raises(Q.QsvError) as e:
+            sim.specialise(bp)
+        assert e.value.code == -6
+    finally:
+        bp.close()
+    big = sim.partition(16, W.random_circuit(16, 50, seed=3), 12, 0, (5, 9))
+    try:
+        with pytest.raises(Q.QsvError) as e:
+            sim.specialise(big)
+        assert e.value.code == -6 and big.info["specialised"] == 0
+        psi = sim.zero_state(16)
+        sim.apply(big, psi)
+        torch.cuda.synchronize()
+        assert maxabs(psi.cpu().numpy(), oracle.apply(16, W.random_circuit(16, 50, seed=3))) <= TOL
+    finally:
+        big.close()
+    host = Q.qsv_partition(None, 8, W.ghz(8), None, 4, 0, None)
+    try:
+        with pytest.raises(Q.QsvError) as e:
+            Q.qsv_plan_specialise(sim.ctx, host)
+        assert e.value.code == -5
+    finally:
+        Q.qsv_plan_destroy(host)

@@ -214,3 +214,46 @@ def test_distributed_edge_cases():
     for n, g in ((16, 0), (16, 5), (2, 1)):
         with pytest.raises(Q.QsvError):
             Q.qsv_partition_distributed(None, n, W.ghz(n), g)
+
+
+# ---------------------------------------------------------------- specialised sweeps (compile only: no GPU here)
+
+def test_specialise_compiles_without_a_gpu():
+    """Generated kernels for every partition compile for gfx950 (hipRTC in the
+    qsv_rtc helper); without a context nothing is loaded."""
+    plan = Q.qsv_partition(None, 10, W.random_circuit(10, 120, seed=91, n_params=3), None, 6, 0, None)
+    try:
+        assert Q.qsv_plan_specialise(None, plan) > 0
+        assert Q.qsv_plan_info(plan)["specialised"] == 0
+    finally:
+        Q.qsv_plan_destroy(plan)
+
+
+def test_specialise_rejections():
+    gates, _ = W.ansatz(6, 2)
+    batched = Q.qsv_partition(None, 6, np.concatenate([gates, gates]), [0, len(gates), 2 * len(gates)], 0, 0, None)
+    big = Q.qsv_partition(None, 16, W.ghz(16), None, 12, 0, (5, 9))  # 14-qubit tiles: 128 KiB of LDS
+    try:
+        for plan in (batched, big):
+            with pytest.raises(Q.QsvError) as e:
+                Q.qsv_plan_specialise(None, plan)
+            assert e.value.code == -6
+        with pytest.raises(Q.QsvError) as e:
+            Q.qsv_plan_specialise(None, None)
+        assert e.value.code == -1
+    finally:
+        Q.qsv_plan_destroy(batched)
+        Q.qsv_plan_destroy(big)
+
+
+def test_compiler_helper_reports_errors(tmp_path):
+    import subprocess
+    helper = os.path.join(os.path.dirname(Q.library_path()), "qsv_rtc")
+    bad = tmp_path / "bad.hip"
+    bad.write_text('#include "spec.cuh"\nnot a declaration;\n')
+    r = subprocess.run([helper, str(bad), str(tmp_path / "bad.co"), str(tmp_path / "bad.log")])
+    assert r.returncode == 1
+    assert "error" in (tmp_path / "bad.log").read_text()
+    assert not (tmp_path / "bad.co").exists()
+    r = subprocess.run([helper, str(bad)])
+    assert r.returncode == 2
