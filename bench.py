@@ -3,12 +3,15 @@
 Headline (the `value`): the 28-qubit random brickwork circuit (40 layers of U3
 on every qubit + alternating CZ/CX nearest-neighbour pairs + 5% random
 long-range CX, seed 2, complex64, 2 GiB state), partitioned with k = 10 local
-qubits.  One step = the whole fused circuit applied to the state resident in
-HBM (every partition sweep) plus <Z_0> reduced in float64.  value = algorithmic
-HBM bytes of the step (16 B per amplitude per sweep + 8 B per amplitude for the
-expectation) / step time, in GB/s.
+qubits, every partition running as its own specialised kernel (generated and
+compiled before the timed region; the compile time is reported).  One step =
+the whole fused circuit applied to the state resident in HBM (every partition
+sweep) plus <Z_0> reduced in float64.  value = algorithmic HBM bytes of the
+step (16 B per amplitude per sweep + 8 B per amplitude for the expectation) /
+step time, in GB/s.
 
 Side measurements (separate timed regions, not in `value`):
+  * the same plan on the table-driven sweep kernel (before specialising);
   * the same circuit gate by gate (one sweep per gate) -> fused speed-up;
   * the 28-qubit QFT (diagonal-heavy), fused and gate by gate;
   * the headline circuit with the distributed level (4 and 16 emulated ranks,
@@ -43,8 +46,9 @@ FP32_VECTOR_PEAK = 157.3     # TFLOP/s (packed FP32 VALU; unpacked issue gives h
 HERE = os.path.dirname(os.path.abspath(__file__))
 # HBM traffic of the sweep kernel measured with rocprofv3 counters (FETCH_SIZE,
 # WRITE_SIZE) on this workload, and the same counters for a plain 2 GiB copy
-TRAFFIC_FILE = os.path.join(HERE, "profiles", "sweep_kernel_traffic_c2_28q.txt")
-SWEEP_SOURCES = ["sweep.hip", "gates.cuh", "plan.h"]
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "sweep_spec_traffic_c2_28q.txt")
+# sources of the specialised sweep kernels (generator and device templates)
+SWEEP_SOURCES = ["specialise.cpp", "rtc_options.h", "spec.cuh", "tile.cuh", "gates.cuh", "plan.h"]
 
 
 def sweep_sources_sha256():
@@ -81,28 +85,33 @@ def sync():
     torch.cuda.synchronize()
 
 
+def maybe_specialise(sim, plan, args):
+    """Specialise the plan unless --no-specialise; the host seconds, or None
+    where it stays table-driven (not asked, or a tile above 13 qubits)."""
+    if args.no_specialise:
+        return None
+    try:
+        return round(sim.specialise(plan), 2)
+    except Q.QsvError:
+        return None
+
+
 def fused_step(sim, plan, psi, Hz0, out):
     sim.apply(plan, psi)
     Q.qsv_expect(sim.ctx, Hz0, plan.n, 1, psi, out)
 
 
-def bench_headline(sim, args):
-    n, k = 28, args.k
-    gates = W.brickwork_c2()
-    tile = tuple(args.tile) if args.tile else None
-    plan = sim.partition(n, gates, k, 0, tile)
-    info = plan.info
-    psi = sim.zero_state(n)
-    Hz0 = W.z_on(0)
-    out = torch.empty(1, dtype=torch.float64, device=sim.device)
-    for _ in range(args.warmup):
+def timed_steps(sim, plan, psi, Hz0, out, warmup, steps):
+    """warmup + timed fused steps; returns (wall ms per step, summed sweep
+    kernel ms from HIP events, number of timed sweep launches)."""
+    for _ in range(warmup):
         fused_step(sim, plan, psi, Hz0, out)
     sync()
     Q.qsv_set_timing(sim.ctx, True)
     kernel_ms, launches = 0.0, 0
     sync()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         fused_step(sim, plan, psi, Hz0, out)
         ms, nl = Q.qsv_last_sweep_ms(sim.ctx)  # waits for this step's last sweep event
         kernel_ms += ms
@@ -110,10 +119,28 @@ def bench_headline(sim, args):
     sync()
     wall = time.perf_counter() - t0
     Q.qsv_set_timing(sim.ctx, False)
-    step_ms = wall * 1e3 / args.steps
+    return wall * 1e3 / steps, kernel_ms, launches
+
+
+def bench_headline(sim, args):
+    n, k = 28, args.k
+    gates = W.brickwork_c2()
+    tile = tuple(args.tile) if args.tile else None
+    plan = sim.partition(n, gates, k, 0, tile)
+    psi = sim.zero_state(n)
+    Hz0 = W.z_on(0)
+    out = torch.empty(1, dtype=torch.float64, device=sim.device)
+    res = {}
+    if not args.no_specialise:
+        # the same plan on the table-driven sweep first, then specialised
+        ms, kms, nl = timed_steps(sim, plan, psi, Hz0, out, 1, 3)
+        res["table_driven"] = dict(ms_per_step=round(ms, 3), avg_launch_ms=round(kms / max(1, nl), 4))
+        res["specialise_s"] = round(sim.specialise(plan), 2)
+    step_ms, kernel_ms, launches = timed_steps(sim, plan, psi, Hz0, out, args.warmup, args.steps)
+    info = plan.info
     dim = 1 << n
     step_bytes = info["bytes_per_apply"] + 8.0 * dim
-    res = dict(plan=info, step_ms=step_ms, step_bytes=step_bytes, kernel_ms_total=kernel_ms, launches=launches,
+    res.update(plan=info, step_ms=step_ms, step_bytes=step_bytes, kernel_ms_total=kernel_ms, launches=launches,
                z0=float(out[0]))
     plan.close()
     # gate by gate: same kernels, one gate per partition
@@ -223,6 +250,7 @@ def bench_qft(sim, args):
     res = dict(n_qubits=n, n_gates=int(len(gates)))
     for flags, key in ((0, "fused"), (Q.PLAN_GATE_BY_GATE, "gate_by_gate")):
         plan = sim.partition(n, gates, 10, flags, None)
+        spec_s = maybe_specialise(sim, plan, args) if flags == 0 else None
         sim.apply(plan, psi)
         sync()
         t0 = time.perf_counter()
@@ -231,6 +259,8 @@ def bench_qft(sim, args):
         dt = time.perf_counter() - t0
         sweeps = plan.info["n_partitions"]
         res[key] = dict(ms=round(dt * 1e3, 2), sweeps=sweeps, gbs=round(16.0 * (1 << n) * sweeps / dt / 1e9, 1))
+        if flags == 0:
+            res[key]["specialise_s"] = spec_s
         plan.close()
     res["fused_speedup"] = round(res["gate_by_gate"]["ms"] / res["fused"]["ms"], 2)
     del psi
@@ -248,6 +278,7 @@ def bench_distributed(sim, args):
     res = {}
     for g in (2, 4):
         plan = sim.partition_distributed(n, gates, g, args.k)
+        spec_s = maybe_specialise(sim, plan, args)
         di = Q.qsv_plan_distributed_info(plan.handle)
         parts = plan.partitions()
         remap_sweeps = sum(1 for _, gl in parts if gl and gl[0] < 0)
@@ -259,7 +290,7 @@ def bench_distributed(sim, args):
         dt = time.perf_counter() - t0
         res[f"g{g}"] = dict(ranks=1 << g, dist_partitions=di["n_dist_partitions"], exchange_swaps=di["exchange_swaps"],
                             remap_swaps=di["remap_swaps"], sweeps=plan.info["n_partitions"], remap_sweeps=remap_sweeps,
-                            ms=round(dt * 1e3, 2))
+                            ms=round(dt * 1e3, 2), specialise_s=spec_s)
         plan.close()
     del psi
     torch.cuda.empty_cache()
@@ -291,6 +322,7 @@ def bench_c3(sim, args):
     t0 = time.perf_counter()
     plan = sim.partition(n, gates, 0)
     plan_s = time.perf_counter() - t0
+    spec_s = maybe_specialise(sim, plan, args)
     info = plan.info
     psi = sim.zero_state(n)
     H = W.zz_chain(n)
@@ -307,6 +339,7 @@ def bench_c3(sim, args):
     return dict(n_qubits=n, n_gates=int(len(gates)), k_local=info["k_local"], reg_qubits=info["reg_qubits"],
                 log_threads=info["log_threads"], partitions=info["n_partitions"],
                 plan_and_tune_s=round(plan_s, 2), candidates=[list(c) for c in Q.qsv_last_autotune()],
+                specialise_s=spec_s,
                 apply_expect_ms=round(dt * 1e3, 1),
                 gbs=round((info["bytes_per_apply"] + 8.0 * (1 << n)) / dt / 1e9, 1), zz=float(out[0]))
 
@@ -359,6 +392,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--tile", type=int, nargs=2, default=None, help="reg_qubits log_threads")
+    ap.add_argument("--no-specialise", action="store_true",
+                    help="headline on the table-driven sweep kernel instead of per-partition kernels")
     ap.add_argument("--skip-gbg", action="store_true")
     ap.add_argument("--skip-grad", action="store_true")
     ap.add_argument("--skip-batched", action="store_true")
@@ -415,7 +450,9 @@ def main():
                     n_qubits=28, n_gates=info["n_gates"], k_local=info["k_local"], tile_qubits=info["tile_qubits"],
                     reg_qubits=info["reg_qubits"], log_threads=info["log_threads"],
                     partitions=info["n_partitions"], register_stages=info["n_stages"],
-                    plan_seconds=round(info["plan_seconds"], 4)),
+                    plan_seconds=round(info["plan_seconds"], 4),
+                    kernels="one specialised kernel per partition" if info["specialised"] else "table-driven sweep",
+                    specialise_seconds=head.get("specialise_s")),
         hbm_frac=round(value / HBM_PEAK_GBS, 4),
         roofline=roof,
         roofline_hbm=dict(achieved=round(achieved_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
@@ -425,6 +462,9 @@ def main():
                    flops_per_launch=sweep_flops, flops_per_byte=round(intensity, 2), ridge_flops_per_byte=round(ridge, 2),
                    tflops=round(achieved_tf, 3)),
     )
+    if "table_driven" in head:
+        td = head["table_driven"]
+        line["table_driven"] = dict(td, speedup_of_specialised=round(td["ms_per_step"] / head["step_ms"], 3))
     if "gbg_ms" in head:
         line["gate_by_gate"] = dict(ms=round(head["gbg_ms"], 2), sweeps=head["gbg_sweeps"],
                                     gbs=round(16.0 * (1 << 28) * head["gbg_sweeps"] / (head["gbg_ms"] * 1e-3) / 1e9, 1),

@@ -182,7 +182,12 @@ qsv_status qsv_plan_get_info(const qsv_plan *plan, qsv_plan_info *out);
  * forward it starts from (qsv_apply with checkpoints) uses the specialised
  * ones.
  * ctx NULL: generate and compile only, load nothing (a check that needs no
- * GPU); the plan is unchanged.  A plan that is already specialised is left
+ * GPU); the plan is unchanged.  The compile runs in the helper executable
+ * qsv_rtc next to this library.  Environment: QSV_KERNEL_CACHE=<dir> keeps
+ * every compiled program in <dir>, keyed by a hash of the program text, the
+ * device headers and the compile options, and reuses it; with
+ * QSV_KERNEL_CACHE_ONLY=1 as well, a program missing from the cache is an
+ * error (QSV_E_DEVICE) and no compiler process is started.  A plan that is already specialised is left
  * as it is.  seconds_out (may be NULL) receives the host time taken.
  * Errors: QSV_E_ARG (plan null), QSV_E_UNSUPPORTED (a plan of several
  * circuits, or tiles above 13 qubits, i.e. beyond 64 KiB of LDS), QSV_E_STATE

@@ -15,6 +15,8 @@
 #include <string>
 #include <vector>
 
+#include "rtc_options.h"
+
 namespace qsv {
 extern const int rtc_n_headers;
 extern const char *const rtc_header_names[];
@@ -38,10 +40,7 @@ int main(int argc, char **argv)
         log << "hiprtcCreateProgram: " << hiprtcGetErrorString(r) << "\n";
         return 1;
     }
-    // packed FP32 instructions stay disabled, as in the library's own build
-    const char *opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17",
-                          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
-    r = hiprtcCompileProgram(prog, (int)(sizeof opts / sizeof opts[0]), opts);
+    r = hiprtcCompileProgram(prog, qsv::rtc_n_options, const_cast<const char **>(qsv::rtc_options));
     size_t n = 0;
     hiprtcGetProgramLogSize(prog, &n);
     if (n > 1) {

@@ -7,6 +7,13 @@
 // beside the library; hipRTC serialises compiles within one process, so up to
 // 16 helpers run at once as child processes.  The caller loads the code
 // objects.
+//
+// Code-object cache (optional): with QSV_KERNEL_CACHE=<dir> every program's
+// code object is kept in <dir>/<key>.co, the key being a 64-bit FNV-1a hash
+// of the program, the embedded device headers and the compile options; a
+// later plan with the same program loads it instead of compiling.  With
+// QSV_KERNEL_CACHE_ONLY=1 as well, a program missing from the cache is an
+// error and no compiler process is started (for runs under a profiler).
 #include <dlfcn.h>
 #include <spawn.h>
 #include <sys/stat.h>
@@ -25,10 +32,16 @@
 #include <vector>
 
 #include "internal.h"
+#include "rtc_options.h"
 
 extern char **environ;
 
 namespace qsv {
+
+// The device headers the generated programs include (embedded at build time).
+extern const int rtc_n_headers;
+extern const char *const rtc_header_names[];
+extern const char *const rtc_header_texts[];
 
 namespace {
 
@@ -174,6 +187,26 @@ std::string helper_path()
     return (slash == std::string::npos ? std::string(".") : lib.substr(0, slash)) + "/qsv_rtc";
 }
 
+uint64_t fnv1a(uint64_t h, const std::string &s)
+{
+    for (unsigned char c : s) {
+        h ^= c;
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+std::string cache_key(const std::string &src)
+{
+    uint64_t h = 1469598103934665603ull;
+    for (int i = 0; i < rtc_n_options; ++i) h = fnv1a(h, rtc_options[i]);
+    for (int i = 0; i < rtc_n_headers; ++i) h = fnv1a(fnv1a(h, rtc_header_names[i]), rtc_header_texts[i]);
+    h = fnv1a(h, src);
+    char b[24];
+    std::snprintf(b, sizeof b, "%016llx", (unsigned long long)h);
+    return b;
+}
+
 struct TempDir {
     std::string path;
     std::vector<std::string> files;
@@ -192,7 +225,6 @@ std::string specialise_compile(const Plan &plan, std::vector<SpecChunk> &chunks,
     chunks.clear();
     if (np == 0) return "";
     const std::string helper = helper_path();
-    if (access(helper.c_str(), X_OK) != 0) return "compiler helper not found: " + helper;
     unsigned hw = std::thread::hardware_concurrency();
     const int nc = std::max(1, std::min({np, max_procs, hw ? (int)hw : 1}));
     // contiguous partition ranges of near-equal op counts
@@ -223,32 +255,50 @@ std::string specialise_compile(const Plan &plan, std::vector<SpecChunk> &chunks,
     if (!mkdtemp(tb.data())) return "cannot create a temporary directory for the generated kernels";
     tmp.path = tb.data();
     const size_t n = chunks.size();
-    std::vector<std::string> src(n), out(n), log(n);
+    const char *cdir = std::getenv("QSV_KERNEL_CACHE");
+    const std::string cache = cdir && *cdir ? cdir : "";
+    const char *conly = std::getenv("QSV_KERNEL_CACHE_ONLY");
+    const bool cache_only = !cache.empty() && conly && *conly && std::string(conly) != "0";
+    std::vector<std::string> src(n), out(n), log(n), cached(n);
+    std::vector<size_t> todo;
     for (size_t c = 0; c < n; ++c) {
+        const std::string text = specialise_source(plan, chunks[c].p0, chunks[c].p1);
+        if (!cache.empty()) {
+            cached[c] = cache + "/" + cache_key(text) + ".co";
+            const std::string code = read_file(cached[c]);
+            if (!code.empty()) {
+                chunks[c].code.assign(code.begin(), code.end());
+                continue;
+            }
+            if (cache_only) return "kernel not in the cache (QSV_KERNEL_CACHE_ONLY is set): " + cached[c];
+        }
         src[c] = tmp.path + "/p" + std::to_string(c) + ".hip";
         out[c] = tmp.path + "/p" + std::to_string(c) + ".co";
         log[c] = tmp.path + "/p" + std::to_string(c) + ".log";
         tmp.files.insert(tmp.files.end(), {src[c], out[c], log[c]});
         std::ofstream f(src[c], std::ios::binary);
-        f << specialise_source(plan, chunks[c].p0, chunks[c].p1);
+        f << text;
         if (!f) return "cannot write " + src[c];
+        todo.push_back(c);
     }
+    if (!todo.empty() && access(helper.c_str(), X_OK) != 0) return "compiler helper not found: " + helper;
     // run the helpers, at most nc at a time; wait only for our own children
     std::string err;
     std::vector<pid_t> pid(n, -1);
     std::deque<size_t> running;
     size_t next = 0;
     for (;;) {
-        while (err.empty() && next < n && (int)running.size() < nc) {
+        while (err.empty() && next < todo.size() && (int)running.size() < nc) {
+            const size_t c = todo[next++];
             std::string a0 = helper;
-            char *argv[] = {&a0[0], &src[next][0], &out[next][0], &log[next][0], nullptr};
+            char *argv[] = {&a0[0], &src[c][0], &out[c][0], &log[c][0], nullptr};
             pid_t child;
             if (posix_spawn(&child, helper.c_str(), nullptr, nullptr, argv, environ) != 0) {
                 err = "cannot start " + helper;
                 break;
             }
-            pid[next] = child;
-            running.push_back(next++);
+            pid[c] = child;
+            running.push_back(c);
         }
         if (running.empty()) break;
         const size_t c = running.front();
@@ -266,10 +316,17 @@ std::string specialise_compile(const Plan &plan, std::vector<SpecChunk> &chunks,
         }
     }
     if (!err.empty()) return err;
-    for (size_t c = 0; c < n; ++c) {
+    for (size_t c : todo) {
         const std::string code = read_file(out[c]);
         if (code.empty()) return "no code object from the compiler helper for chunk " + std::to_string(c);
         chunks[c].code.assign(code.begin(), code.end());
+        if (!cached[c].empty()) {  // publish by rename, so readers see whole files only
+            const std::string part = cached[c] + "." + std::to_string(getpid()) + ".tmp";
+            std::ofstream f(part, std::ios::binary);
+            f.write(code.data(), (std::streamsize)code.size());
+            f.close();
+            if (!f || std::rename(part.c_str(), cached[c].c_str()) != 0) std::remove(part.c_str());
+        }
     }
     return "";
 }

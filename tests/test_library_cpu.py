@@ -257,3 +257,28 @@ def test_compiler_helper_reports_errors(tmp_path):
     assert not (tmp_path / "bad.co").exists()
     r = subprocess.run([helper, str(bad)])
     assert r.returncode == 2
+
+
+def test_specialise_code_object_cache(tmp_path, monkeypatch):
+    """QSV_KERNEL_CACHE keeps one code object per generated program; with
+    QSV_KERNEL_CACHE_ONLY a plan whose programs are all cached specialises
+    without starting a compiler, and any other plan is refused."""
+    gates = W.random_circuit(9, 80, seed=92, n_params=2)
+    monkeypatch.setenv("QSV_KERNEL_CACHE", str(tmp_path))
+    plan = Q.qsv_partition(None, 9, gates, None, 6, 0, None)
+    try:
+        Q.qsv_plan_specialise(None, plan)
+        files = sorted(p.name for p in tmp_path.iterdir())
+        assert files and all(f.endswith(".co") and len(f) == 19 for f in files)
+        monkeypatch.setenv("QSV_KERNEL_CACHE_ONLY", "1")
+        Q.qsv_plan_specialise(None, plan)  # every program found: nothing compiled
+        assert sorted(p.name for p in tmp_path.iterdir()) == files
+    finally:
+        Q.qsv_plan_destroy(plan)
+    other = Q.qsv_partition(None, 9, W.random_circuit(9, 80, seed=93), None, 6, 0, None)
+    try:
+        with pytest.raises(Q.QsvError) as e:
+            Q.qsv_plan_specialise(None, other)
+        assert e.value.code == -4 and "not in the cache" in str(e.value)
+    finally:
+        Q.qsv_plan_destroy(other)
