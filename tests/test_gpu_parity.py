@@ -304,7 +304,7 @@ def test_c4_gradient_vs_oracle_and_fd(sim):
         g = th_req.grad.cpu().numpy()
     finally:
         plan.close()
-    assert abs(float(e) - e_ref) < 1e-4
+    assert abs(float(e.detach()) - e_ref) < 1e-4
     assert np.max(np.abs(g - g_ref)) < 1e-4
     h = 1e-3
     for j in (0, 1, 57, 200, 399):
