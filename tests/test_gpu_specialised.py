@@ -12,6 +12,7 @@ import torch
 import oracle
 import paper_2509_14098_amd as Q
 import workloads as W
+from spec_cases import RANDOM_CASES, SHAPES
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
@@ -48,8 +49,7 @@ def maxabs(a, b):
     return float(np.max(np.abs(np.asarray(a, np.complex128) - np.asarray(b, np.complex128))))
 
 
-@pytest.mark.parametrize("n,ng,k,tile", [(3, 60, 2, (3, 6)), (7, 100, 5, (4, 6)), (11, 200, 7, (4, 8)),
-                                         (13, 250, 10, (5, 8)), (16, 300, 12, (4, 9)), (20, 300, 12, (5, 8))])
+@pytest.mark.parametrize("n,ng,k,tile", RANDOM_CASES)
 def test_specialised_random_circuits(sim, n, ng, k, tile):
     """Every gate kind (fixed and parameterised) at random positions."""
     theta = np.random.default_rng(n).uniform(-3, 3, size=5)
@@ -57,6 +57,23 @@ def test_specialised_random_circuits(sim, n, ng, k, tile):
     ref = oracle.apply(n, gates, theta)
     a, b, info = both(sim, n, gates, k, tile, theta)
     assert info["n_partitions"] >= 1
+    assert maxabs(b, ref) <= TOL
+    assert maxabs(a, b) <= SAME
+
+
+@pytest.mark.parametrize("R,LW", SHAPES)
+def test_specialised_every_kernel_shape(sim, R, LW):
+    """Full tiles of every kernel shape up to 13 tile qubits, several tiles and
+    tile-index qubits, against the oracle and the table-driven sweep."""
+    n = R + LW + 2
+    theta = np.random.default_rng(R * 16 + LW).uniform(-3, 3, size=4)
+    # one register qubit holds a gate's local qubits only when at most one must be
+    # local: no SWAP or dense two-qubit gate there (the planner would widen R)
+    kinds = [k for k in W.KIND if k not in ("SWAP", "MAT2")] if R == 1 else None
+    gates = W.random_circuit(n, 150, seed=6000 + 16 * R + LW, n_params=4, kinds=kinds)
+    ref = oracle.apply(n, gates, theta)
+    a, b, info = both(sim, n, gates, min(n, R + LW - 1, 9), (R, LW), theta)
+    assert (info["reg_qubits"], info["log_threads"], info["tile_qubits"]) == (R, LW, R + LW)
     assert maxabs(b, ref) <= TOL
     assert maxabs(a, b) <= SAME
 

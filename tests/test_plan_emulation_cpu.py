@@ -116,6 +116,22 @@ def test_every_op_kind_is_exercised(emu):
     assert not missing, missing
 
 
+def test_specialised_parity_cases_cover_every_op_kind(emu):
+    """The random circuits of the specialised-kernel GPU tests lower to every
+    op kind as well (their plans are the ones emulated here), and the
+    emulated plans match the oracle."""
+    from spec_cases import RANDOM_CASES
+    emu.kind_counts(reset=True)
+    for n, ng, k, (R, LW) in RANDOM_CASES:
+        theta = np.random.default_rng(n).uniform(-3, 3, size=5)
+        gates = W.random_circuit(n, ng, seed=5000 + n, n_params=5)
+        out = emu(n, gates, k, R, LW, theta)
+        assert np.max(np.abs(out - oracle.apply(n, gates, theta))) < 1e-5, (n, R, LW)
+    counts = emu.kind_counts(reset=True)
+    missing = [k for k, v in OP_KINDS.items() if counts[v] == 0]
+    assert not missing, missing
+
+
 @pytest.mark.parametrize("n,g,R,LW,k", [(9, 2, 1, 6, 6), (10, 3, 1, 6, 5), (12, 4, 2, 6, 7), (14, 2, 4, 8, 10)])
 def test_distributed_plans(emu, n, g, R, LW, k):
     """Distributed level: remap SWAPs between distributed partitions, each
