@@ -12,51 +12,9 @@
 
 #include "gates.cuh"
 #include "kernels.h"
+#include "tile.cuh"
 
 namespace qsv {
-
-template <int LW>
-__device__ __forceinline__ void load_pairs(const float2 *__restrict__ src, float2 *lds, const DevPart *__restrict__ P,
-                                           uint64_t base, uint32_t tid)
-{
-    const int t = P->t;
-    const uint32_t npairs = 1u << (t - 1);
-    uint64_t gthr = 0;
-    for (int b = 1; b < LW + 1 && b < t; ++b)
-        if (((2u * tid) >> b) & 1u) gthr |= 1ull << P->tq[b];
-    for (uint32_t p0 = 0; p0 < npairs; p0 += (1u << LW)) {
-        const uint32_t p = p0 + tid;
-        if (p < npairs) {
-            uint64_t g = base | gthr;
-            for (int b = LW + 1; b < t; ++b)
-                if (((2u * p0) >> b) & 1u) g |= 1ull << P->tq[b];
-            const float4 v = *reinterpret_cast<const float4 *>(src + g);
-            lds[swz(2u * p)] = float2{v.x, v.y};
-            lds[swz(2u * p + 1)] = float2{v.z, v.w};
-        }
-    }
-}
-
-template <int LW>
-__device__ __forceinline__ void store_pairs(float2 *__restrict__ dst, const float2 *lds, const DevPart *__restrict__ P,
-                                            uint64_t base, uint32_t tid)
-{
-    const int t = P->t;
-    const uint32_t npairs = 1u << (t - 1);
-    uint64_t gthr = 0;
-    for (int b = 1; b < LW + 1 && b < t; ++b)
-        if (((2u * tid) >> b) & 1u) gthr |= 1ull << P->tq[b];
-    for (uint32_t p0 = 0; p0 < npairs; p0 += (1u << LW)) {
-        const uint32_t p = p0 + tid;
-        if (p < npairs) {
-            uint64_t g = base | gthr;
-            for (int b = LW + 1; b < t; ++b)
-                if (((2u * p0) >> b) & 1u) g |= 1ull << P->tq[b];
-            const float2 x = lds[swz(2u * p)], y = lds[swz(2u * p + 1)];
-            *reinterpret_cast<float4 *>(dst + g) = float4{x.x, x.y, y.x, y.y};
-        }
-    }
-}
 
 template <int R, int LW>
 __global__ __launch_bounds__(1 << LW) void reverse_kernel(const float2 *__restrict__ psi_src, float2 *__restrict__ lam,
@@ -154,6 +112,12 @@ static hipError_t launch_reverse_t(const Plan &plan, int pidx, const float2 *psi
                                   160 * 1024);
         (void)hipGetLastError();
         attr = true;
+    }
+    if (!plan.spec_rev_fn.empty() && plan.spec_rev_fn[pidx]) {  // the partition's specialised walk
+        const float *pool = plan.d_pool;
+        void *args[] = {&psi, &lam, &pool, &gpart, &stride};
+        return hipModuleLaunchKernel((hipFunction_t)plan.spec_rev_fn[pidx], (uint32_t)(1ull << P.n_glb), 1, 1,
+                                     1u << LW, 1, 1, (uint32_t)lds, s, args, nullptr);
     }
     hipLaunchKernelGGL((reverse_kernel<R, LW>), dim3((uint32_t)(1ull << P.n_glb)), dim3(1 << LW), lds, s, psi, lam,
                        plan.d_parts, pidx, plan.d_stages, plan.d_ops, plan.d_pool, gpart, stride);

@@ -551,7 +551,8 @@ qsv_status qsv_plan_specialise(qsv_ctx *ctx, qsv_plan *plan, double *seconds_out
         if (seconds_out) *seconds_out = secs;
         if (!ctx) return;  // compile only
         hip_check(hipSetDevice(ctx->device), "hipSetDevice");
-        std::vector<void *> fn(plan->parts.size(), nullptr), mods;
+        const bool rev = specialise_reverse(*plan);
+        std::vector<void *> fn(plan->parts.size(), nullptr), rfn(rev ? plan->parts.size() : 0, nullptr), mods;
         std::string lerr;
         for (const SpecChunk &c : chunks) {
             hipModule_t m = nullptr;
@@ -561,10 +562,12 @@ qsv_status qsv_plan_specialise(qsv_ctx *ctx, qsv_plan *plan, double *seconds_out
             }
             mods.push_back((void *)m);
             for (int p = c.p0; p < c.p1 && lerr.empty(); ++p) {
-                hipFunction_t f = nullptr;
-                const std::string name = "qsv_spec_" + std::to_string(p);
-                if (hipModuleGetFunction(&f, m, name.c_str()) != hipSuccess) lerr = "hipModuleGetFunction " + name;
-                fn[p] = (void *)f;
+                for (int r = 0; r < (rev ? 2 : 1) && lerr.empty(); ++r) {
+                    hipFunction_t f = nullptr;
+                    const std::string name = (r ? "qsv_rspec_" : "qsv_spec_") + std::to_string(p);
+                    if (hipModuleGetFunction(&f, m, name.c_str()) != hipSuccess) lerr = "hipModuleGetFunction " + name;
+                    (r ? rfn : fn)[p] = (void *)f;
+                }
             }
             if (!lerr.empty()) break;
         }
@@ -574,6 +577,7 @@ qsv_status qsv_plan_specialise(qsv_ctx *ctx, qsv_plan *plan, double *seconds_out
             fail(QSV_E_DEVICE, lerr);
         }
         plan->spec_fn = std::move(fn);
+        plan->spec_rev_fn = std::move(rfn);
         plan->spec_modules = std::move(mods);
         plan->specialised = true;
         plan->specialise_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

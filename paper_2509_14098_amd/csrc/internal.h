@@ -84,6 +84,7 @@ struct Plan {
     int64_t remap_swaps = 0;          // all remap SWAPs (including the final return to logical order)
     // specialised sweeps (qsv_plan_specialise): per partition a hipFunction_t, null for none
     std::vector<void *> spec_fn;
+    std::vector<void *> spec_rev_fn;  // the adjoint walk's kernels (gradient plans with tiles of 12 qubits or fewer)
     std::vector<void *> spec_modules; // hipModule_t, unloaded with the plan
     bool specialised = false;
     double specialise_seconds = 0;
@@ -122,6 +123,9 @@ struct SpecChunk {
     std::vector<char> code;
 };
 std::string specialise_source(const Plan &plan, int p0, int p1);
+// Whether the adjoint walk is specialised too: gradient plans whose psi and
+// lambda tiles fit 64 KiB of LDS together.
+bool specialise_reverse(const Plan &plan);
 // Compiles every partition of a single-circuit plan on up to max_threads host
 // threads; returns "" or the error (with the compiler log).
 std::string specialise_compile(const Plan &plan, std::vector<SpecChunk> &chunks, int max_threads);

@@ -88,8 +88,14 @@ void put_op(std::string &s, const DevOp &o)
 
 }  // namespace
 
-// Source of the program holding the specialised kernels qsv_spec_<p> of
-// partitions [p0, p1).  Every float is written as an exact hexadecimal literal.
+bool specialise_reverse(const Plan &plan)
+{
+    return (plan.flags & QSV_PLAN_GRAD) && ((size_t)16 << plan.t) <= (size_t)64 * 1024;
+}
+
+// Source of the program holding the specialised kernels qsv_spec_<p> (and,
+// for gradient plans, qsv_rspec_<p>) of partitions [p0, p1).  Every float is
+// written as an exact hexadecimal literal.
 std::string specialise_source(const Plan &plan, int p0, int p1)
 {
     std::set<int32_t> dyn_mats;  // pool entries written from theta at apply time
@@ -165,6 +171,15 @@ std::string specialise_source(const Plan &plan, int p0, int p1)
                       "{\n    qsv::spec_sweep<qsv_gen::P%d>(psi, ckpt, pool);\n}\n",
                       1 << plan.LW, p, p);
         s += b;
+        if (specialise_reverse(plan)) {
+            std::snprintf(b, sizeof b,
+                          "extern \"C\" __global__ __launch_bounds__(%d) void qsv_rspec_%d(const float2 *__restrict__ "
+                          "psi, float2 *__restrict__ lam, const float *__restrict__ pool, double *__restrict__ gpart, "
+                          "int64_t slot_stride)\n"
+                          "{\n    qsv::spec_reverse<qsv_gen::P%d>(psi, lam, pool, gpart, slot_stride);\n}\n",
+                          1 << plan.LW, p, p);
+            s += b;
+        }
     }
     return s;
 }

@@ -144,4 +144,49 @@ __device__ __forceinline__ void store_tile(float2 *__restrict__ psi, float2 *__r
     }
 }
 
+// Tile copies HBM -> LDS and LDS -> HBM for the adjoint walk, one amplitude
+// pair per thread per step (any tile size).
+template <int LW>
+__device__ __forceinline__ void load_pairs(const float2 *__restrict__ src, float2 *lds, const DevPart *__restrict__ P,
+                                           uint64_t base, uint32_t tid)
+{
+    const int t = P->t;
+    const uint32_t npairs = 1u << (t - 1);
+    uint64_t gthr = 0;
+    for (int b = 1; b < LW + 1 && b < t; ++b)
+        if (((2u * tid) >> b) & 1u) gthr |= 1ull << P->tq[b];
+    for (uint32_t p0 = 0; p0 < npairs; p0 += (1u << LW)) {
+        const uint32_t p = p0 + tid;
+        if (p < npairs) {
+            uint64_t g = base | gthr;
+            for (int b = LW + 1; b < t; ++b)
+                if (((2u * p0) >> b) & 1u) g |= 1ull << P->tq[b];
+            const float4 v = *reinterpret_cast<const float4 *>(src + g);
+            lds[swz(2u * p)] = float2{v.x, v.y};
+            lds[swz(2u * p + 1)] = float2{v.z, v.w};
+        }
+    }
+}
+
+template <int LW>
+__device__ __forceinline__ void store_pairs(float2 *__restrict__ dst, const float2 *lds, const DevPart *__restrict__ P,
+                                            uint64_t base, uint32_t tid)
+{
+    const int t = P->t;
+    const uint32_t npairs = 1u << (t - 1);
+    uint64_t gthr = 0;
+    for (int b = 1; b < LW + 1 && b < t; ++b)
+        if (((2u * tid) >> b) & 1u) gthr |= 1ull << P->tq[b];
+    for (uint32_t p0 = 0; p0 < npairs; p0 += (1u << LW)) {
+        const uint32_t p = p0 + tid;
+        if (p < npairs) {
+            uint64_t g = base | gthr;
+            for (int b = LW + 1; b < t; ++b)
+                if (((2u * p0) >> b) & 1u) g |= 1ull << P->tq[b];
+            const float2 x = lds[swz(2u * p)], y = lds[swz(2u * p + 1)];
+            *reinterpret_cast<float4 *>(dst + g) = float4{x.x, x.y, y.x, y.y};
+        }
+    }
+}
+
 }  // namespace qsv

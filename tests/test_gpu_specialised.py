@@ -124,7 +124,8 @@ def test_specialised_reads_theta_at_apply_time(sim):
 
 def test_specialised_forward_feeds_the_adjoint(sim):
     """Checkpoints written by the specialised sweeps equal the table-driven
-    ones, and the gradient from them matches the oracle's adjoint."""
+    ones; the specialised adjoint walk gives the table-driven gradient and
+    matches the oracle's adjoint."""
     n, npar = 16, 6
     theta = np.random.default_rng(7).uniform(-3, 3, size=npar)
     gates = W.random_circuit(n, 200, seed=3107, n_params=npar)
@@ -145,9 +146,32 @@ def test_specialised_forward_feeds_the_adjoint(sim):
     finally:
         plan.close()
     assert maxabs(res[0][0], res[1][0]) <= SAME
+    assert abs(res[0][1] - res[1][1]) < 1e-6 and np.max(np.abs(res[0][2] - res[1][2])) < 1e-5
     e, g = res[1][1], res[1][2]
     assert abs(e - e_ref) < 1e-4
     assert np.max(np.abs(g - g_ref[:len(g)])) < 1e-4
+
+
+def test_specialised_c4_gradient(sim):
+    """20-qubit RY.RZ + CX-ladder ansatz, 10 layers, 400 parameters, through
+    the autograd Function on a specialised plan (forward sweeps and adjoint
+    walk generated): energy and every gradient entry against the oracle."""
+    n = 20
+    gates, npar = W.ansatz(n, 10)
+    theta = W.ansatz_params(npar, seed=4)
+    H = W.zz_chain_plus_x(n, 0.5)
+    e_ref, g_ref = oracle.adjoint(n, gates, theta, H)
+    plan = sim.partition(n, gates, 10, Q.PLAN_GRAD)
+    try:
+        sim.specialise(plan)
+        th = torch.as_tensor(theta, device="cuda").clone().requires_grad_(True)
+        e = Q.Energy.apply(th, sim, plan, H)
+        e.backward()
+        g = th.grad.cpu().numpy()
+    finally:
+        plan.close()
+    assert abs(float(e.detach()) - e_ref) < 1e-4
+    assert np.max(np.abs(g - g_ref)) < 1e-4
 
 
 def test_specialised_distributed_plan(sim):
