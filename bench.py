@@ -20,7 +20,8 @@ Side measurements (separate timed regions, not in `value`):
     shape chosen by the autotuner, plus <sum Z_i Z_i+1>;
   * host planning time for 34-qubit circuits of 20 400 and 51 000 gates;
   * the 20-qubit RY.RZ + CX-ladder ansatz (400 parameters): adjoint gradient
-    time / forward time;
+    time / forward time (forward = apply + energy), specialised and
+    table-driven;
   * 2048 x 14-qubit ansatz instances (depths 4..16): energy + gradient of all
     instances in one persistent launch;
   * the oracle (plain complex128 CPU simulator) on a bounded prefix of the
@@ -180,23 +181,34 @@ def bench_gradient(sim, args):
     def backward():
         Q.qsv_adjoint_grad(sim.ctx, plan.handle, H, theta, psi, ckpt, energy, grad)
 
-    for _ in range(3):
-        forward()
-        backward()
-    sync()
-    reps = 20
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        forward()
-    sync()
-    t_fwd = (time.perf_counter() - t0) / reps
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        backward()
-    sync()
-    t_bwd = (time.perf_counter() - t0) / reps
-    res = dict(fwd_ms=t_fwd * 1e3, grad_ms=t_bwd * 1e3, ratio=t_bwd / t_fwd, energy=float(energy[0]),
-               partitions=plan.info["n_partitions"])
+    def timed():
+        for _ in range(3):
+            forward()
+            backward()
+        sync()
+        reps = 20
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            forward()
+        sync()
+        t_fwd = (time.perf_counter() - t0) / reps
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            backward()
+        sync()
+        t_bwd = (time.perf_counter() - t0) / reps
+        return t_fwd * 1e3, t_bwd * 1e3
+
+    # the table-driven kernels first, then the plan specialised (forward sweeps
+    # and adjoint walk generated per partition)
+    f0, b0 = timed()
+    res = dict(fwd_ms=f0, grad_ms=b0, ratio=b0 / f0)
+    spec_s = maybe_specialise(sim, plan, args)
+    if spec_s is not None:
+        f1, b1 = timed()
+        res = dict(fwd_ms=f1, grad_ms=b1, ratio=b1 / f1, specialise_s=spec_s,
+                   table_driven=dict(fwd_ms=round(f0, 4), grad_ms=round(b0, 4), ratio=round(b0 / f0, 4)))
+    res.update(energy=float(energy[0]), partitions=plan.info["n_partitions"])
     plan.close()
     return res
 

@@ -775,12 +775,12 @@ qsv_status qsv_adjoint_grad(qsv_ctx *ctx, const qsv_plan *plan, const qsv_pauli_
         const size_t dim = (size_t)1 << n;
         // scratch: lambda state + reduction partials + gradient partials
         float2 *lam = (float2 *)ctx->ensure(ctx->lam, ctx->lam_bytes, dim * sizeof(float2));
-        const int n_blocks = 512;
+        const int n_blocks = 4096;  // cap on the blocks of lambda = H psi
         const int t = plan->t;
         const int64_t n_tiles = (int64_t)1 << (n - t);
         const int64_t waves = std::max(1, (1 << plan->LW) / 64);
         const int64_t n_slots = (int64_t)plan->grad_param.size();
-        size_t red = sizeof(double) * n_blocks * std::max<size_t>(1, g.groups.size());
+        size_t red = sizeof(double) * (size_t)apply_h_blocks(n, n_blocks);
         size_t gp = sizeof(double) * (size_t)std::max<int64_t>(1, n_slots) * n_tiles * waves;
         size_t sl = sizeof(double) * (size_t)std::max<int64_t>(1, n_slots);
         const size_t gp_off = (red + 255) & ~size_t(255), sl_off = (gp_off + gp + 255) & ~size_t(255);

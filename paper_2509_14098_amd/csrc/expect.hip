@@ -171,10 +171,18 @@ hipError_t launch_expect(const DevGroup *groups, int n_groups, const DevTerm *te
     return hipGetLastError();
 }
 
+int apply_h_blocks(int n, int cap)
+{
+    // one amplitude per thread: each amplitude walks every Pauli group with a
+    // dependent table load and gather, so many waves are needed to cover them
+    const uint64_t b = std::max<uint64_t>(1, (1ull << n) / RED_THREADS);
+    return (int)std::min<uint64_t>(b, (uint64_t)std::max(cap, 1));
+}
+
 hipError_t launch_apply_h(const DevGroup *groups, int n_groups, const DevTerm *terms, int n, const float2 *psi,
                           float2 *lam, double *partials, int n_blocks, double *energy, hipStream_t s)
 {
-    const int nb = blocks_for(1ull << n, n_blocks);
+    const int nb = apply_h_blocks(n, n_blocks);
     hipLaunchKernelGGL(apply_h_kernel, dim3(nb), dim3(RED_THREADS), 0, s, groups, n_groups, terms, n, psi, lam,
                        partials);
     hipError_t e = hipGetLastError();

@@ -25,6 +25,8 @@ struct DevGroup {
 int expect_blocks(int n, int cap);
 hipError_t launch_expect(const DevGroup *groups, int n_groups, const DevTerm *terms, int n, int64_t batch,
                          const float2 *psi, double *partials, int n_blocks, double *out, hipStream_t s);
+// Blocks launch_apply_h uses for 2^n amplitudes and a cap (one partial each).
+int apply_h_blocks(int n, int cap);
 hipError_t launch_apply_h(const DevGroup *groups, int n_groups, const DevTerm *terms, int n, const float2 *psi,
                           float2 *lam, double *partials, int n_blocks, double *energy, hipStream_t s);
 
