@@ -4,7 +4,8 @@ Headline (the `value`): the 28-qubit random brickwork circuit (40 layers of U3
 on every qubit + alternating CZ/CX nearest-neighbour pairs + 5% random
 long-range CX, seed 2, complex64, 2 GiB state), partitioned with k = 10 local
 qubits, every partition running as its own specialised kernel (generated and
-compiled before the timed region; the compile time is reported).  One step =
+compiled before the timed region; the compile time is reported).  The tile
+shape is chosen by the autotuner timing specialised candidates at k = 10.  One step =
 the whole fused circuit applied to the state resident in HBM (every partition
 sweep) plus <Z_0> reduced in float64.  value = algorithmic HBM bytes of the
 step (16 B per amplitude per sweep + 8 B per amplitude for the expectation) /
@@ -17,7 +18,8 @@ Side measurements (separate timed regions, not in `value`):
   * the headline circuit with the distributed level (4 and 16 emulated ranks,
     remaps as SWAP sweeps);
   * the 32-qubit, 60-layer U3 + random-matching CX circuit with k and the tile
-    shape chosen by the autotuner, plus <sum Z_i Z_i+1>;
+    shape chosen by the autotuner (timing specialised candidates), plus
+    <sum Z_i Z_i+1>;
   * host planning time for 34-qubit circuits of 20 400 and 51 000 gates;
   * the 20-qubit RY.RZ + CX-ladder ansatz (400 parameters): adjoint gradient
     time / forward time (forward = apply + energy), specialised and
@@ -127,7 +129,10 @@ def bench_headline(sim, args):
     n, k = 28, args.k
     gates = W.brickwork_c2()
     tile = tuple(args.tile) if args.tile else None
-    plan = sim.partition(n, gates, k, 0, tile)
+    # the tile shape is tuned at k = 10 by timing specialised candidates (unless given)
+    flags = 0 if (args.no_specialise or tile) else Q.PLAN_TUNE_SPECIALISED
+    plan = sim.partition(n, gates, k, flags, tile)
+    tuned = [list(c) for c in Q.qsv_last_autotune()] if flags else None
     psi = sim.zero_state(n)
     Hz0 = W.z_on(0)
     out = torch.empty(1, dtype=torch.float64, device=sim.device)
@@ -142,7 +147,7 @@ def bench_headline(sim, args):
     dim = 1 << n
     step_bytes = info["bytes_per_apply"] + 8.0 * dim
     res.update(plan=info, step_ms=step_ms, step_bytes=step_bytes, kernel_ms_total=kernel_ms, launches=launches,
-               z0=float(out[0]))
+               z0=float(out[0]), tile_candidates=tuned)
     plan.close()
     # gate by gate: same kernels, one gate per partition
     if not args.skip_gbg:
@@ -332,7 +337,7 @@ def bench_c3(sim, args):
     n = 32
     gates = W.brickwork_c3()
     t0 = time.perf_counter()
-    plan = sim.partition(n, gates, 0)
+    plan = sim.partition(n, gates, 0, 0 if args.no_specialise else Q.PLAN_TUNE_SPECIALISED)
     plan_s = time.perf_counter() - t0
     spec_s = maybe_specialise(sim, plan, args)
     info = plan.info
@@ -462,7 +467,8 @@ def main():
                     n_qubits=28, n_gates=info["n_gates"], k_local=info["k_local"], tile_qubits=info["tile_qubits"],
                     reg_qubits=info["reg_qubits"], log_threads=info["log_threads"],
                     partitions=info["n_partitions"], register_stages=info["n_stages"],
-                    plan_seconds=round(info["plan_seconds"], 4),
+                    plan_and_tune_seconds=round(info["plan_seconds"], 3),
+                    tile_candidates=head.get("tile_candidates"),
                     kernels="one specialised kernel per partition" if info["specialised"] else "table-driven sweep",
                     specialise_seconds=head.get("specialise_s")),
         hbm_frac=round(value / HBM_PEAK_GBS, 4),

@@ -95,6 +95,12 @@ typedef struct qsv_plan qsv_plan;
 /* Plan flags. */
 #define QSV_PLAN_GATE_BY_GATE 1u /* one gate per partition: the unfused baseline, same kernels */
 #define QSV_PLAN_GRAD 2u         /* keep what qsv_adjoint_grad needs (checkpoint layout) */
+/* Autotune for specialised kernels (qsv_plan_specialise): candidates are timed
+ * as specialised sweeps (their sampled partitions compiled, in seconds of host
+ * time each), only tile shapes of at most 13 qubits are tried, and with
+ * k_local > 0 only the tile shape is tuned, at that k.  Needs a context and a
+ * single circuit; ignored when a tile shape is given. */
+#define QSV_PLAN_TUNE_SPECIALISED 4u
 
 /* Kernel tile shape: a workgroup of 2^log_threads threads holds a tile of
  * 2^(reg_qubits + log_threads) amplitudes, reg_qubits of them per thread.
@@ -152,8 +158,10 @@ qsv_status qsv_set_stream(qsv_ctx *ctx, void *hip_stream);
  * device (autotuner, needs ctx; n_qubits above the default tile): k in
  * {8, 10, 12} below the tile size, five tile shapes; each candidate's time is
  * an evenly spaced sample of at most 8 of its partition sweeps on a scratch
- * state (2^n x 8 bytes, freed afterwards) scaled to all partitions.  The
- * choice is cached per device and circuit.  tile may be NULL (default shape).
+ * state (2^n x 8 bytes, freed afterwards) scaled to all partitions.  With
+ * QSV_PLAN_TUNE_SPECIALISED the samples run as specialised kernels (also
+ * with k_local > 0, then tuning the tile shape only).  The choice is cached
+ * per device, circuit, flags and k_local.  tile may be NULL (default shape).
  * The gate array is copied; it is not retained.  The plan is freed by
  * qsv_plan_destroy.
  * Batched plans (n_circuits > 1) keep each whole state on chip: 4 <= n <= 14.
@@ -283,8 +291,8 @@ qsv_status qsv_adjoint_grad(qsv_ctx *ctx, const qsv_plan *plan, const qsv_pauli_
                             const double *theta_dev, const void *psi_final_dev, const void *ckpt_dev,
                             double *energy_dev, double *grad_dev);
 
-/* Candidates timed by the last autotuning run in this process (k_local == 0
- * on a context): writes up to cap records of 4 int32 (k, reg_qubits,
+/* Candidates timed by the last autotuning run in this process (k_local == 0,
+ * or QSV_PLAN_TUNE_SPECIALISED, on a context): writes up to cap records of 4 int32 (k, reg_qubits,
  * log_threads, estimated microseconds for the whole circuit) and returns the
  * number of candidates. */
 int32_t qsv_last_autotune(int32_t *out, int32_t cap);

@@ -25,6 +25,7 @@ KIND = dict(H=1, X=2, Y=3, Z=4, S=5, SDG=6, T=7, TDG=8, SX=9, RX=10, RY=11, RZ=1
             CX=20, CY=21, CZ=22, CP=23, SWAP=24, RZZ=25, MAT1=30, MAT2=31)
 PLAN_GATE_BY_GATE = 1
 PLAN_GRAD = 2
+PLAN_TUNE_SPECIALISED = 4
 
 
 class QsvError(RuntimeError):

@@ -354,55 +354,113 @@ static std::map<std::pair<int, size_t>, TuneChoice> g_tune_cache;
 static std::vector<TuneChoice> g_last_tune;
 static std::mutex g_tune_mutex;  // the cache and the last-run record are process-wide
 
-static TuneChoice autotune(qsv_ctx *ctx, int n, const qsv_gate *gates, const std::vector<int64_t> &off, uint32_t flags)
+// Loads compiled programs of specialised kernels into the plan (current
+// device): the forward kernel of every partition the chunks cover and, with
+// rev, its reverse kernel.
+static void load_spec(Plan &plan, const std::vector<SpecChunk> &chunks, bool rev)
 {
+    std::vector<void *> fn(plan.parts.size(), nullptr), rfn(rev ? plan.parts.size() : 0, nullptr), mods;
+    std::string lerr;
+    for (const SpecChunk &c : chunks) {
+        hipModule_t m = nullptr;
+        if (hipModuleLoadData(&m, c.code.data()) != hipSuccess) {
+            lerr = "hipModuleLoadData failed";
+            break;
+        }
+        mods.push_back((void *)m);
+        for (int p = c.p0; p < c.p1 && lerr.empty(); ++p) {
+            for (int r = 0; r < (rev ? 2 : 1) && lerr.empty(); ++r) {
+                hipFunction_t f = nullptr;
+                const std::string name = (r ? "qsv_rspec_" : "qsv_spec_") + std::to_string(p);
+                if (hipModuleGetFunction(&f, m, name.c_str()) != hipSuccess) lerr = "hipModuleGetFunction " + name;
+                (r ? rfn : fn)[p] = (void *)f;
+            }
+        }
+        if (!lerr.empty()) break;
+    }
+    if (!lerr.empty()) {
+        (void)hipGetLastError();
+        for (void *m : mods) (void)hipModuleUnload((hipModule_t)m);
+        fail(QSV_E_DEVICE, lerr);
+    }
+    for (void *m : plan.spec_modules) (void)hipModuleUnload((hipModule_t)m);
+    plan.spec_fn = std::move(fn);
+    plan.spec_rev_fn = std::move(rfn);
+    plan.spec_modules = std::move(mods);
+}
+
+static TuneChoice autotune(qsv_ctx *ctx, int n, const qsv_gate *gates, const std::vector<int64_t> &off, uint32_t flags,
+                           int k_fixed)
+{
+    const bool spec = flags & QSV_PLAN_TUNE_SPECIALISED;
+    flags &= ~QSV_PLAN_TUNE_SPECIALISED;
     std::string key((const char *)gates, sizeof(qsv_gate) * (size_t)off.back());
-    key += std::to_string(n) + "/" + std::to_string(flags);
+    key += std::to_string(n) + "/" + std::to_string(flags) + "/" + std::to_string(k_fixed) + (spec ? "/s" : "");
     auto ck = std::make_pair(ctx->device, std::hash<std::string>()(key));
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     auto it = g_tune_cache.find(ck);
     if (it != g_tune_cache.end()) return it->second;
-    TuneChoice best{std::min(9, n), 4, 8, -1.0};
+    TuneChoice best{k_fixed ? k_fixed : std::min(9, n), 4, 8, -1.0};
     g_last_tune.clear();
     void *psi = nullptr;
     if (hipMalloc(&psi, (size_t)8 << n) != hipSuccess) {
         (void)hipGetLastError();
         return best;  // no room for a trial state: default shape
     }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    struct Release {  // also on an error thrown by a candidate
+        qsv_ctx *ctx;
+        void *&psi;
+        hipEvent_t &e0, &e1;
+        ~Release()
+        {
+            (void)hipStreamSynchronize(ctx->stream);
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+            dev_free(psi);
+        }
+    } release{ctx, psi, e0, e1};
     hip_check(hipMemsetAsync(psi, 0, (size_t)8 << n, ctx->stream), "hipMemsetAsync");
-    hipEvent_t e0, e1;
     hip_check(hipEventCreate(&e0), "hipEventCreate");
     hip_check(hipEventCreate(&e1), "hipEventCreate");
     const int shapes[][2] = {{5, 8}, {4, 8}, {4, 9}, {5, 9}, {4, 10}};
     for (auto &sh : shapes) {
         const int R = sh[0], LW = sh[1], t = R + LW;
         if ((flags & QSV_PLAN_GRAD) && t > 13) continue;
+        if (spec && t > 13) continue;  // specialised sweeps take tiles of at most 13 qubits
         for (int k : {8, 10, 12}) {
-            if (k >= t || k > n) continue;
+            if (k_fixed) k = k_fixed;
+            if (k >= t || k > n) {
+                if (k_fixed) break;
+                continue;
+            }
             qsv_plan *P = make_plan(ctx, n, gates, off, flags, k, R, LW);
+            std::unique_ptr<qsv_plan, void (*)(qsv_plan *)> guard(P, [](qsv_plan *p) { qsv_plan_destroy(p); });
             // time an evenly spaced sample of at most 8 partition sweeps (after one warm-up
             // sweep) and scale it to the whole circuit
             const int np = (int)P->parts.size(), ns = std::min(np, 8);
-            float ms = 0;
-            hip_check(launch_sweep(*P, P->R, P->LW, 0, (float2 *)psi, nullptr, ctx->stream), "sweep");
-            hip_check(hipEventRecord(e0, ctx->stream), "hipEventRecord");
-            for (int i = 0; i < ns; ++i) {
-                const int p = (int)(((int64_t)2 * i + 1) * np / (2 * ns));
-                hip_check(launch_sweep(*P, P->R, P->LW, p, (float2 *)psi, nullptr, ctx->stream), "sweep");
+            std::vector<int> sample;
+            for (int i = 0; i < ns; ++i) sample.push_back((int)(((int64_t)2 * i + 1) * np / (2 * ns)));
+            if (spec) {  // the sampled partitions as specialised kernels
+                std::vector<SpecChunk> chunks;
+                const std::string err = specialise_compile(*P, chunks, 16, &sample);
+                if (!err.empty()) fail(QSV_E_DEVICE, err);
+                load_spec(*P, chunks, false);
             }
+            float ms = 0;
+            hip_check(launch_sweep(*P, P->R, P->LW, sample[0], (float2 *)psi, nullptr, ctx->stream), "sweep");
+            hip_check(hipEventRecord(e0, ctx->stream), "hipEventRecord");
+            for (int p : sample)
+                hip_check(launch_sweep(*P, P->R, P->LW, p, (float2 *)psi, nullptr, ctx->stream), "sweep");
             hip_check(hipEventRecord(e1, ctx->stream), "hipEventRecord");
             hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
             hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
             ms *= (float)np / (float)ns;
-            qsv_plan_destroy(P);
             g_last_tune.push_back(TuneChoice{k, R, LW, ms});
             if (best.ms < 0 || ms < best.ms) best = TuneChoice{k, R, LW, ms};
+            if (k_fixed) break;
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    hip_check(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
-    dev_free(psi);
     g_tune_cache[ck] = best;
     return best;
 }
@@ -417,7 +475,7 @@ qsv_status qsv_partition(qsv_ctx *ctx, int32_t n_qubits, const qsv_gate *gates, 
         if (n_qubits < 1 || n_qubits > 34) fail(QSV_E_ARG, "n_qubits must be in [1, 34]");
         if (k_local < 0) fail(QSV_E_ARG, "k_local must be >= 0");
         if (n_circuits < 1) fail(QSV_E_ARG, "n_circuits must be >= 1");
-        if (flags & ~(QSV_PLAN_GATE_BY_GATE | QSV_PLAN_GRAD)) fail(QSV_E_ARG, "unknown flag");
+        if (flags & ~(QSV_PLAN_GATE_BY_GATE | QSV_PLAN_GRAD | QSV_PLAN_TUNE_SPECIALISED)) fail(QSV_E_ARG, "unknown flag");
         if (!circ_offsets) fail(QSV_E_ARG, "circ_offsets is null");
         std::vector<int64_t> off(n_circuits + 1, 0);
         for (int c = 0; c <= n_circuits; ++c) off[c] = circ_offsets[c];
@@ -451,10 +509,13 @@ qsv_status qsv_partition(qsv_ctx *ctx, int32_t n_qubits, const qsv_gate *gates, 
             fail(QSV_E_UNSUPPORTED, "gradient plans need a tile of at most 13 qubits");
         int k = k_local == 0 ? (n_qubits <= R + LW ? n_qubits : R + LW - 3) : k_local;
         if (n_circuits > 1) k = n_qubits;  // one partition per circuit: the whole state stays on chip
-        if (k_local == 0 && ctx && n_circuits == 1 && !user_tile && n_qubits > R + LW &&
+        const bool tune_spec = flags & QSV_PLAN_TUNE_SPECIALISED;
+        flags &= ~QSV_PLAN_TUNE_SPECIALISED;
+        if ((k_local == 0 || tune_spec) && ctx && n_circuits == 1 && !user_tile && n_qubits > R + LW &&
             !(flags & QSV_PLAN_GATE_BY_GATE)) {
             hip_check(hipSetDevice(ctx->device), "hipSetDevice");
-            TuneChoice c = autotune(ctx, n_qubits, gates, off, flags);
+            TuneChoice c = autotune(ctx, n_qubits, gates, off, flags | (tune_spec ? QSV_PLAN_TUNE_SPECIALISED : 0u),
+                                    k_local);
             k = c.k;
             R = c.R;
             LW = c.LW;
@@ -551,34 +612,7 @@ qsv_status qsv_plan_specialise(qsv_ctx *ctx, qsv_plan *plan, double *seconds_out
         if (seconds_out) *seconds_out = secs;
         if (!ctx) return;  // compile only
         hip_check(hipSetDevice(ctx->device), "hipSetDevice");
-        const bool rev = specialise_reverse(*plan);
-        std::vector<void *> fn(plan->parts.size(), nullptr), rfn(rev ? plan->parts.size() : 0, nullptr), mods;
-        std::string lerr;
-        for (const SpecChunk &c : chunks) {
-            hipModule_t m = nullptr;
-            if (hipModuleLoadData(&m, c.code.data()) != hipSuccess) {
-                lerr = "hipModuleLoadData failed";
-                break;
-            }
-            mods.push_back((void *)m);
-            for (int p = c.p0; p < c.p1 && lerr.empty(); ++p) {
-                for (int r = 0; r < (rev ? 2 : 1) && lerr.empty(); ++r) {
-                    hipFunction_t f = nullptr;
-                    const std::string name = (r ? "qsv_rspec_" : "qsv_spec_") + std::to_string(p);
-                    if (hipModuleGetFunction(&f, m, name.c_str()) != hipSuccess) lerr = "hipModuleGetFunction " + name;
-                    (r ? rfn : fn)[p] = (void *)f;
-                }
-            }
-            if (!lerr.empty()) break;
-        }
-        if (!lerr.empty()) {
-            (void)hipGetLastError();
-            for (void *m : mods) (void)hipModuleUnload((hipModule_t)m);
-            fail(QSV_E_DEVICE, lerr);
-        }
-        plan->spec_fn = std::move(fn);
-        plan->spec_rev_fn = std::move(rfn);
-        plan->spec_modules = std::move(mods);
+        load_spec(*plan, chunks, specialise_reverse(*plan));
         plan->specialised = true;
         plan->specialise_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         if (seconds_out) *seconds_out = plan->specialise_seconds;

@@ -122,12 +122,15 @@ struct SpecChunk {
     int p0 = 0, p1 = 0;
     std::vector<char> code;
 };
-std::string specialise_source(const Plan &plan, int p0, int p1);
+std::string specialise_source(const Plan &plan, int p0, int p1, bool with_reverse);
 // Whether the adjoint walk is specialised too: gradient plans whose psi and
 // lambda tiles fit 64 KiB of LDS together.
 bool specialise_reverse(const Plan &plan);
-// Compiles every partition of a single-circuit plan on up to max_threads host
-// threads; returns "" or the error (with the compiler log).
-std::string specialise_compile(const Plan &plan, std::vector<SpecChunk> &chunks, int max_threads);
+// Compiles the partitions of a single-circuit plan (every one, forward and,
+// where specialise_reverse holds, reverse kernels; or only the forward kernels
+// of the listed partitions, one program each) in up to max_procs compiler
+// processes; returns "" or the error (with the compiler log).
+std::string specialise_compile(const Plan &plan, std::vector<SpecChunk> &chunks, int max_procs,
+                               const std::vector<int> *subset = nullptr);
 
 }  // namespace qsv

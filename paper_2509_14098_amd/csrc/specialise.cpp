@@ -96,7 +96,7 @@ bool specialise_reverse(const Plan &plan)
 // Source of the program holding the specialised kernels qsv_spec_<p> (and,
 // for gradient plans, qsv_rspec_<p>) of partitions [p0, p1).  Every float is
 // written as an exact hexadecimal literal.
-std::string specialise_source(const Plan &plan, int p0, int p1)
+std::string specialise_source(const Plan &plan, int p0, int p1, bool with_reverse)
 {
     std::set<int32_t> dyn_mats;  // pool entries written from theta at apply time
     for (const ParamGate &g : plan.pgates) dyn_mats.insert(g.mat);
@@ -171,7 +171,7 @@ std::string specialise_source(const Plan &plan, int p0, int p1)
                       "{\n    qsv::spec_sweep<qsv_gen::P%d>(psi, ckpt, pool);\n}\n",
                       1 << plan.LW, p, p);
         s += b;
-        if (specialise_reverse(plan)) {
+        if (with_reverse) {
             std::snprintf(b, sizeof b,
                           "extern \"C\" __global__ __launch_bounds__(%d) void qsv_rspec_%d(const float2 *__restrict__ "
                           "psi, float2 *__restrict__ lam, const float *__restrict__ pool, double *__restrict__ gpart, "
@@ -234,11 +234,13 @@ struct TempDir {
 
 }  // namespace
 
-std::string specialise_compile(const Plan &plan, std::vector<SpecChunk> &chunks, int max_procs)
+std::string specialise_compile(const Plan &plan, std::vector<SpecChunk> &chunks, int max_procs,
+                               const std::vector<int> *subset)
 {
     const int np = (int)plan.parts.size();
     chunks.clear();
     if (np == 0) return "";
+    const bool with_reverse = !subset && specialise_reverse(plan);
     const std::string helper = helper_path();
     unsigned hw = std::thread::hardware_concurrency();
     const int nc = std::max(1, std::min({np, max_procs, hw ? (int)hw : 1}));
@@ -251,6 +253,15 @@ std::string specialise_compile(const Plan &plan, std::vector<SpecChunk> &chunks,
         cum[p + 1] = cum[p] + n;
     }
     int p = 0;
+    if (subset) {  // one program per listed partition
+        for (int q : *subset) {
+            SpecChunk ch;
+            ch.p0 = q;
+            ch.p1 = q + 1;
+            chunks.push_back(ch);
+        }
+        p = np;
+    }
     for (int c = 0; c < nc && p < np; ++c) {
         SpecChunk ch;
         ch.p0 = p;
@@ -277,7 +288,7 @@ std::string specialise_compile(const Plan &plan, std::vector<SpecChunk> &chunks,
     std::vector<std::string> src(n), out(n), log(n), cached(n);
     std::vector<size_t> todo;
     for (size_t c = 0; c < n; ++c) {
-        const std::string text = specialise_source(plan, chunks[c].p0, chunks[c].p1);
+        const std::string text = specialise_source(plan, chunks[c].p0, chunks[c].p1, with_reverse);
         if (!cache.empty()) {
             cached[c] = cache + "/" + cache_key(text) + ".co";
             const std::string code = read_file(cached[c]);

@@ -206,6 +206,28 @@ def test_specialised_qft_and_empty_circuit(sim):
     assert np.array_equal(b, rnd.cpu().numpy()) and np.array_equal(a, b)
 
 
+def test_autotuner_times_specialised_candidates(sim):
+    """QSV_PLAN_TUNE_SPECIALISED with k given: only tile shapes of at most 13
+    qubits at that k are timed, the plan takes the fastest, and its
+    specialised sweeps match the oracle."""
+    n = 18
+    gates = W.random_circuit(n, 200, seed=8101, n_params=3)
+    theta = np.random.default_rng(3).uniform(-3, 3, size=3)
+    plan = sim.partition(n, gates, 8, Q.PLAN_TUNE_SPECIALISED)
+    try:
+        cand = Q.qsv_last_autotune()
+        assert len(cand) >= 2 and all(c[0] == 8 and c[1] + c[2] <= 13 for c in cand)
+        best = min(cand, key=lambda c: c[3])
+        assert (plan.info["k_local"], plan.info["reg_qubits"], plan.info["log_threads"]) == tuple(best[:3])
+        sim.specialise(plan)
+        psi = sim.zero_state(n)
+        sim.apply(plan, psi, theta)
+        torch.cuda.synchronize()
+        assert maxabs(psi.cpu().numpy(), oracle.apply(n, gates, theta)) <= TOL
+    finally:
+        plan.close()
+
+
 def test_specialise_errors(sim):
     """Batched plans and tiles above 64 KiB of LDS are not specialised; a
     host-only plan has nothing to load on a device.  Each error leaves the
