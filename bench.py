@@ -47,34 +47,47 @@ import workloads as W
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
 FP32_VECTOR_PEAK = 157.3     # TFLOP/s (packed FP32 VALU; unpacked issue gives half)
 HERE = os.path.dirname(os.path.abspath(__file__))
-# HBM traffic of the sweep kernel measured with rocprofv3 counters (FETCH_SIZE,
-# WRITE_SIZE) on this workload, and the same counters for a plain 2 GiB copy
-TRAFFIC_FILE = os.path.join(HERE, "profiles", "sweep_spec_traffic_c2_28q.txt")
-# sources of the specialised sweep kernels (generator and device templates)
-SWEEP_SOURCES = ["specialise.cpp", "rtc_options.h", "spec.cuh", "tile.cuh", "gates.cuh", "plan.h"]
+# HBM traffic of the headline's sweep kernels measured with rocprofv3 counters
+# (FETCH_SIZE, WRITE_SIZE) on this workload, and the same counters for a plain
+# 2 GiB copy: one summary per kernel kind, each for the tile shape it was taken on
+TRAFFIC = {
+    "specialised": (os.path.join(HERE, "profiles", "sweep_spec_traffic_c2_28q.txt"),
+                    ["specialise.cpp", "rtc_options.h", "spec.cuh", "tile.cuh", "gates.cuh", "plan.h"]),
+    "table-driven": (os.path.join(HERE, "profiles", "sweep_kernel_traffic_c2_28q.txt"),
+                     ["sweep.hip", "tile.cuh", "gates.cuh", "plan.h"]),
+}
+# sources hashed by --copy-calibration's report (the specialised kernels')
+SWEEP_SOURCES = TRAFFIC["specialised"][1]
 
 
-def sweep_sources_sha256():
+def sources_sha256(files):
     import hashlib
     h = hashlib.sha256()
-    for f in SWEEP_SOURCES:
+    for f in files:
         with open(os.path.join(HERE, "paper_2509_14098_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per sweep launch from the committed counter summary, scaled by
-    the copy calibration; None if it is missing or was taken on other kernel
-    sources."""
+def sweep_sources_sha256():
+    return sources_sha256(SWEEP_SOURCES)
+
+
+def measured_traffic(kind="specialised", reg_qubits=4, log_threads=9):
+    """HBM bytes per sweep launch from the committed counter summary of this
+    kernel kind, scaled by the copy calibration; None if it is missing, was
+    taken on other kernel sources or on another tile shape."""
+    path, files = TRAFFIC[kind]
     try:
         kv = {}
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             for line in fh:
                 if ":" in line and not line.startswith("#"):
                     k, v = line.split(":", 1)
                     kv[k.strip()] = v.strip()
-        if kv.get("kernel_sources_sha256") != sweep_sources_sha256():
+        if kv.get("kernel_sources_sha256") != sources_sha256(files):
+            return None
+        if (int(kv["reg_qubits"]), int(kv["log_threads"])) != (reg_qubits, log_threads):
             return None
         copy_bytes = float(kv["copy_bytes"])
         fetch = float(kv["sweep_fetch_kib_per_dispatch"]) * copy_bytes / float(kv["copy_fetch_kib_per_dispatch"])
@@ -449,7 +462,8 @@ def main():
     ridge = FP32_VECTOR_PEAK * 1e12 / (HBM_PEAK_GBS * 1e9)
     achieved_gbs = sweep_bytes / (avg_launch_ms * 1e-3) / 1e9
     achieved_tf = sweep_flops / (avg_launch_ms * 1e-3) / 1e12
-    traffic = measured_traffic()
+    traffic = measured_traffic("specialised" if info["specialised"] else "table-driven", info["reg_qubits"],
+                               info["log_threads"])
     traffic = None if traffic is None else round(traffic)
     if intensity > ridge:
         roof = dict(bound="alu", achieved=round(achieved_tf, 3), peak=FP32_VECTOR_PEAK, unit="TFLOP/s",
