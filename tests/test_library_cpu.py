@@ -282,3 +282,17 @@ def test_specialise_code_object_cache(tmp_path, monkeypatch):
         assert e.value.code == -4 and "not in the cache" in str(e.value)
     finally:
         Q.qsv_plan_destroy(other)
+
+
+def test_tune_specialised_flag_on_host_only_plans():
+    """QSV_PLAN_TUNE_SPECIALISED is a valid flag; without a context nothing is
+    timed and the given k and the default tile shape are kept."""
+    plan = Q.qsv_partition(None, 16, W.brickwork_c3(n=16, layers=4), None, 8, Q.PLAN_TUNE_SPECIALISED, None)
+    try:
+        info = Q.qsv_plan_info(plan)
+        assert (info["k_local"], info["reg_qubits"], info["log_threads"]) == (8, 4, 8)
+    finally:
+        Q.qsv_plan_destroy(plan)
+    with pytest.raises(Q.QsvError) as e:
+        Q.qsv_partition(None, 16, W.ghz(16), None, 8, 8, None)  # no such flag
+    assert e.value.code == -1
