@@ -104,6 +104,41 @@ def test_specialised_c2_full(sim):
         torch.cuda.empty_cache()
 
 
+def test_specialised_maximum_size_34_qubits(sim):
+    """34 qubits (128 GiB, 2^21 workgroups per sweep) on specialised kernels
+    with 13-qubit tiles: a U3 layer against its product-state closed form on
+    sampled amplitudes, then a brickwork and its inverse back to it."""
+    n = 34
+    torch.cuda.empty_cache()
+
+    def spec_apply(gates, psi):
+        plan = sim.partition(n, gates, 10, 0, (4, 9))
+        try:
+            sim.specialise(plan)
+            sim.apply(plan, psi)
+            torch.cuda.synchronize()
+        finally:
+            plan.close()
+
+    layer, ang = W.u3_layer(n, seed=11)
+    psi = sim.zero_state(n)
+    spec_apply(layer, psi)
+    idx = np.random.default_rng(5).integers(0, 1 << n, size=1024)
+    got = psi[torch.as_tensor(idx, device=psi.device)].cpu().numpy()
+    ref = np.ones(len(idx), complex)
+    for q in range(n):
+        b = (idx >> q) & 1
+        ref *= np.where(b == 0, np.cos(ang[q, 0] / 2), np.exp(1j * ang[q, 1]) * np.sin(ang[q, 0] / 2))
+    assert np.max(np.abs(got - ref)) < 1e-7
+    body = W.brickwork_c3(n=n, layers=3, seed=12)
+    spec_apply(body, psi)
+    spec_apply(W.inverse_circuit(body), psi)
+    back = psi[torch.as_tensor(idx, device=psi.device)].cpu().numpy()
+    assert np.max(np.abs(back - ref)) < 1e-6
+    del psi
+    torch.cuda.empty_cache()
+
+
 def test_specialised_reads_theta_at_apply_time(sim):
     """Parameterised rotations keep their matrices in device memory: one
     specialised plan, two parameter vectors, both against the oracle."""
