@@ -241,6 +241,29 @@ def test_specialised_qft_and_empty_circuit(sim):
     assert np.array_equal(b, rnd.cpu().numpy()) and np.array_equal(a, b)
 
 
+def test_specialised_kernels_from_the_code_object_cache(sim, tmp_path, monkeypatch):
+    """A plan specialised with QSV_KERNEL_CACHE set leaves its code objects
+    there; the same plan built again loads them (QSV_KERNEL_CACHE_ONLY: no
+    compiler started) and reaches the oracle's state."""
+    n = 15
+    theta = np.random.default_rng(9).uniform(-3, 3, size=4)
+    gates = W.random_circuit(n, 200, seed=9109, n_params=4)
+    ref = oracle.apply(n, gates, theta)
+    monkeypatch.setenv("QSV_KERNEL_CACHE", str(tmp_path))
+    for cache_only in ("0", "1"):
+        monkeypatch.setenv("QSV_KERNEL_CACHE_ONLY", cache_only)
+        plan = sim.partition(n, gates, 9, 0, (4, 8))
+        try:
+            sim.specialise(plan)
+            psi = sim.zero_state(n)
+            sim.apply(plan, psi, theta)
+            torch.cuda.synchronize()
+            assert maxabs(psi.cpu().numpy(), ref) <= TOL
+        finally:
+            plan.close()
+        assert any(p.suffix == ".co" for p in tmp_path.iterdir())
+
+
 def test_autotuner_times_specialised_candidates(sim):
     """QSV_PLAN_TUNE_SPECIALISED with k given: only tile shapes of at most 13
     qubits at that k are timed, the plan takes the fastest, and its
