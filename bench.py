@@ -183,7 +183,9 @@ def bench_gradient(sim, args):
     gates, npar = W.ansatz(n, 10)
     theta = torch.as_tensor(W.ansatz_params(npar, seed=4), device=sim.device)
     H = W.zz_chain_plus_x(n, 0.5)
-    plan = sim.partition(n, gates, 10, Q.PLAN_GRAD)
+    # the tile shape is tuned at k = 10 by timing specialised candidates (unless not specialising)
+    plan = sim.partition(n, gates, 10, Q.PLAN_GRAD | (0 if args.no_specialise else Q.PLAN_TUNE_SPECIALISED))
+    tile = [plan.info["reg_qubits"], plan.info["log_threads"]]
     psi = sim.zero_state(n)
     ckpt = sim.checkpoints(plan)
     out = torch.empty(1, dtype=torch.float64, device=sim.device)
@@ -226,7 +228,7 @@ def bench_gradient(sim, args):
         f1, b1 = timed()
         res = dict(fwd_ms=f1, grad_ms=b1, ratio=b1 / f1, specialise_s=spec_s,
                    table_driven=dict(fwd_ms=round(f0, 4), grad_ms=round(b0, 4), ratio=round(b0 / f0, 4)))
-    res.update(energy=float(energy[0]), partitions=plan.info["n_partitions"])
+    res.update(energy=float(energy[0]), partitions=plan.info["n_partitions"], tile=tile)
     plan.close()
     return res
 

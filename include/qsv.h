@@ -156,7 +156,9 @@ qsv_status qsv_set_stream(qsv_ctx *ctx, void *hip_stream);
  * host-only plan usable with the introspection calls only).
  * k_local == 0 chooses k and the tile shape by timing candidates on the
  * device (autotuner, needs ctx; n_qubits above the default tile): k in
- * {8, 10, 12} below the tile size, five tile shapes; each candidate's time is
+ * {8, 10, 12} below the tile size, six tile shapes (reg_qubits x
+ * 2^log_threads: 5 x 256, 4 x 256, 4 x 512, 5 x 512, 4 x 1024, 3 x 256); each
+ * candidate's time is
  * an evenly spaced sample of at most 8 of its partition sweeps on a scratch
  * state (2^n x 8 bytes, freed afterwards) scaled to all partitions.  With
  * QSV_PLAN_TUNE_SPECIALISED the samples run as specialised kernels (also

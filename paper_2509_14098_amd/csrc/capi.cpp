@@ -423,7 +423,8 @@ static TuneChoice autotune(qsv_ctx *ctx, int n, const qsv_gate *gates, const std
     hip_check(hipMemsetAsync(psi, 0, (size_t)8 << n, ctx->stream), "hipMemsetAsync");
     hip_check(hipEventCreate(&e0), "hipEventCreate");
     hip_check(hipEventCreate(&e1), "hipEventCreate");
-    const int shapes[][2] = {{5, 8}, {4, 8}, {4, 9}, {5, 9}, {4, 10}};
+    // (3, 8): 11-qubit tiles, twice the workgroups of (4, 8) for states of ~20 qubits
+    const int shapes[][2] = {{5, 8}, {4, 8}, {4, 9}, {5, 9}, {4, 10}, {3, 8}};
     for (auto &sh : shapes) {
         const int R = sh[0], LW = sh[1], t = R + LW;
         if ((flags & QSV_PLAN_GRAD) && t > 13) continue;
