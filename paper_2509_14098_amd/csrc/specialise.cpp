@@ -21,6 +21,7 @@
 #include <unistd.h>
 
 #include <algorithm>
+#include <cerrno>
 #include <cstdio>
 #include <cstdlib>
 #include <deque>
@@ -330,7 +331,10 @@ std::string specialise_compile(const Plan &plan, std::vector<SpecChunk> &chunks,
         const size_t c = running.front();
         running.pop_front();
         int st = 0;
-        if (waitpid(pid[c], &st, 0) != pid[c]) {
+        pid_t w;
+        do w = waitpid(pid[c], &st, 0);  // a signal to the host process must not orphan the child
+        while (w < 0 && errno == EINTR);
+        if (w != pid[c]) {
             if (err.empty()) err = "waitpid failed";
             continue;
         }
