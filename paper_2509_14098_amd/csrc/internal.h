@@ -116,8 +116,9 @@ void build_plan(Plan &plan);
 // distributed partitions and gate map.
 void distribute(Plan &plan, const qsv_gate *gates, int64_t G, int n_global);
 
-// specialise.cpp: generated sweep kernels, one per partition, compiled with
-// hipRTC.  Partitions [p0, p1) share one program and code object.
+// specialise.cpp (program text) and rtc_driver.cpp (compilation): generated
+// sweep kernels, one per partition, compiled with hipRTC.  Partitions [p0, p1)
+// share one program and code object.
 struct SpecChunk {
     int p0 = 0, p1 = 0;
     std::vector<char> code;
