@@ -182,23 +182,25 @@ qsv_status qsv_plan_get_info(const qsv_plan *plan, qsv_plan_info *out);
  * computation of each partition is generated as code).  For every partition
  * a kernel is generated with the partition's tile qubits, register stages,
  * lowered ops and constant gate matrices as compile-time constants. The
- * kernels are compiled for gfx950 with hipRTC on up to 16 host threads and
- * loaded on the context's device.  Afterwards qsv_apply on this plan
+ * kernels are compiled for gfx950 with hipRTC in up to 16 helper processes
+ * at once and loaded on the context's device.  Afterwards qsv_apply on this plan
  * launches them instead of the table-driven sweep kernel.  The ops, their
  * order and their arithmetic are the same; only the compiler's choice of
  * fused multiply-adds may differ in the last bits.  Matrices of
  * parameterised rotations are still formed from theta at every qsv_apply.
- * The reverse walk of qsv_adjoint_grad keeps the table-driven kernels; the
- * forward it starts from (qsv_apply with checkpoints) uses the specialised
- * ones.
+ * Plans made with QSV_PLAN_GRAD whose tiles take at most 12 qubits (psi and
+ * lambda tiles together in 64 KiB of LDS) also get one specialised reverse
+ * kernel per partition, which qsv_adjoint_grad then launches; other plans
+ * keep the table-driven reverse walk.  The forward it starts from (qsv_apply
+ * with checkpoints) uses the specialised sweeps.
  * ctx NULL: generate and compile only, load nothing (a check that needs no
  * GPU); the plan is unchanged.  The compile runs in the helper executable
  * qsv_rtc next to this library.  Environment: QSV_KERNEL_CACHE=<dir> keeps
  * every compiled program in <dir>, keyed by a hash of the program text, the
  * device headers and the compile options, and reuses it; with
  * QSV_KERNEL_CACHE_ONLY=1 as well, a program missing from the cache is an
- * error (QSV_E_DEVICE) and no compiler process is started.  A plan that is already specialised is left
- * as it is.  seconds_out (may be NULL) receives the host time taken.
+ * error (QSV_E_DEVICE) and no compiler process is started.  A plan that is
+ * already specialised is left as it is.  seconds_out (may be NULL) receives the host time taken.
  * Errors: QSV_E_ARG (plan null), QSV_E_UNSUPPORTED (a plan of several
  * circuits, or tiles above 13 qubits, i.e. beyond 64 KiB of LDS), QSV_E_STATE
  * (plan without device tables on the context's device), QSV_E_DEVICE (the
