@@ -16,6 +16,13 @@ Brute-force versions of the paper's graph analysis, written for clarity:
   locality exemptions for diagonal gates and non-local controls).
 
 All quantities are integers or exact fractions.
+
+Pins: the worked example (GHZ-3: critical-path lengths, CC values and the
+partition tree of Fig. 5), CC against networkx's closeness centrality and
+against the paper's recursive form of RN and dist.  Which partition the greedy picks beyond that example
+is parity unpinned: the paper prints no other partition, so the tests check
+the invariants every valid partition meets (locality, dependency order, the
+sequential state) instead.
 """
 from __future__ import annotations
 
