@@ -259,6 +259,28 @@ def test_compiler_helper_reports_errors(tmp_path):
     assert r.returncode == 2
 
 
+def test_specialise_survives_signals_during_compile():
+    """A signal delivered to the host process while it waits for the compiler
+    helpers (here an interval timer every 5 ms) neither fails the compile nor
+    leaves a helper unreaped."""
+    import signal
+    hits = []
+    old = signal.signal(signal.SIGALRM, lambda *_: hits.append(1))
+    plan = Q.qsv_partition(None, 10, W.random_circuit(10, 150, seed=94, n_params=3), None, 6, 0, None)
+    try:
+        signal.setitimer(signal.ITIMER_REAL, 0.005, 0.005)
+        try:
+            assert Q.qsv_plan_specialise(None, plan) > 0
+        finally:
+            signal.setitimer(signal.ITIMER_REAL, 0)
+    finally:
+        signal.signal(signal.SIGALRM, old)
+        Q.qsv_plan_destroy(plan)
+    assert hits
+    with pytest.raises(ChildProcessError):
+        os.waitpid(-1, os.WNOHANG)  # no child left behind
+
+
 def test_specialise_code_object_cache(tmp_path, monkeypatch):
     """QSV_KERNEL_CACHE keeps one code object per generated program; with
     QSV_KERNEL_CACHE_ONLY a plan whose programs are all cached specialises
