@@ -143,13 +143,9 @@ __global__ __launch_bounds__(RED_THREADS) void apply_h_kernel(const DevGroup *__
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
-// Blocks for `work` amplitudes: 4 amplitudes per thread, at most cap blocks.
-// Below the cap a 2^20 state still gives every SIMD four waves (at 16 per
-// thread it had one and was bound by latency); from 2^24 amplitudes on, the
-// cap of 4096 blocks leaves 16 or more per thread, the unrolled path.
 static int blocks_for(uint64_t work, int cap)
 {
-    uint64_t b = (work + RED_THREADS * 4 - 1) / (RED_THREADS * 4);
+    uint64_t b = (work + RED_THREADS * 16 - 1) / (RED_THREADS * 16);
     return (int)std::max<uint64_t>(1, std::min<uint64_t>(b, (uint64_t)cap));
 }
 
