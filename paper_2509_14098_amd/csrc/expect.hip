@@ -70,8 +70,28 @@ __global__ __launch_bounds__(RED_THREADS) void expect_kernel(const DevGroup *__r
                 nf4 v[8];
 #pragma unroll
                 for (int u = 0; u < 8; ++u) v[u] = __builtin_nontemporal_load(n4 + i + u * stride);
+                // the 16 weights with the term loop outside: 16 independent float64
+                // sums per term (one chain per amplitude would leave the lanes
+                // waiting on each add); each weight still adds its terms in order
+                double w[16];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) acc += pair(i + u * stride, float4{v[u].x, v[u].y, v[u].z, v[u].w});
+                for (int u = 0; u < 16; ++u) w[u] = 0.0;
+                for (int t = G.term_begin; t < G.term_end; ++t) {
+                    const double c = terms[t].cre;
+                    const uint64_t zm = terms[t].z_mask;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const uint64_t x = 2 * (i + u * stride);
+                        w[2 * u] += c * parity_sign(x & zm);
+                        w[2 * u + 1] += c * parity_sign((x + 1) & zm);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const double p0 = (double)v[u].x * v[u].x + (double)v[u].y * v[u].y;
+                    const double p1 = (double)v[u].z * v[u].z + (double)v[u].w * v[u].w;
+                    acc += p0 * w[2 * u] + p1 * w[2 * u + 1];
+                }
             }
             for (; i < n2; i += stride) acc += pair(i, s4[i]);
         }
