@@ -99,10 +99,8 @@ __global__ __launch_bounds__(RED_THREADS) void expect_kernel(const DevGroup *__r
         const int lb = __builtin_ctzll(G.x_mask);
         const uint64_t low = 1ull << lb;
         const uint64_t half = 1ull << (n - 1);
-        for (uint64_t k = (uint64_t)blockIdx.x * RED_THREADS + threadIdx.x; k < half; k += stride) {
-            const uint64_t x = ((k >> lb) << (lb + 1)) | (k & (low - 1));
+        auto term_sum = [&](uint64_t x, float2 a, float2 c) __attribute__((always_inline)) {
             const uint64_t y = x ^ G.x_mask;
-            const float2 a = s[x], c = s[y];
             // z = conj(psi_y) psi_x
             const double zr = (double)c.x * a.x + (double)c.y * a.y;
             const double zi = (double)c.x * a.y - (double)c.y * a.x;
@@ -111,6 +109,24 @@ __global__ __launch_bounds__(RED_THREADS) void expect_kernel(const DevGroup *__r
                 const double sx = parity_sign(x & T.z_mask), sy = parity_sign(y & T.z_mask);
                 acc += sx * (T.cre * zr - T.cim * zi) + sy * (T.cre * zr + T.cim * zi);
             }
+        };
+        auto first = [&](uint64_t k) __attribute__((always_inline)) { return ((k >> lb) << (lb + 1)) | (k & (low - 1)); };
+        uint64_t k = (uint64_t)blockIdx.x * RED_THREADS + threadIdx.x;
+        // four pairs' loads in flight per thread, then their sums in the order of the plain loop
+        for (; k + 3 * stride < half; k += 4 * stride) {
+            float2 a[4], c[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint64_t x = first(k + u * stride);
+                a[u] = s[x];
+                c[u] = s[x ^ G.x_mask];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) term_sum(first(k + u * stride), a[u], c[u]);
+        }
+        for (; k < half; k += stride) {
+            const uint64_t x = first(k);
+            term_sum(x, s[x], s[x ^ G.x_mask]);
         }
     }
     const double tot = block_sum(acc, sh);
