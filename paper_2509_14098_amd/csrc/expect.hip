@@ -159,10 +159,8 @@ __global__ __launch_bounds__(RED_THREADS) void apply_h_kernel(const DevGroup *__
     for (uint64_t x = (uint64_t)blockIdx.x * RED_THREADS + threadIdx.x; x < dim; x += stride) {
         const float2 px = psi[x];
         double lr = 0.0, li = 0.0;
-        for (int g = 0; g < n_groups; ++g) {
-            const DevGroup G = groups[g];
+        auto add_group = [&](const DevGroup &G, float2 py) __attribute__((always_inline)) {
             const uint64_t y = x ^ G.x_mask;
-            const float2 py = G.x_mask ? psi[y] : px;
             double wr = 0.0, wi = 0.0;
             for (int t = G.term_begin; t < G.term_end; ++t) {
                 const double sg = parity_sign(y & terms[t].z_mask);
@@ -171,6 +169,22 @@ __global__ __launch_bounds__(RED_THREADS) void apply_h_kernel(const DevGroup *__
             }
             lr += wr * py.x - wi * py.y;
             li += wr * py.y + wi * py.x;
+        };
+        int g = 0;
+        // four groups' gathers in flight, then their sums in group order
+        for (; g + 3 < n_groups; g += 4) {
+            float2 py[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint64_t xm = groups[g + u].x_mask;
+                py[u] = xm ? psi[x ^ xm] : px;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) add_group(groups[g + u], py[u]);
+        }
+        for (; g < n_groups; ++g) {
+            const uint64_t xm = groups[g].x_mask;
+            add_group(groups[g], xm ? psi[x ^ xm] : px);
         }
         lam[x] = float2{(float)lr, (float)li};
         acc += (double)px.x * lr + (double)px.y * li;
