@@ -19,10 +19,11 @@ All quantities are integers or exact fractions.
 
 Pins: the worked example (GHZ-3: critical-path lengths, CC values and the
 partition tree of Fig. 5), CC against networkx's closeness centrality and
-against the paper's recursive form of RN and dist.  Which partition the greedy picks beyond that example
-is parity unpinned: the paper prints no other partition, so the tests check
-the invariants every valid partition meets (locality, dependency order, the
-sequential state) instead.
+against the paper's recursive form of RN and dist, and four small circuits
+worked out by hand in which competing frontier gates are ordered by CC, then
+by critical-path length, then by index (each rule, reversed, changes one of
+their partitions).  On large circuits the tests check the invariants every
+valid partition meets (locality, dependency order, the sequential state).
 """
 from __future__ import annotations
 

@@ -318,3 +318,16 @@ def test_tune_specialised_flag_on_host_only_plans():
     with pytest.raises(Q.QsvError) as e:
         Q.qsv_partition(None, 16, W.ghz(16), None, 8, 8, None)  # no such flag
     assert e.value.code == -1
+
+
+def test_planner_ranking_on_hand_derived_cases():
+    """The native planner reaches the hand-derived partitions in which
+    closeness centrality, then critical-path length, then gate index decide
+    between competing frontier gates (the same cases pin the oracle)."""
+    from test_oracle_centrality import RANKING_CASES
+    for name, n, k, specs, _, _, parts_ref in RANKING_CASES:
+        plan = Q.qsv_partition(None, n, W.make_gates(specs), None, k, 0, (1, 6))
+        try:
+            assert [(list(S), list(g)) for S, g in _plan_parts(plan)] == parts_ref, name
+        finally:
+            Q.qsv_plan_destroy(plan)

@@ -130,3 +130,74 @@ def test_partition_of_benchmark_circuit_c1():
     parts = C.greedy_partition(12, g, 8)
     C.check_partition(12, g, 8, parts)
     assert len(parts) >= 2
+
+
+# ---------------------------------------------------------------------------
+# Hand-derived pins of the greedy's ranking (Section 4.2, Fig. 5 step 3: take
+# the frontier gates of highest closeness centrality; ties by lower
+# critical-path length, then lower gate index).  In each circuit two or more
+# ready gates compete for the last free local qubit, so the rule fixes which
+# gates share a partition.  Nodes: psi = 0, gate i = node i + 1; N = G + 1;
+# CC = |RN|^2 / (N dist) with dist = sum over RN of (l_w - l_v).  The values
+# below were worked out by hand (the derivations are listed with the
+# partitioner's readings); the tests check the oracle against them.
+
+def _mk(specs):
+    return W.make_gates(specs)
+
+
+# (name, n, k, gate specs, l per node, CC per node, expected partitions)
+RANKING_CASES = [
+    # CC decides: g0 = H0 (RN {g2, g3}, dist 1 + 2, CC 4/15) beats g1 = H2
+    # (a sink, CC 0); the SWAP(0,1) then fills the local set {0, 1}, and H2
+    # is left for a second partition.  Ascending CC would start with H2.
+    ("cc", 3, 2, [("H", (0,)), ("H", (2,)), ("SWAP", (0, 1)), ("H", (1,))],
+     [0, 1, 1, 2, 3],
+     [Fraction(16, 35), Fraction(4, 15), Fraction(0), Fraction(1, 5), Fraction(0)],
+     [([0, 1], [0, 2, 3]), ([0, 2], [1])]),
+    # Critical-path length decides: after H0, the sinks SWAP(0,1) (l 2) and
+    # H2 (l 1) tie at CC 0; the lower l takes qubit 2, so the SWAP waits.
+    # Preferring the lower index (or the higher l) would take the SWAP.
+    ("l", 3, 2, [("H", (0,)), ("SWAP", (0, 1)), ("H", (2,))],
+     [0, 1, 2, 1],
+     [Fraction(9, 16), Fraction(1, 4), Fraction(0), Fraction(0)],
+     [([0, 2], [0, 2]), ([0, 1], [1])]),
+    # Gate index decides: after H0 (CC 1/5), the sinks H1 and H2 tie at CC 0
+    # and l 1; the lower index takes qubit 1, then the second H0 (l 2) fits.
+    ("index", 3, 2, [("H", (0,)), ("H", (1,)), ("H", (2,)), ("H", (0,))],
+     [0, 1, 1, 1, 2],
+     [Fraction(16, 25), Fraction(1, 5), Fraction(0), Fraction(0), Fraction(0)],
+     [([0, 1], [0, 1, 3]), ([0, 2], [2])]),
+    # Centrality, not reach: a chain of five H on qubit 0 gives its head four
+    # downstream gates at distances 1..4 (CC 16/90 = 8/45), SWAP(1,2) has two
+    # at distance 1 (CC 4/18 = 2/9 > 8/45).  The SWAP opens the first
+    # partition with its two followers; ranking by reach or ascending CC
+    # would open with the chain instead.
+    ("reach", 3, 2, [("H", (0,))] * 5 + [("SWAP", (1, 2)), ("H", (1,)), ("H", (2,))],
+     [0, 1, 2, 3, 4, 5, 1, 2, 2],
+     [Fraction(16, 45), Fraction(8, 45), Fraction(1, 6), Fraction(4, 27), Fraction(1, 9), Fraction(0),
+      Fraction(2, 9), Fraction(0), Fraction(0)],
+     [([1, 2], [5, 6, 7]), ([0, 1], [0, 1, 2, 3, 4])]),
+]
+
+
+@pytest.mark.parametrize("case", RANKING_CASES, ids=[c[0] for c in RANKING_CASES])
+def test_ranking_pins_hand_derived(case):
+    _, n, k, specs, l_ref, cc_ref, parts_ref = case
+    gates = _mk(specs)
+    assert C.critical_path_lengths(n, gates) == l_ref
+    assert [c for _, _, c in C.closeness(n, gates)] == cc_ref
+    parts = C.greedy_partition(n, gates, k)
+    assert parts == parts_ref
+    C.check_partition(n, gates, k, parts)
+    # every candidate ordering still reaches the sequential state
+    order = [g for _, p in parts for g in p]
+    assert np.max(np.abs(oracle.apply(n, gates) - oracle.apply(n, gates[order]))) < 1e-13
+
+
+def test_controls_join_the_local_set_only_when_there_is_room():
+    """Section 4.2's second exemption: after H1 and H2 fill the local set
+    {1, 2}, CX(0 -> 1) still joins the partition (only its target must be
+    local) and its control stays global."""
+    gates = _mk([("H", (1,)), ("CX", (0, 1)), ("H", (2,))])
+    assert C.greedy_partition(3, gates, 2) == [([1, 2], [0, 2, 1])]
