@@ -101,6 +101,42 @@ def sync():
     torch.cuda.synchronize()
 
 
+# The plans the benchmark times.  The parity tests build their plans through
+# these same functions, so every benchmarked plan is also a tested plan.
+
+def headline_plan(sim, k=10, tile=None, tune_specialised=True):
+    """The 28-qubit brickwork at k local qubits; without a tile shape the
+    autotuner picks one by timing specialised candidates at that k."""
+    flags = Q.PLAN_TUNE_SPECIALISED if (tune_specialised and tile is None) else 0
+    return sim.partition(28, W.brickwork_c2(), k, flags, tile)
+
+
+def gradient_plan(sim, tune_specialised=True, tile=None):
+    """The 20-qubit RY.RZ + CX-ladder ansatz (10 layers, 400 parameters) at
+    k = 10 with checkpoints; without a tile shape it is tuned for specialised
+    kernels."""
+    gates, npar = W.ansatz(20, 10)
+    flags = Q.PLAN_GRAD | (Q.PLAN_TUNE_SPECIALISED if (tune_specialised and tile is None) else 0)
+    return sim.partition(20, gates, 10, flags, tile), gates, W.ansatz_params(npar, seed=4), W.zz_chain_plus_x(20, 0.5)
+
+
+def c3_plan(sim, n=32, tune_specialised=True):
+    """The U3 + random-matching CX circuit (60 layers) with k and the tile
+    shape chosen by the autotuner."""
+    gates = W.brickwork_c3(n=n)
+    return sim.partition(n, gates, 0, Q.PLAN_TUNE_SPECIALISED if tune_specialised else 0), gates
+
+
+def batched_plan(sim, B=2048, n=14):
+    """B instances of the n-qubit ansatz with depths U{4..16} (seed 5) in
+    one gradient plan; returns the plan, the circuits and their parameters."""
+    circs, _, thetas = W.ansatz_batch(B, n, 4, 16, seed=5)
+    gates = np.concatenate(circs)
+    off = np.concatenate([[0], np.cumsum([len(c) for c in circs])])
+    plan = sim.partition(n, gates, 0, Q.PLAN_GRAD, None, circ_offsets=off)
+    return plan, circs, thetas, W.zz_chain_plus_x(n, 0.5)
+
+
 def maybe_specialise(sim, plan, args):
     """Specialise the plan unless --no-specialise; the host seconds, or None
     where it stays table-driven (not asked, or a tile above 13 qubits)."""
@@ -143,9 +179,8 @@ def bench_headline(sim, args):
     gates = W.brickwork_c2()
     tile = tuple(args.tile) if args.tile else None
     # the tile shape is tuned at k = 10 by timing specialised candidates (unless given)
-    flags = 0 if (args.no_specialise or tile) else Q.PLAN_TUNE_SPECIALISED
-    plan = sim.partition(n, gates, k, flags, tile)
-    tuned = [list(c) for c in Q.qsv_last_autotune()] if flags else None
+    plan = headline_plan(sim, k, tile, not args.no_specialise)
+    tuned = [list(c) for c in Q.qsv_last_autotune()] if not (args.no_specialise or tile) else None
     psi = sim.zero_state(n)
     Hz0 = W.z_on(0)
     out = torch.empty(1, dtype=torch.float64, device=sim.device)
@@ -180,11 +215,10 @@ def bench_headline(sim, args):
 
 def bench_gradient(sim, args):
     n = 20
-    gates, npar = W.ansatz(n, 10)
-    theta = torch.as_tensor(W.ansatz_params(npar, seed=4), device=sim.device)
-    H = W.zz_chain_plus_x(n, 0.5)
     # the tile shape is tuned at k = 10 by timing specialised candidates (unless not specialising)
-    plan = sim.partition(n, gates, 10, Q.PLAN_GRAD | (0 if args.no_specialise else Q.PLAN_TUNE_SPECIALISED))
+    plan, gates, theta_np, H = gradient_plan(sim, not args.no_specialise)
+    npar = len(theta_np)
+    theta = torch.as_tensor(theta_np, device=sim.device)
     tile = [plan.info["reg_qubits"], plan.info["log_threads"]]
     psi = sim.zero_state(n)
     ckpt = sim.checkpoints(plan)
@@ -237,14 +271,11 @@ def bench_batched(sim, args):
     """2048 instances of the 14-qubit ansatz (depths U{4..16}), energy and
     gradient of every instance in one persistent launch."""
     n, B = 14, 2048
-    circs, depths, thetas = W.ansatz_batch(B, n, 4, 16, seed=5)
-    gates = np.concatenate(circs)
-    off = np.concatenate([[0], np.cumsum([len(c) for c in circs])])
-    theta = torch.as_tensor(np.concatenate(thetas), device=sim.device)
-    H = W.zz_chain_plus_x(n, 0.5)
     t0 = time.perf_counter()
-    plan = sim.partition(n, gates, 0, Q.PLAN_GRAD, None, circ_offsets=off)
+    plan, circs, thetas, H = batched_plan(sim, B, n)
     plan_s = time.perf_counter() - t0
+    gates = np.concatenate(circs)
+    theta = torch.as_tensor(np.concatenate(thetas), device=sim.device)
     energy = torch.empty(B, dtype=torch.float64, device=sim.device)
     grad = torch.empty(len(theta), dtype=torch.float64, device=sim.device)
     psi = torch.empty((B, 1 << n), dtype=torch.complex64, device=sim.device)
@@ -350,9 +381,8 @@ def bench_c3(sim, args):
     """32-qubit local share (60 layers of U3 + random CX matchings): the
     autotuner chooses k and the tile shape, then one apply and <sum Z_i Z_i+1>."""
     n = 32
-    gates = W.brickwork_c3()
     t0 = time.perf_counter()
-    plan = sim.partition(n, gates, 0, 0 if args.no_specialise else Q.PLAN_TUNE_SPECIALISED)
+    plan, gates = c3_plan(sim, n, not args.no_specialise)
     plan_s = time.perf_counter() - t0
     spec_s = maybe_specialise(sim, plan, args)
     info = plan.info

@@ -141,7 +141,10 @@ const char *qsv_last_error(void);
  */
 qsv_status qsv_create(int32_t device, void *hip_stream, qsv_ctx **out);
 qsv_status qsv_destroy(qsv_ctx *ctx);
-/* Change the stream later calls are queued on. */
+/* Change the stream later calls are queued on.  The context's scratch
+ * buffers are shared by all its calls, so the new stream is made to wait for
+ * the work already queued on the old one (an event, no host wait); calls on
+ * one context are therefore ordered even across streams. */
 qsv_status qsv_set_stream(qsv_ctx *ctx, void *hip_stream);
 
 /*

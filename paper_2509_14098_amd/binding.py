@@ -11,7 +11,7 @@ import ctypes
 import os
 
 import numpy as np
-import torch  # noqa: F401  (must be loaded before libqsv.so: one HIP runtime per process)
+import torch  # (must be loaded before libqsv.so: one HIP runtime per process)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(HERE, "libqsv.so")
@@ -92,15 +92,26 @@ def _check(rc):
         raise QsvError(rc, load_library().qsv_last_error().decode())
 
 
-def _dptr(t):
-    """Device address of a torch tensor (None -> NULL)."""
+def _dptr(t, dtype=None, min_numel=0, name="tensor"):
+    """Device address of a torch tensor (None -> NULL), after checking that it
+    is a contiguous GPU tensor of the element type the C interface reads and
+    holds at least min_numel elements."""
     if t is None:
         return None
     if not t.is_cuda:
-        raise QsvError(-1, "expected a GPU tensor")
+        raise QsvError(-1, f"{name}: expected a GPU tensor")
     if not t.is_contiguous():
-        raise QsvError(-1, "expected a contiguous tensor")
+        raise QsvError(-1, f"{name}: expected a contiguous tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise QsvError(-1, f"{name}: expected {dtype}, got {t.dtype}")
+    if t.numel() < min_numel:
+        raise QsvError(-1, f"{name}: {t.numel()} elements, the call needs {min_numel}")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _state_len(plan):
+    i = qsv_plan_info(plan)
+    return i, i["n_circuits"] << i["n_qubits"]
 
 
 def _stream_ptr(stream):
@@ -212,7 +223,10 @@ def qsv_plan_partition(plan, circuit: int, level: int, p: int):
 
 
 def qsv_apply(ctx, plan, theta, psi, ckpt=None):
-    _check(load_library().qsv_apply(ctx, plan, _dptr(theta), _dptr(psi), _dptr(ckpt)))
+    i, dim = _state_len(plan)
+    _check(load_library().qsv_apply(
+        ctx, plan, _dptr(theta, torch.float64, i["n_params"], "theta"), _dptr(psi, torch.complex64, dim, "psi"),
+        _dptr(ckpt, torch.complex64, i["ckpt_bytes"] // 8, "ckpt")))
 
 
 def _pauli(H):
@@ -224,10 +238,15 @@ def _pauli(H):
 
 def qsv_expect(ctx, H, n_qubits: int, batch: int, psi, out):
     h, hp = _pauli(H)
-    _check(load_library().qsv_expect(ctx, hp, len(h), n_qubits, batch, _dptr(psi), _dptr(out)))
+    dim = batch << n_qubits if 0 < n_qubits < 63 and batch > 0 else 0
+    _check(load_library().qsv_expect(ctx, hp, len(h), n_qubits, batch, _dptr(psi, torch.complex64, dim, "psi"),
+                                     _dptr(out, torch.float64, max(batch, 0), "out")))
 
 
 def qsv_adjoint_grad(ctx, plan, H, theta, psi_final, ckpt, energy, grad):
     h, hp = _pauli(H)
-    _check(load_library().qsv_adjoint_grad(ctx, plan, hp, len(h), _dptr(theta), _dptr(psi_final), _dptr(ckpt),
-                                           _dptr(energy), _dptr(grad)))
+    i, dim = _state_len(plan)
+    _check(load_library().qsv_adjoint_grad(
+        ctx, plan, hp, len(h), _dptr(theta, torch.float64, i["n_params"], "theta"),
+        _dptr(psi_final, torch.complex64, dim, "psi_final"), _dptr(ckpt, torch.complex64, i["ckpt_bytes"] // 8, "ckpt"),
+        _dptr(energy, torch.float64, i["n_circuits"], "energy"), _dptr(grad, torch.float64, i["n_params"], "grad")))

@@ -108,6 +108,7 @@ struct qsv_ctx {
     void *pinned = nullptr;
     size_t pinned_bytes = 0;
     hipEvent_t pinned_ready = nullptr;
+    hipEvent_t handoff = nullptr;  // orders work across a change of stream
     int *queue = nullptr;
     int n_cu = 0;
 
@@ -229,6 +230,7 @@ qsv_status qsv_destroy(qsv_ctx *ctx)
         dev_free(ctx->queue);
         if (ctx->pinned) (void)hipHostFree(ctx->pinned);
         if (ctx->pinned_ready) (void)hipEventDestroy(ctx->pinned_ready);
+        if (ctx->handoff) (void)hipEventDestroy(ctx->handoff);
         for (auto e : ctx->events) (void)hipEventDestroy(e);
         delete ctx;
     });
@@ -238,7 +240,15 @@ qsv_status qsv_set_stream(qsv_ctx *ctx, void *hip_stream)
 {
     return guarded([&] {
         if (!ctx) fail(QSV_E_ARG, "ctx is null");
-        ctx->stream = (hipStream_t)hip_stream;
+        hipStream_t next = (hipStream_t)hip_stream;
+        if (next == ctx->stream) return;
+        // the context's scratch buffers are shared by every call: work queued on the new
+        // stream waits for what the old stream still has in flight
+        hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+        if (!ctx->handoff) hip_check(hipEventCreateWithFlags(&ctx->handoff, hipEventDisableTiming), "hipEventCreate");
+        hip_check(hipEventRecord(ctx->handoff, ctx->stream), "hipEventRecord");
+        hip_check(hipStreamWaitEvent(next, ctx->handoff, 0), "hipStreamWaitEvent");
+        ctx->stream = next;
     });
 }
 

@@ -33,14 +33,14 @@ __device__ __forceinline__ double block_sum(double v, double *sh)
 
 __device__ __forceinline__ double parity_sign(uint64_t v) { return (__popcll(v) & 1) ? -1.0 : 1.0; }
 
-// partials[(b * n_groups + g) * gridDim.x + block]
-__global__ __launch_bounds__(RED_THREADS) void expect_kernel(const DevGroup *__restrict__ groups,
-                                                              const DevTerm *__restrict__ terms, int n,
+// partials[(b * n_groups + g) * gridDim.x + block] for the groups g = g0 + blockIdx.y
+__global__ __launch_bounds__(RED_THREADS) void expect_kernel(const DevGroup *__restrict__ groups, int g0,
+                                                              int n_groups, const DevTerm *__restrict__ terms, int n,
                                                               const float2 *__restrict__ psi,
                                                               double *__restrict__ partials)
 {
     __shared__ double sh[RED_THREADS];
-    const int gi = blockIdx.y;
+    const int gi = g0 + (int)blockIdx.y;
     const int64_t b = blockIdx.z;
     const DevGroup G = groups[gi];
     const float2 *__restrict__ s = psi + ((uint64_t)b << n);
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(RED_THREADS) void expect_kernel(const DevGroup *__r
         }
     }
     const double tot = block_sum(acc, sh);
-    if (threadIdx.x == 0) partials[((uint64_t)b * gridDim.y + gi) * gridDim.x + blockIdx.x] = tot;
+    if (threadIdx.x == 0) partials[((uint64_t)b * n_groups + gi) * gridDim.x + blockIdx.x] = tot;
 }
 
 // out[b] = sum of per_batch partials, fixed order
@@ -209,13 +209,16 @@ hipError_t launch_expect(const DevGroup *groups, int n_groups, const DevTerm *te
         return hipGetLastError();
     }
     const int nb = blocks_for(1ull << n, n_blocks);
-    const int64_t zmax = 65535;  // grid z limit: batches beyond it go in chunks
-    for (int64_t b0 = 0; b0 < batch; b0 += zmax) {
-        const int64_t nz = std::min<int64_t>(zmax, batch - b0);
-        hipLaunchKernelGGL(expect_kernel, dim3(nb, n_groups, (uint32_t)nz), dim3(RED_THREADS), 0, s, groups, terms, n,
-                           psi + ((uint64_t)b0 << n), partials + (uint64_t)b0 * n_groups * nb);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+    const int64_t lim = 65535;  // grid y and z limits: groups and batches beyond them go in chunks
+    for (int64_t b0 = 0; b0 < batch; b0 += lim) {
+        const int64_t nz = std::min<int64_t>(lim, batch - b0);
+        for (int g0 = 0; g0 < n_groups; g0 += (int)lim) {
+            const int ny = (int)std::min<int64_t>(lim, n_groups - g0);
+            hipLaunchKernelGGL(expect_kernel, dim3(nb, ny, (uint32_t)nz), dim3(RED_THREADS), 0, s, groups, g0, n_groups,
+                               terms, n, psi + ((uint64_t)b0 << n), partials + (uint64_t)b0 * n_groups * nb);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
     }
     hipLaunchKernelGGL(final_sum_kernel, dim3((uint32_t)batch), dim3(RED_THREADS), 0, s, partials, nb * n_groups, out);
     return hipGetLastError();

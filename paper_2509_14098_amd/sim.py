@@ -68,9 +68,10 @@ class Simulator:
         return psi
 
     def theta(self, values):
+        """Parameters as the contiguous float64 device tensor the library reads."""
         if values is None:
             return None
-        return torch.as_tensor(values, dtype=torch.float64, device=self.device).contiguous()
+        return torch.as_tensor(values).to(device=self.device, dtype=torch.float64).contiguous()
 
     def checkpoints(self, plan: Plan):
         nbytes = plan.info["ckpt_bytes"]
@@ -78,7 +79,7 @@ class Simulator:
 
     def apply(self, plan: Plan, psi, theta=None, ckpt=None):
         self._sync_stream()
-        B.qsv_apply(self.ctx, plan.handle, self.theta(theta) if not torch.is_tensor(theta) else theta, psi, ckpt)
+        B.qsv_apply(self.ctx, plan.handle, self.theta(theta), psi, ckpt)
         return psi
 
     def expect(self, H, psi, n_qubits, batch=1):
@@ -91,8 +92,7 @@ class Simulator:
         self._sync_stream()
         energy = torch.empty(plan.info["n_circuits"], dtype=torch.float64, device=self.device)
         grad = torch.empty(max(plan.n_params, 1), dtype=torch.float64, device=self.device)
-        th = theta if torch.is_tensor(theta) else self.theta(theta)
-        B.qsv_adjoint_grad(self.ctx, plan.handle, H, th, psi_final, ckpt, energy, grad)
+        B.qsv_adjoint_grad(self.ctx, plan.handle, H, self.theta(theta), psi_final, ckpt, energy, grad)
         return energy, grad[:plan.n_params]
 
     def close(self):
@@ -114,11 +114,12 @@ class Energy(torch.autograd.Function):
         sim.apply(plan, psi, th, ckpt)
         e = sim.expect(H, psi, plan.n)[0]
         ctx.save_for_backward(th)
-        ctx.sim, ctx.plan, ctx.H, ctx.psi, ctx.ckpt, ctx.dtype = sim, plan, H, psi, ckpt, theta.dtype
-        return e
+        ctx.sim, ctx.plan, ctx.H, ctx.psi, ctx.ckpt = sim, plan, H, psi, ckpt
+        ctx.dtype, ctx.device = theta.dtype, theta.device
+        return e.to(theta.device)
 
     @staticmethod
     def backward(ctx, g_e):
         (th,) = ctx.saved_tensors
         _, grad = ctx.sim.adjoint_grad(ctx.plan, ctx.H, th, ctx.psi, ctx.ckpt)
-        return (grad * g_e).to(ctx.dtype), None, None, None
+        return (grad * g_e.to(grad.device)).to(device=ctx.device, dtype=ctx.dtype), None, None, None

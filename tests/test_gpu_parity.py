@@ -252,6 +252,37 @@ def test_expect_vs_oracle(sim, n, seed):
     assert abs(got - ref) < 1e-9 * max(1, abs(ref))
 
 
+def _walsh_hadamard(v):
+    """Unnormalised fast Walsh-Hadamard transform along the last axis."""
+    v = np.array(v, dtype=np.complex128)
+    h = 1
+    while h < v.shape[-1]:
+        v = v.reshape(-1, 2, h)
+        v = np.stack([v[:, 0] + v[:, 1], v[:, 0] - v[:, 1]], axis=1).reshape(-1)
+        h *= 2
+    return v
+
+
+def test_expect_more_groups_than_a_grid_row(sim):
+    """70 000 X strings with distinct masks (more groups than one launch's
+    65 535 grid rows) on 17 qubits.  Reference: <psi|X^m|psi> =
+    sum_x conj(psi_{x^m}) psi_x is the XOR autocorrelation of psi, which the
+    Walsh-Hadamard transform turns into a pointwise product."""
+    n = 17
+    rng = np.random.default_rng(31)
+    psi = (rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)) / np.sqrt(2 << n)
+    psi = psi.astype(np.complex64)
+    masks = rng.choice(np.arange(1, 1 << n), size=70000, replace=False).astype(np.uint64)
+    coeff = rng.normal(size=masks.size)
+    H = np.zeros(masks.size, dtype=W.PAULI_DTYPE)
+    H["coeff"], H["x_mask"] = coeff, masks
+    p = psi.astype(np.complex128)
+    corr = _walsh_hadamard(_walsh_hadamard(p) * _walsh_hadamard(np.conj(p))) / (1 << n)  # sum_x psi_x conj(psi_{x^m})
+    ref = float(np.sum(coeff * corr[masks.astype(np.int64)].real))
+    got = float(sim.expect(H, torch.as_tensor(psi, device="cuda"), n)[0])
+    assert abs(got - ref) < 1e-9 * max(1.0, float(np.sum(np.abs(coeff))))
+
+
 def test_expect_batched(sim):
     n, B = 6, 5
     rng = np.random.default_rng(8)
@@ -264,13 +295,27 @@ def test_expect_batched(sim):
 
 # ---------------------------------------------------------------- adjoint gradient
 
+def random_pauli_sum(n, rng, n_terms=9):
+    """Real-weighted Pauli strings over X, Y and Z (Y terms give the
+    imaginary weights i^{#Y} of lambda = H psi), plus a constant."""
+    terms = [(float(rng.normal()), {int(q): "XYZ"[int(rng.integers(3))]
+                                    for q in rng.choice(n, size=int(rng.integers(1, min(n, 4) + 1)), replace=False)})
+             for _ in range(n_terms)]
+    terms.append((float(rng.normal()), {int(rng.integers(n)): "Y"}))  # at least one Y
+    return W.pauli_sum(terms + [(0.25, {})])
+
+
+@pytest.mark.parametrize("hkind", ["zz+x", "xyz"])
 @pytest.mark.parametrize("n,ng,seed", [(2, 30, 1), (5, 80, 2), (9, 150, 3), (14, 200, 4), (16, 200, 5)])
-def test_adjoint_vs_oracle(sim, n, ng, seed):
+def test_adjoint_vs_oracle(sim, n, ng, seed, hkind):
     npar = 6
     rng = np.random.default_rng(seed)
     theta = rng.uniform(-3, 3, size=npar)
     gates = W.random_circuit(n, ng, seed=3000 + seed, n_params=npar)
-    H = W.zz_chain_plus_x(n, 0.5) if n > 1 else W.z_on(0)
+    if hkind == "xyz":
+        H = random_pauli_sum(n, rng)
+    else:
+        H = W.zz_chain_plus_x(n, 0.5) if n > 1 else W.z_on(0)
     e_ref, g_ref = oracle.adjoint(n, gates, theta, H)
     plan = sim.partition(n, gates, min(n, 9), Q.PLAN_GRAD, (4, 8))
     try:
@@ -324,11 +369,13 @@ def _batch(circs, thetas):
     return gates, off, theta
 
 
+@pytest.mark.parametrize("hkind", ["zz+x", "xyz"])
 @pytest.mark.parametrize("n,B,seed", [(4, 3, 1), (9, 7, 2), (14, 64, 5)])
-def test_batched_energy_gradient_and_states(sim, n, B, seed):
+def test_batched_energy_gradient_and_states(sim, n, B, seed, hkind):
     """Uneven-depth ansatz instances in one persistent launch: every
     instance's final state, energy and gradient against the oracle run on
-    that instance alone (depths span the extremes 4 and 16)."""
+    that instance alone (depths span the extremes 4 and 16), for the ZZ + X
+    observable and for a random Pauli sum with Y terms."""
     circs, depths, thetas = W.ansatz_batch(B, n, 4, 16, seed=seed)
     depths[0], depths[-1] = 4, 16
     circs[0], _ = W.ansatz(n, 4)
@@ -336,7 +383,7 @@ def test_batched_energy_gradient_and_states(sim, n, B, seed):
     thetas[0] = W.ansatz_params(2 * n * 4, seed=seed + 100)
     thetas[-1] = W.ansatz_params(2 * n * 16, seed=seed + 101)
     gates, off, theta = _batch(circs, thetas)
-    H = W.zz_chain_plus_x(n, 0.5)
+    H = W.zz_chain_plus_x(n, 0.5) if hkind == "zz+x" else random_pauli_sum(n, np.random.default_rng(seed + 40))
     plan = sim.partition(n, gates, 0, Q.PLAN_GRAD, None, circ_offsets=off)
     try:
         assert plan.n_params == len(theta)
