@@ -281,6 +281,31 @@ qsv_status qsv_expect(qsv_ctx *ctx, const qsv_pauli_term *H, int32_t n_terms, in
                       const void *psi_dev, double *out_dev);
 
 /*
+ * qsv_expect for callers that cannot allocate memory: code recorded under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, same kernels and the same results (bit for bit) as
+ * qsv_expect, but the call allocates nothing, on the device or pinned: its
+ * scratch (the grouped Pauli terms, then the per-block float64 partial sums)
+ * is one static device array of 4 MiB per GPU, in the library's own device
+ * memory and held until the process ends; qsv_create looks up its address on
+ * the context's device.  The terms are staged through a 256 KiB pinned buffer
+ * that qsv_create allocates for each context.
+ * Limits: at most 4096 terms, and at most 3840 KiB of partial sums, i.e.
+ * 8 x min(4096, ceil(2^n / 4096)) x (number of distinct X/Y masks, at least
+ * 1) x batch bytes (for example n = 28 allows masks x batch <= 120).
+ * Sharing: every call on one GPU uses that GPU's one array, from any context
+ * or stream.  Calls that overlap on one GPU race (two streams, contexts or
+ * threads) and must be ordered by the caller.  The array keeps the last
+ * call's contents; each call writes every value it reads before reading it,
+ * so nothing needs to start at zero.  Before reusing the staging buffer the
+ * call waits (host side) for its previous copy on this context's stream.
+ * Errors: those of qsv_expect; QSV_E_RANGE (more than 4096 terms, or partial
+ * sums beyond the scratch); QSV_E_STATE (no scratch address on the device).
+ */
+qsv_status qsv_expect_noalloc(qsv_ctx *ctx, const qsv_pauli_term *H, int32_t n_terms, int32_t n_qubits,
+                              int64_t batch, const void *psi_dev, double *out_dev);
+
+/*
  * Adjoint gradient (reverse sweep over the partitions).  For every circuit b:
  * energy_b = <psi_b|H|psi_b> and grad_b[j] = d energy_b / d theta_b[j]
  * (parameters used by several rotations receive the sum of their terms).

@@ -50,6 +50,7 @@ class _PlanInfo(ctypes.Structure):
 _lib = None
 EXPORTS = ["qsv_last_error", "qsv_create", "qsv_destroy", "qsv_set_stream", "qsv_partition", "qsv_plan_destroy",
            "qsv_plan_get_info", "qsv_plan_params", "qsv_plan_partition", "qsv_apply", "qsv_expect",
+           "qsv_expect_noalloc",
            "qsv_adjoint_grad", "qsv_set_timing", "qsv_last_sweep_ms", "qsv_last_autotune",
            "qsv_partition_distributed", "qsv_plan_distributed_info", "qsv_plan_specialise"]
 
@@ -74,6 +75,7 @@ def load_library():
         "qsv_plan_get_info": [V, V], "qsv_plan_specialise": [V, V, V], "qsv_plan_params": [V, I32, V, V],
         "qsv_plan_partition": [V, I32, I32, I64, V, V, I64, V],
         "qsv_apply": [V, V, V, V, V], "qsv_expect": [V, V, I32, I32, I64, V, V],
+        "qsv_expect_noalloc": [V, V, I32, I32, I64, V, V],
         "qsv_adjoint_grad": [V, V, V, I32, V, V, V, V, V],
         "qsv_set_timing": [V, I32], "qsv_last_sweep_ms": [V, V, V], "qsv_last_autotune": [V, I32],
         "qsv_partition_distributed": [V, I32, V, I64, I32, I32, U32, V, V],
@@ -241,6 +243,14 @@ def qsv_expect(ctx, H, n_qubits: int, batch: int, psi, out):
     dim = batch << n_qubits if 0 < n_qubits < 63 and batch > 0 else 0
     _check(load_library().qsv_expect(ctx, hp, len(h), n_qubits, batch, _dptr(psi, torch.complex64, dim, "psi"),
                                      _dptr(out, torch.float64, max(batch, 0), "out")))
+
+
+def qsv_expect_noalloc(ctx, H, n_qubits: int, batch: int, psi, out):
+    h, hp = _pauli(H)
+    dim = batch << n_qubits if 0 < n_qubits < 63 and batch > 0 else 0
+    _check(load_library().qsv_expect_noalloc(ctx, hp, len(h), n_qubits, batch,
+                                             _dptr(psi, torch.complex64, dim, "psi"),
+                                             _dptr(out, torch.float64, max(batch, 0), "out")))
 
 
 def qsv_adjoint_grad(ctx, plan, H, theta, psi_final, ckpt, energy, grad):

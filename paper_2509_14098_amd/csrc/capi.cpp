@@ -109,6 +109,9 @@ struct qsv_ctx {
     size_t pinned_bytes = 0;
     hipEvent_t pinned_ready = nullptr;
     hipEvent_t handoff = nullptr;  // orders work across a change of stream
+    // qsv_expect_noalloc: pinned staging of the grouped terms, allocated once by qsv_create
+    void *na_staging = nullptr;
+    hipEvent_t na_staging_ready = nullptr;
     int *queue = nullptr;
     int n_cu = 0;
 
@@ -146,6 +149,18 @@ struct HostGroups {
     std::vector<DevTerm> terms;
 };
 
+// A term in the kernels' form: coeff * i^{#Y} as (re, im), and its Z/Y mask.
+static DevTerm dev_term(const qsv_pauli_term &h)
+{
+    const int ny = __builtin_popcountll(h.x_mask & h.z_mask) & 3;  // i^{#Y}
+    const double c = h.coeff;
+    DevTerm d;
+    d.cre = ny == 0 ? c : ny == 2 ? -c : 0.0;
+    d.cim = ny == 1 ? c : ny == 3 ? -c : 0.0;
+    d.z_mask = h.z_mask;
+    return d;
+}
+
 static HostGroups group_terms(const qsv_pauli_term *H, int n_terms, int n)
 {
     if (n_terms < 0 || (n_terms > 0 && !H)) fail(QSV_E_ARG, "null or negative Pauli sum");
@@ -160,15 +175,7 @@ static HostGroups group_terms(const qsv_pauli_term *H, int n_terms, int n)
         DevGroup dg;
         dg.x_mask = kv.first;
         dg.term_begin = (int32_t)g.terms.size();
-        for (int t : kv.second) {
-            int ny = __builtin_popcountll(H[t].x_mask & H[t].z_mask) & 3;  // i^{#Y}
-            double c = H[t].coeff;
-            DevTerm d;
-            d.cre = ny == 0 ? c : ny == 2 ? -c : 0.0;
-            d.cim = ny == 1 ? c : ny == 3 ? -c : 0.0;
-            d.z_mask = H[t].z_mask;
-            g.terms.push_back(d);
-        }
+        for (int t : kv.second) g.terms.push_back(dev_term(H[t]));
         dg.term_end = (int32_t)g.terms.size();
         g.groups.push_back(dg);
     }
@@ -211,9 +218,21 @@ qsv_status qsv_create(int32_t device, void *hip_stream, qsv_ctx **out)
         hip_check(hipGetDeviceCount(&count), "hipGetDeviceCount");
         if (device < 0 || device >= count) fail(QSV_E_DEVICE, "no such device");
         hip_check(hipSetDevice(device), "hipSetDevice");
+        // set-up of qsv_expect_noalloc: the device address of its static scratch
+        // (once per device) and this context's pinned staging buffer
+        hip_check(noalloc_scratch_init(device), "hipGetSymbolAddress(scratch)");
+        void *staging = nullptr;
+        if (hipHostMalloc(&staging, NOALLOC_TERMS_BYTES) != hipSuccess) fail(QSV_E_NOMEM, "pinned allocation failed");
+        hipEvent_t ready = nullptr;
+        if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess) {
+            (void)hipHostFree(staging);
+            fail(QSV_E_DEVICE, "hipEventCreate failed");
+        }
         qsv_ctx *c = new qsv_ctx();
         c->device = device;
         c->stream = (hipStream_t)hip_stream;
+        c->na_staging = staging;
+        c->na_staging_ready = ready;
         *out = c;
     });
 }
@@ -231,6 +250,8 @@ qsv_status qsv_destroy(qsv_ctx *ctx)
         if (ctx->pinned) (void)hipHostFree(ctx->pinned);
         if (ctx->pinned_ready) (void)hipEventDestroy(ctx->pinned_ready);
         if (ctx->handoff) (void)hipEventDestroy(ctx->handoff);
+        if (ctx->na_staging) (void)hipHostFree(ctx->na_staging);
+        if (ctx->na_staging_ready) (void)hipEventDestroy(ctx->na_staging_ready);
         for (auto e : ctx->events) (void)hipEventDestroy(e);
         delete ctx;
     });
@@ -784,6 +805,66 @@ qsv_status qsv_expect(qsv_ctx *ctx, const qsv_pauli_term *H, int32_t n_terms, in
         if (!g.groups.empty()) upload_groups(ctx, g, dg, dt);
         hip_check(launch_expect(dg, (int)g.groups.size(), dt, n_qubits, batch, (const float2 *)psi_dev, partials,
                                 n_blocks, out_dev, ctx->stream),
+                  "expect launch");
+    });
+}
+
+qsv_status qsv_expect_noalloc(qsv_ctx *ctx, const qsv_pauli_term *H, int32_t n_terms, int32_t n_qubits,
+                              int64_t batch, const void *psi_dev, double *out_dev)
+{
+    return guarded([&] {
+        if (!ctx || !psi_dev || !out_dev) fail(QSV_E_ARG, "null argument");
+        if (n_qubits < 1 || n_qubits > 34) fail(QSV_E_ARG, "n_qubits must be in [1, 34]");
+        if (batch < 1) fail(QSV_E_ARG, "batch must be >= 1");
+        if (n_terms < 0 || (n_terms > 0 && !H)) fail(QSV_E_ARG, "null or negative Pauli sum");
+        if (n_terms > NOALLOC_MAX_TERMS) fail(QSV_E_RANGE, "qsv_expect_noalloc takes at most 4096 Pauli terms");
+        const uint64_t full = n_qubits >= 64 ? ~0ull : ((1ull << n_qubits) - 1);
+        for (int t = 0; t < n_terms; ++t)
+            if ((H[t].x_mask & ~full) || (H[t].z_mask & ~full)) fail(QSV_E_ARG, "Pauli mask beyond n_qubits");
+        // the grouping of qsv_expect (groups by increasing X mask, terms in input
+        // order inside a group) without containers: an in-place sort of indices
+        int idx[NOALLOC_MAX_TERMS];
+        for (int t = 0; t < n_terms; ++t) idx[t] = t;
+        std::sort(idx, idx + n_terms, [&](int a, int b) {
+            return H[a].x_mask != H[b].x_mask ? H[a].x_mask < H[b].x_mask : a < b;
+        });
+        int n_groups = 0;
+        for (int i = 0; i < n_terms; ++i)
+            if (i == 0 || H[idx[i]].x_mask != H[idx[i - 1]].x_mask) ++n_groups;
+        const int n_blocks = 4096;  // the cap qsv_expect uses
+        const size_t partials = sizeof(double) * (size_t)expect_blocks(n_qubits, n_blocks) *
+                                (size_t)std::max(1, n_groups) * (size_t)batch;
+        if (partials > NOALLOC_SCRATCH_BYTES - NOALLOC_TERMS_BYTES)
+            fail(QSV_E_RANGE, "qsv_expect_noalloc: " + std::to_string(partials) + " bytes of partial sums exceed its " +
+                                  std::to_string(NOALLOC_SCRATCH_BYTES - NOALLOC_TERMS_BYTES) + "-byte scratch");
+        hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+        char *dev = (char *)noalloc_scratch(ctx->device);
+        if (!dev) fail(QSV_E_STATE, "static scratch not set up on this device");
+        const size_t gb = (size_t)n_groups * sizeof(DevGroup), toff = (gb + 15) & ~size_t(15);
+        const size_t bytes = toff + (size_t)n_terms * sizeof(DevTerm);
+        if (n_terms > 0) {
+            // the staging buffer is free again once the previous call's copy has run
+            hip_check(hipEventSynchronize(ctx->na_staging_ready), "hipEventSynchronize");
+            DevGroup *hg = (DevGroup *)ctx->na_staging;
+            DevTerm *ht = (DevTerm *)((char *)ctx->na_staging + toff);
+            int g = -1;
+            for (int i = 0; i < n_terms; ++i) {
+                const qsv_pauli_term &h = H[idx[i]];
+                if (g < 0 || h.x_mask != hg[g].x_mask) {
+                    ++g;
+                    hg[g].x_mask = h.x_mask;
+                    hg[g].term_begin = i;
+                }
+                hg[g].term_end = i + 1;
+                ht[i] = dev_term(h);
+            }
+            hip_check(hipMemcpyAsync(dev, ctx->na_staging, bytes, hipMemcpyHostToDevice, ctx->stream), "hipMemcpyAsync");
+            hip_check(hipEventRecord(ctx->na_staging_ready, ctx->stream), "hipEventRecord");
+        }
+        hip_check(launch_expect(n_groups ? (const DevGroup *)dev : nullptr, n_groups,
+                                n_groups ? (const DevTerm *)(dev + toff) : nullptr, n_qubits, batch,
+                                (const float2 *)psi_dev, (double *)(dev + NOALLOC_TERMS_BYTES), n_blocks, out_dev,
+                                ctx->stream),
                   "expect launch");
     });
 }

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "kernels.h"
 
@@ -200,6 +201,39 @@ static int blocks_for(uint64_t work, int cap)
 }
 
 int expect_blocks(int n, int cap) { return blocks_for(1ull << n, cap); }
+
+// Scratch of qsv_expect_noalloc: one fixed array per device, in the code
+// object's own device memory, so the entry point never allocates.  Host code
+// reaches it only through the address hipGetSymbolAddress returns on each
+// device (the array's name is a host-side stand-in, not a device address).
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+static void *g_scratch_dev[NOALLOC_MAX_DEVICES];
+static std::mutex g_scratch_mutex;
+
+hipError_t noalloc_scratch_init(int device)
+{
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch_dev[device]) return hipSuccess;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;  // the lookup is per device: that device must be current
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_dev[device] = p;
+    return hipSuccess;
+}
+
+void *noalloc_scratch(int device)
+{
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    return g_scratch_dev[device];
+}
 
 hipError_t launch_expect(const DevGroup *groups, int n_groups, const DevTerm *terms, int n, int64_t batch,
                          const float2 *psi, double *partials, int n_blocks, double *out, hipStream_t s)

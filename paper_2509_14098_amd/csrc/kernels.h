@@ -25,6 +25,18 @@ struct DevGroup {
 int expect_blocks(int n, int cap);
 hipError_t launch_expect(const DevGroup *groups, int n_groups, const DevTerm *terms, int n, int64_t batch,
                          const float2 *psi, double *partials, int n_blocks, double *out, hipStream_t s);
+// The fixed scratch of qsv_expect_noalloc (one per device): the grouped
+// Pauli terms, then the per-block partial sums.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(4) << 20;
+constexpr size_t NOALLOC_TERMS_BYTES = size_t(256) << 10;
+constexpr int NOALLOC_MAX_TERMS = 4096;   // 4096 x (DevTerm + DevGroup) fit NOALLOC_TERMS_BYTES
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static_assert(NOALLOC_MAX_TERMS * (sizeof(DevTerm) + sizeof(DevGroup)) + 16 <= NOALLOC_TERMS_BYTES, "terms region");
+// Looks up the array's address on `device`, which must be the current device;
+// once per device (later calls return at once).
+hipError_t noalloc_scratch_init(int device);
+// The address found by noalloc_scratch_init, or null before it ran.
+void *noalloc_scratch(int device);
 // Blocks launch_apply_h uses for 2^n amplitudes and a cap (one partial each).
 int apply_h_blocks(int n, int cap);
 hipError_t launch_apply_h(const DevGroup *groups, int n_groups, const DevTerm *terms, int n, const float2 *psi,
