@@ -170,7 +170,10 @@ qsv_status qsv_set_stream(qsv_ctx *ctx, void *hip_stream);
  * The gate array is copied; it is not retained.  The plan is freed by
  * qsv_plan_destroy.
  * Batched plans (n_circuits > 1) keep each whole state on chip: 4 <= n <= 14.
- * Errors: QSV_E_ARG (n_qubits < 1 or > 34, k_local < 0, qubit out of range,
+ * Qubit counts: up to 35 with a context (a 2^35-amplitude complex64 state
+ * is 256 GiB, the largest that fits the MI355X's 288 GB), up to 40 for
+ * host-only plans (ctx NULL: e.g. the whole of a multi-GPU run).
+ * Errors: QSV_E_ARG (n_qubits < 1 or above those limits, k_local < 0, qubit out of range,
  * q0 == q1, unknown kind, bad offsets, a batched plan with n_qubits > 14),
  * QSV_E_RANGE (param >= 0 on a non-rotation), QSV_E_NOMEM, QSV_E_DEVICE.
  */
@@ -237,8 +240,9 @@ qsv_status qsv_plan_params(const qsv_plan *plan, int32_t circuit, int64_t *offse
  * differ in that high bit.  On one GPU these SWAPs run as sweeps of the same
  * kernels; a final set of SWAPs restores the logical order, so qsv_apply,
  * qsv_expect and qsv_adjoint_grad see the state in logical order.
- * k_local == 0 gives the default k; tile as in qsv_partition.
- * Errors: QSV_E_ARG (n_global < 1, fewer than tile-size qubits left local,
+ * k_local == 0 gives the default k; tile as in qsv_partition.  n_qubits
+ * from 2 up to 35 with a context, up to 40 for host-only plans (ctx NULL).
+ * Errors: QSV_E_ARG (n_qubits out of range, n_global < 1, fewer than tile-size qubits left local,
  * invalid gates, k_local not below the tile size), QSV_E_RANGE,
  * QSV_E_UNSUPPORTED (gradient plans with tiles over 13 qubits), QSV_E_NOMEM,
  * QSV_E_DEVICE.
@@ -334,6 +338,11 @@ int32_t qsv_last_autotune(int32_t *out, int32_t cap);
  * with HIP events on the context stream when timing is enabled. */
 qsv_status qsv_set_timing(qsv_ctx *ctx, int32_t enable);
 qsv_status qsv_last_sweep_ms(qsv_ctx *ctx, double *total_ms, int64_t *n_launches);
+/* The duration in ms of each sweep launch of the last qsv_apply on ctx (in
+ * partition order; at most cap written to ms_out, host memory), measured with
+ * the same HIP events when timing is enabled; *n_launches = the number of
+ * launches (0 when timing was off).  Waits for the last launch to finish. */
+qsv_status qsv_last_sweep_times(qsv_ctx *ctx, float *ms_out, int64_t cap, int64_t *n_launches);
 
 #ifdef __cplusplus
 }

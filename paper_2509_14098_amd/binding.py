@@ -51,7 +51,7 @@ _lib = None
 EXPORTS = ["qsv_last_error", "qsv_create", "qsv_destroy", "qsv_set_stream", "qsv_partition", "qsv_plan_destroy",
            "qsv_plan_get_info", "qsv_plan_params", "qsv_plan_partition", "qsv_apply", "qsv_expect",
            "qsv_expect_noalloc",
-           "qsv_adjoint_grad", "qsv_set_timing", "qsv_last_sweep_ms", "qsv_last_autotune",
+           "qsv_adjoint_grad", "qsv_set_timing", "qsv_last_sweep_ms", "qsv_last_sweep_times", "qsv_last_autotune",
            "qsv_partition_distributed", "qsv_plan_distributed_info", "qsv_plan_specialise"]
 
 
@@ -77,7 +77,7 @@ def load_library():
         "qsv_apply": [V, V, V, V, V], "qsv_expect": [V, V, I32, I32, I64, V, V],
         "qsv_expect_noalloc": [V, V, I32, I32, I64, V, V],
         "qsv_adjoint_grad": [V, V, V, I32, V, V, V, V, V],
-        "qsv_set_timing": [V, I32], "qsv_last_sweep_ms": [V, V, V], "qsv_last_autotune": [V, I32],
+        "qsv_set_timing": [V, I32], "qsv_last_sweep_ms": [V, V, V], "qsv_last_sweep_times": [V, V, I64, V], "qsv_last_autotune": [V, I32],
         "qsv_partition_distributed": [V, I32, V, I64, I32, I32, U32, V, V],
         "qsv_plan_distributed_info": [V, V, V, V, V],
     }
@@ -144,6 +144,15 @@ def qsv_last_sweep_ms(ctx):
     ms, n = ctypes.c_double(), ctypes.c_int64()
     _check(load_library().qsv_last_sweep_ms(ctx, ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def qsv_last_sweep_times(ctx):
+    """Per-launch ms of the last qsv_apply (timing enabled), as a numpy array."""
+    n = ctypes.c_int64()
+    _check(load_library().qsv_last_sweep_times(ctx, None, 0, ctypes.byref(n)))
+    out = np.zeros(max(n.value, 1), dtype=np.float32)
+    _check(load_library().qsv_last_sweep_times(ctx, out.ctypes.data_as(ctypes.c_void_p), n.value, ctypes.byref(n)))
+    return out[:n.value]
 
 
 def qsv_partition(ctx, n_qubits: int, gates, circ_offsets=None, k_local: int = 0, flags: int = 0, tile=None):

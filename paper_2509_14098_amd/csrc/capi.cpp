@@ -21,6 +21,13 @@ namespace {
 
 thread_local std::string g_err;
 
+// Largest states: 2^35 complex64 amplitudes (256 GiB) is the largest power of
+// two that fits one MI355X's 288 GB of HBM; host-only plans (no device
+// tables) reach the qubit counts of multi-GPU runs, e.g. the 40-qubit circuit
+// whose 32-qubit rank share the sweeps run on.
+constexpr int MAX_DEVICE_QUBITS = 35;
+constexpr int MAX_HOST_QUBITS = 40;
+
 struct Fail {
     qsv_status code;
     std::string msg;
@@ -300,6 +307,20 @@ qsv_status qsv_last_sweep_ms(qsv_ctx *ctx, double *total_ms, int64_t *n_launches
     });
 }
 
+qsv_status qsv_last_sweep_times(qsv_ctx *ctx, float *ms_out, int64_t cap, int64_t *n_launches)
+{
+    return guarded([&] {
+        if (!ctx || !n_launches || cap < 0 || (cap > 0 && !ms_out)) fail(QSV_E_ARG, "null argument");
+        *n_launches = ctx->timing ? ctx->last_launches : 0;
+        if (*n_launches > 0) {
+            hip_check(hipEventSynchronize(ctx->events[2 * ctx->last_launches - 1]), "hipEventSynchronize");
+            for (int64_t i = 0; i < std::min(cap, *n_launches); ++i)
+                hip_check(hipEventElapsedTime(&ms_out[i], ctx->events[2 * i], ctx->events[2 * i + 1]),
+                          "hipEventElapsedTime");
+        }
+    });
+}
+
 // Build (and, with a context, upload) a plan for validated input.
 static qsv_plan *make_plan(qsv_ctx *ctx, int n_qubits, const qsv_gate *gates, const std::vector<int64_t> &off,
                            uint32_t flags, int k, int R, int LW, int n_global = 0)
@@ -504,7 +525,8 @@ qsv_status qsv_partition(qsv_ctx *ctx, int32_t n_qubits, const qsv_gate *gates, 
     return guarded([&] {
         auto t0 = std::chrono::steady_clock::now();
         if (!out) fail(QSV_E_ARG, "out is null");
-        if (n_qubits < 1 || n_qubits > 34) fail(QSV_E_ARG, "n_qubits must be in [1, 34]");
+        if (n_qubits < 1 || n_qubits > (ctx ? MAX_DEVICE_QUBITS : MAX_HOST_QUBITS))
+            fail(QSV_E_ARG, ctx ? "n_qubits must be in [1, 35]" : "n_qubits must be in [1, 40] for a host-only plan");
         if (k_local < 0) fail(QSV_E_ARG, "k_local must be >= 0");
         if (n_circuits < 1) fail(QSV_E_ARG, "n_circuits must be >= 1");
         if (flags & ~(QSV_PLAN_GATE_BY_GATE | QSV_PLAN_GRAD | QSV_PLAN_TUNE_SPECIALISED)) fail(QSV_E_ARG, "unknown flag");
@@ -707,7 +729,8 @@ qsv_status qsv_partition_distributed(qsv_ctx *ctx, int32_t n_qubits, const qsv_g
     return guarded([&] {
         auto t0 = std::chrono::steady_clock::now();
         if (!out) fail(QSV_E_ARG, "out is null");
-        if (n_qubits < 2 || n_qubits > 34) fail(QSV_E_ARG, "n_qubits must be in [2, 34]");
+        if (n_qubits < 2 || n_qubits > (ctx ? MAX_DEVICE_QUBITS : MAX_HOST_QUBITS))
+            fail(QSV_E_ARG, ctx ? "n_qubits must be in [2, 35]" : "n_qubits must be in [2, 40] for a host-only plan");
         if (n_gates < 0 || (n_gates > 0 && !gates)) fail(QSV_E_ARG, "bad gate array");
         if (flags & ~(QSV_PLAN_GATE_BY_GATE | QSV_PLAN_GRAD)) fail(QSV_E_ARG, "unknown flag");
         for (int64_t g = 0; g < n_gates; ++g) {
@@ -792,7 +815,7 @@ qsv_status qsv_expect(qsv_ctx *ctx, const qsv_pauli_term *H, int32_t n_terms, in
 {
     return guarded([&] {
         if (!ctx || !psi_dev || !out_dev) fail(QSV_E_ARG, "null argument");
-        if (n_qubits < 1 || n_qubits > 34) fail(QSV_E_ARG, "n_qubits must be in [1, 34]");
+        if (n_qubits < 1 || n_qubits > MAX_DEVICE_QUBITS) fail(QSV_E_ARG, "n_qubits must be in [1, 35]");
         if (batch < 1) fail(QSV_E_ARG, "batch must be >= 1");
         HostGroups g = group_terms(H, n_terms, n_qubits);
         hip_check(hipSetDevice(ctx->device), "hipSetDevice");
@@ -814,7 +837,7 @@ qsv_status qsv_expect_noalloc(qsv_ctx *ctx, const qsv_pauli_term *H, int32_t n_t
 {
     return guarded([&] {
         if (!ctx || !psi_dev || !out_dev) fail(QSV_E_ARG, "null argument");
-        if (n_qubits < 1 || n_qubits > 34) fail(QSV_E_ARG, "n_qubits must be in [1, 34]");
+        if (n_qubits < 1 || n_qubits > MAX_DEVICE_QUBITS) fail(QSV_E_ARG, "n_qubits must be in [1, 35]");
         if (batch < 1) fail(QSV_E_ARG, "batch must be >= 1");
         if (n_terms < 0 || (n_terms > 0 && !H)) fail(QSV_E_ARG, "null or negative Pauli sum");
         if (n_terms > NOALLOC_MAX_TERMS) fail(QSV_E_RANGE, "qsv_expect_noalloc takes at most 4096 Pauli terms");

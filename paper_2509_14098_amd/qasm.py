@@ -12,6 +12,13 @@ gate kinds of the C interface:
   measured qubit (the library computes the amplitudes before measurement; it
   does not sample); reset and gates after a measurement are rejected.
 
+Reading of `rz`: qelib1.inc defines rz(a) as u1(a) = diag(1, e^{ia}); this
+reader takes it as the rotation RZ(a) = exp(-i a Z / 2) = diag(e^{-ia/2},
+e^{ia/2}) instead (the convention of Qiskit, through which the paper parses
+its circuits, Section 4.1).  The two differ by the global phase e^{-ia/2}:
+every expectation value and probability is the same, amplitudes are not.
+`u1` and `p` are the phase gate diag(1, e^{ia}) as in qelib1.
+
 Qubits of successive qreg declarations are numbered consecutively: qubit q of
 the circuit is bit q of the amplitude index.  Angle expressions may use
 numbers, pi, + - * / and parentheses; they are evaluated with a small

@@ -212,14 +212,21 @@ def test_c3_full_size_properties(sim):
     torch.cuda.empty_cache()
 
 
-def test_maximum_size_34_qubits(sim):
-    """The largest state the interface accepts, 34 qubits (128 GiB): a U3
-    layer matches its product-state closed form on sampled amplitudes, and
-    a short brickwork followed by its inverse returns to the U3 state."""
-    n = 34
+def test_maximum_size_35_qubits(sim):
+    """The largest state the interface accepts, 35 qubits (256 GiB of the
+    MI355X's 288 GB): a U3 layer matches its product-state closed form on
+    sampled amplitudes and in <Z_q> and <sum Z_i Z_i+1>, and a short
+    brickwork followed by its inverse returns to the U3 state."""
+    n = 35
     torch.cuda.empty_cache()
+    try:
+        psi = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
+    except torch.OutOfMemoryError:
+        pytest.skip("a 256 GiB state does not fit the free device memory")
+    psi.zero_()
+    psi[0] = 1.0
     layer, ang = W.u3_layer(n, seed=11)
-    psi, _ = run(sim, n, layer, k=10)
+    run(sim, n, layer, k=10, psi=psi)
     idx = np.random.default_rng(5).integers(0, 1 << n, size=1024)
     got = psi[torch.as_tensor(idx, device=psi.device)].cpu().numpy()
     ref = np.ones(len(idx), complex)
@@ -227,6 +234,10 @@ def test_maximum_size_34_qubits(sim):
         b = (idx >> q) & 1
         ref *= np.where(b == 0, np.cos(ang[q, 0] / 2), np.exp(1j * ang[q, 1]) * np.sin(ang[q, 0] / 2))
     assert np.max(np.abs(got - ref)) < 1e-7
+    for q in (0, 17, 34):
+        assert abs(float(sim.expect(W.z_on(q), psi, n)[0]) - np.cos(ang[q, 0])) < 1e-5
+    zz = float(sim.expect(W.zz_chain(n), psi, n)[0])
+    assert abs(zz - sum(np.cos(ang[i, 0]) * np.cos(ang[i + 1, 0]) for i in range(n - 1))) < 1e-4
     body = W.brickwork_c3(n=n, layers=3, seed=12)
     run(sim, n, body, k=10, psi=psi)
     run(sim, n, W.inverse_circuit(body), k=10, psi=psi)

@@ -153,7 +153,35 @@ def test_invalid_input_rejected(case, code):
     assert e.value.code == code
 
 
-@pytest.mark.parametrize("name,n,g", [("c2", 28, 4), ("c3", 32, 8), ("qft", 24, 4), ("rand", 18, 3)])
+@pytest.mark.parametrize("name,n,layers,k", [("c2", 28, 120, 10), ("c3", 34, 100, 12)])
+def test_partition_matches_oracle_above_5000_gates(name, n, layers, k):
+    """Paper-scale gate counts: the 28-qubit brickwork generator at 120
+    layers (5 055 gates) and the random-matching generator at 34 qubits and
+    100 layers (5 100 gates), exact partitions against the oracle's greedy."""
+    gen = W.brickwork_c2 if name == "c2" else W.brickwork_c3
+    gates = gen(n=n, layers=layers, seed=11)
+    assert len(gates) > 5000
+    plan = _compare(n, gates, k, tile=(5, 8))
+    Q.qsv_plan_destroy(plan)
+
+
+def test_host_only_plans_reach_40_qubits():
+    """Host-only plans (no device tables) take up to 40 qubits, device plans
+    up to 35 (a 256 GiB complex64 state): the 40-qubit circuit whose 32-qubit
+    rank share is the 60-layer random-matching workload plans on the host."""
+    gates = W.brickwork_c3(n=40, layers=4, seed=3)
+    plan = Q.qsv_partition(None, 40, gates, None, 10, 0, None)
+    assert Q.qsv_plan_info(plan)["n_qubits"] == 40
+    Q.qsv_plan_destroy(plan)
+    with pytest.raises(Q.QsvError) as e:
+        Q.qsv_partition(None, 41, W.ghz(41), None, 10, 0, None)
+    assert e.value.code == -1 and "40" in str(e.value)
+    with pytest.raises(Q.QsvError):
+        Q.qsv_partition_distributed(None, 41, W.ghz(41), 8)
+
+
+@pytest.mark.parametrize("name,n,g", [("c2", 28, 4), ("c3", 32, 8), ("qft", 24, 4), ("rand", 18, 3),
+                                      ("c3-40", 40, 8)])
 def test_distributed_level_matches_oracle(name, n, g):
     """The distributed level is the same greedy with n - g local qubits (exact
     gate lists against the oracle's); every distributed partition's local set
@@ -161,7 +189,9 @@ def test_distributed_level_matches_oracle(name, n, g):
     partitions under it keep every gate in order, with tiles inside one rank
     (low positions) except for the remap SWAPs."""
     gates = {"c2": W.brickwork_c2, "c3": W.brickwork_c3, "qft": lambda: W.qft(n),
-             "rand": lambda: W.random_circuit(n, 300, seed=123)}[name]()
+             "rand": lambda: W.random_circuit(n, 300, seed=123),
+             # the whole 40-qubit run: 256 ranks of 32 qubits
+             "c3-40": lambda: W.brickwork_c3(n=40)}[name]()
     plan = Q.qsv_partition_distributed(None, n, gates, g)
     try:
         info = Q.qsv_plan_distributed_info(plan)
