@@ -300,6 +300,18 @@ def bench_gradient(sim, args):
         f1, b1 = timed()
         res = dict(fwd_ms=f1, grad_ms=b1, ratio=b1 / f1, specialise_s=spec_s,
                    table_driven=dict(fwd_ms=round(f0, 4), grad_ms=round(b0, 4), ratio=round(b0 / f0, 4)))
+    # the energy alone (qsv_expect of H on the forward's state: term upload,
+    # tile passes, final sum), GPU time between events around each call
+    for _ in range(3):
+        Q.qsv_expect(sim.ctx, H, n, 1, psi, out)
+    sync()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(50)]
+    for e0, e1 in ev:
+        e0.record()
+        Q.qsv_expect(sim.ctx, H, n, 1, psi, out)
+        e1.record()
+    sync()
+    res["energy_us"] = float(np.median([e0.elapsed_time(e1) for e0, e1 in ev])) * 1e3
     res.update(energy=float(energy[0]), partitions=plan.info["n_partitions"], tile=tile)
     res["_grad"] = grad.cpu().numpy()  # compared with the oracle in the CPU leg
     res["_energy"] = float(energy[0])
@@ -670,7 +682,8 @@ def main():
                                     # holds the <Z0> reduction)
                                     fused_speedup=round(head["gbg_ms"] / head["step_ms"], 2))
     if not args.skip_grad:
-        line["adjoint"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in bench_gradient(sim, args).items()}
+        line["adjoint"] = {k: (round(v, 4) if isinstance(v, float) and not k.startswith("_") else v)
+                           for k, v in bench_gradient(sim, args).items()}
     if not args.skip_batched:
         line["batched"] = bench_batched(sim, args)
     if not args.skip_gbg:

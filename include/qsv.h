@@ -292,11 +292,12 @@ qsv_status qsv_expect(qsv_ctx *ctx, const qsv_pauli_term *H, int32_t n_terms, in
  * scratch (the grouped Pauli terms, then the per-block float64 partial sums)
  * is one static device array of 4 MiB per GPU, in the library's own device
  * memory and held until the process ends; qsv_create looks up its address on
- * the context's device.  The terms are staged through a 256 KiB pinned buffer
+ * the context's device.  The terms are staged through a 512 KiB pinned buffer
  * that qsv_create allocates for each context.
- * Limits: at most 4096 terms, and at most 3840 KiB of partial sums, i.e.
- * 8 x min(4096, ceil(2^n / 4096)) x (number of distinct X/Y masks, at least
- * 1) x batch bytes (for example n = 28 allows masks x batch <= 120).
+ * Limits: at most 4096 terms, and at most 3.5 MiB of partial sums, i.e.
+ * 8 x min(1024, 2^(n-12)) x (tile passes, at least 1) x batch bytes, where a
+ * pass covers the X/Y masks that fit one 12-qubit tile together with qubits
+ * 0-3 (for example n = 28 allows passes x batch <= 448).
  * Sharing: every call on one GPU uses that GPU's one array, from any context
  * or stream.  Calls that overlap on one GPU race (two streams, contexts or
  * threads) and must be ordered by the caller.  The array keeps the last

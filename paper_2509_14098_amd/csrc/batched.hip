@@ -63,6 +63,7 @@ __global__ __launch_bounds__(1 << LW) void batched_kernel(
     const float *__restrict__ pool, const int32_t *__restrict__ order, const int32_t *__restrict__ circ_part,
     const int64_t *__restrict__ circ_theta, const int64_t *__restrict__ circ_npar,
     const int32_t *__restrict__ param_off, const int32_t *__restrict__ param_slots,
+    const int32_t *__restrict__ circ_pool_delta, const int32_t *__restrict__ circ_slot_delta,
     const DevGroup *__restrict__ groups, const DevTerm *__restrict__ terms, BatchArgs A)
 {
     constexpr int NA = 1 << R, WAVES = (1 << LW) / 64;
@@ -78,7 +79,12 @@ __global__ __launch_bounds__(1 << LW) void batched_kernel(
         __syncthreads();
         if (item >= A.n_circuits) break;
         const int c = order[item];
+        // circuits of the same structure share their tables: this circuit's own
+        // matrices and gradient slots sit at a constant offset from the ones the
+        // tables name
         const DevPart *__restrict__ P = parts + circ_part[c];
+        const float *__restrict__ cpool = pool + circ_pool_delta[c];
+        const int32_t slot_delta = circ_slot_delta[c];
         const int t = P->t, w = t - R;
         const bool active = tid < (1u << w);
         const uint32_t dim = 1u << t;
@@ -89,7 +95,7 @@ __global__ __launch_bounds__(1 << LW) void batched_kernel(
         } else {  // forward from |0..0>
             for (uint32_t x = tid; x < dim; x += (1u << LW)) lds[swz(x)] = float2{x == 0 ? 1.f : 0.f, 0.f};
             __syncthreads();
-            run_stages<R, false>(lds, stages, ops, pool, P->stage_begin, P->stage_end, w, tid, 0);
+            run_stages<R, false>(lds, stages, ops, cpool, P->stage_begin, P->stage_end, w, tid, 0);
         }
         if (A.psi_out) {  // the tile is the whole state and its positions are the qubits in order
             float2 *dst = A.psi_out + (uint64_t)c * dim;
@@ -155,12 +161,12 @@ __global__ __launch_bounds__(1 << LW) void batched_kernel(
                 const DevOp o = ops[k];
                 if (o.grad_slot >= 0) {
                     const double v = wave_sum(grad_term<R>(a, l, o, tid, 0));
-                    if ((tid & 63) == 0) A.gpart[(int64_t)o.grad_slot * WAVES + wave] = v;
+                    if ((tid & 63) == 0) A.gpart[(int64_t)(o.grad_slot + slot_delta) * WAVES + wave] = v;
                 }
                 // one array at a time: with 1024 threads a lane has 128 VGPRs, too
                 // few to update psi and lambda together without spilling
-                apply_op<R, true>(a, o, pool, tid, 0);
-                apply_op<R, true>(l, o, pool, tid, 0);
+                apply_op<R, true>(a, o, cpool, tid, 0);
+                apply_op<R, true>(l, o, cpool, tid, 0);
             }
         }
         // this circuit's gradient entries: slots in slot order, waves in order
@@ -221,7 +227,8 @@ hipError_t launch_batched(const Plan &plan, const DevGroup *groups, int n_groups
     set_lds_attr<BATCH_R, BATCH_LW>();
     hipLaunchKernelGGL((batched_kernel<BATCH_R, BATCH_LW>), dim3(grid), dim3(1 << BATCH_LW), lds, s, plan.d_parts,
                        plan.d_stages, plan.d_ops, plan.d_pool, plan.d_batch_order, plan.d_circ_part,
-                       plan.d_circ_theta, plan.d_circ_npar, plan.d_param_off, plan.d_param_slots, groups, terms, A);
+                       plan.d_circ_theta, plan.d_circ_npar, plan.d_param_off, plan.d_param_slots,
+                       plan.d_circ_pool_delta, plan.d_circ_slot_delta, groups, terms, A);
     return hipGetLastError();
 }
 

@@ -151,11 +151,6 @@ struct qsv_ctx {
 
 struct qsv_plan : public Plan {};
 
-struct HostGroups {
-    std::vector<DevGroup> groups;
-    std::vector<DevTerm> terms;
-};
-
 // A term in the kernels' form: coeff * i^{#Y} as (re, im), and its Z/Y mask.
 static DevTerm dev_term(const qsv_pauli_term &h)
 {
@@ -165,35 +160,87 @@ static DevTerm dev_term(const qsv_pauli_term &h)
     d.cre = ny == 0 ? c : ny == 2 ? -c : 0.0;
     d.cim = ny == 1 ? c : ny == 3 ? -c : 0.0;
     d.z_mask = h.z_mask;
+    d.zt = 0;
+    d.pad = 0;
     return d;
 }
 
-static HostGroups group_terms(const qsv_pauli_term *H, int n_terms, int n)
+// Checks a Pauli sum against n qubits.
+static void check_terms(const qsv_pauli_term *H, int n_terms, int n)
 {
     if (n_terms < 0 || (n_terms > 0 && !H)) fail(QSV_E_ARG, "null or negative Pauli sum");
     const uint64_t full = n >= 64 ? ~0ull : ((1ull << n) - 1);
-    std::map<uint64_t, std::vector<int>> by_x;
-    for (int t = 0; t < n_terms; ++t) {
+    for (int t = 0; t < n_terms; ++t)
         if ((H[t].x_mask & ~full) || (H[t].z_mask & ~full)) fail(QSV_E_ARG, "Pauli mask beyond n_qubits");
-        by_x[H[t].x_mask].push_back(t);
+}
+
+// Groups the terms by X mask: groups in increasing mask order, terms in input
+// order inside a group.  idx (n_terms entries) is scratch; groups and terms
+// receive at most n_terms records each.  Returns the number of groups.
+// Allocates nothing.
+static int group_into(const qsv_pauli_term *H, int n_terms, int *idx, DevGroup *groups, DevTerm *terms)
+{
+    for (int t = 0; t < n_terms; ++t) idx[t] = t;
+    std::sort(idx, idx + n_terms, [&](int a, int b) {
+        return H[a].x_mask != H[b].x_mask ? H[a].x_mask < H[b].x_mask : a < b;
+    });
+    int g = -1;
+    for (int i = 0; i < n_terms; ++i) {
+        const qsv_pauli_term &h = H[idx[i]];
+        if (g < 0 || h.x_mask != groups[g].x_mask) {
+            ++g;
+            groups[g].x_mask = h.x_mask;
+            groups[g].term_begin = i;
+            groups[g].xt = 0;
+            groups[g].pad = 0;
+        }
+        groups[g].term_end = i + 1;
+        terms[i] = dev_term(h);
     }
+    return g + 1;
+}
+
+struct HostGroups {
+    std::vector<DevPass> passes;  // expectation passes (qsv_expect only)
+    std::vector<DevGroup> groups;
+    std::vector<DevTerm> terms;
+};
+
+static HostGroups group_terms(const qsv_pauli_term *H, int n_terms, int n, bool passes)
+{
+    check_terms(H, n_terms, n);
     HostGroups g;
-    for (auto &kv : by_x) {
-        DevGroup dg;
-        dg.x_mask = kv.first;
-        dg.term_begin = (int32_t)g.terms.size();
-        for (int t : kv.second) g.terms.push_back(dev_term(H[t]));
-        dg.term_end = (int32_t)g.terms.size();
-        g.groups.push_back(dg);
+    std::vector<int> idx(n_terms);
+    g.groups.resize(n_terms);
+    g.terms.resize(n_terms);
+    g.groups.resize(group_into(H, n_terms, idx.data(), g.groups.data(), g.terms.data()));
+    if (passes) {
+        g.passes.resize(g.groups.size());
+        g.passes.resize(
+            plan_expect_passes(n, g.groups.data(), (int)g.groups.size(), g.terms.data(), g.passes.data()));
     }
     return g;
 }
 
-// Upload grouped terms into the context (pinned staging + async copy).
-static void upload_groups(qsv_ctx *ctx, const HostGroups &g, DevGroup *&dgroups, DevTerm *&dterms)
+// Byte offsets of passes, groups and terms in one upload.
+struct TermLayout {
+    size_t groups = 0, terms = 0, end = 0;
+};
+static TermLayout term_layout(size_t n_passes, size_t n_groups, size_t n_terms)
 {
-    size_t gb = g.groups.size() * sizeof(DevGroup), tb = g.terms.size() * sizeof(DevTerm);
-    size_t need = gb + tb + 64;
+    auto up = [](size_t x) { return (x + 15) & ~size_t(15); };
+    TermLayout L;
+    L.groups = up(n_passes * sizeof(DevPass));
+    L.terms = L.groups + up(n_groups * sizeof(DevGroup));
+    L.end = L.terms + n_terms * sizeof(DevTerm);
+    return L;
+}
+
+// Upload grouped terms (and passes) into the context (pinned staging + async copy).
+static void upload_groups(qsv_ctx *ctx, const HostGroups &g, DevPass *&dpasses, DevGroup *&dgroups, DevTerm *&dterms)
+{
+    const TermLayout L = term_layout(g.passes.size(), g.groups.size(), g.terms.size());
+    const size_t need = L.end + 64;
     if (ctx->pinned_ready) hip_check(hipEventSynchronize(ctx->pinned_ready), "hipEventSynchronize");
     if (need > ctx->pinned_bytes) {
         if (ctx->pinned) (void)hipHostFree(ctx->pinned);
@@ -203,14 +250,15 @@ static void upload_groups(qsv_ctx *ctx, const HostGroups &g, DevGroup *&dgroups,
     }
     char *dev = (char *)ctx->ensure(ctx->terms_dev, ctx->terms_bytes, need);
     char *h = (char *)ctx->pinned;
-    size_t toff = (gb + 15) & ~size_t(15);
-    if (gb) std::memcpy(h, g.groups.data(), gb);
-    if (tb) std::memcpy(h + toff, g.terms.data(), tb);
-    hip_check(hipMemcpyAsync(dev, h, toff + tb, hipMemcpyHostToDevice, ctx->stream), "hipMemcpyAsync");
+    if (!g.passes.empty()) std::memcpy(h, g.passes.data(), g.passes.size() * sizeof(DevPass));
+    if (!g.groups.empty()) std::memcpy(h + L.groups, g.groups.data(), g.groups.size() * sizeof(DevGroup));
+    if (!g.terms.empty()) std::memcpy(h + L.terms, g.terms.data(), g.terms.size() * sizeof(DevTerm));
+    hip_check(hipMemcpyAsync(dev, h, L.end, hipMemcpyHostToDevice, ctx->stream), "hipMemcpyAsync");
     if (!ctx->pinned_ready) hip_check(hipEventCreateWithFlags(&ctx->pinned_ready, hipEventDisableTiming), "event");
     hip_check(hipEventRecord(ctx->pinned_ready, ctx->stream), "hipEventRecord");
-    dgroups = (DevGroup *)dev;
-    dterms = (DevTerm *)(dev + toff);
+    dpasses = g.passes.empty() ? nullptr : (DevPass *)dev;
+    dgroups = g.groups.empty() ? nullptr : (DevGroup *)(dev + L.groups);
+    dterms = g.terms.empty() ? nullptr : (DevTerm *)(dev + L.terms);
 }
 
 extern "C" {
@@ -389,6 +437,8 @@ static qsv_plan *make_plan(qsv_ctx *ctx, int n_qubits, const qsv_gate *gates, co
             P->d_circ_part = dev_upload(cpart);
             P->d_circ_theta = dev_upload(ctheta);
             P->d_circ_npar = dev_upload(cnpar);
+            P->d_circ_pool_delta = dev_upload(P->circ_pool_delta);
+            P->d_circ_slot_delta = dev_upload(P->circ_slot_delta);
         }
     }
     return guard.release();
@@ -612,6 +662,8 @@ qsv_status qsv_plan_destroy(qsv_plan *plan)
         dev_free(plan->d_circ_part);
         dev_free(plan->d_circ_theta);
         dev_free(plan->d_circ_npar);
+        dev_free(plan->d_circ_pool_delta);
+        dev_free(plan->d_circ_slot_delta);
         for (void *m : plan->spec_modules) (void)hipModuleUnload((hipModule_t)m);
         delete plan;
     });
@@ -817,17 +869,17 @@ qsv_status qsv_expect(qsv_ctx *ctx, const qsv_pauli_term *H, int32_t n_terms, in
         if (!ctx || !psi_dev || !out_dev) fail(QSV_E_ARG, "null argument");
         if (n_qubits < 1 || n_qubits > MAX_DEVICE_QUBITS) fail(QSV_E_ARG, "n_qubits must be in [1, 35]");
         if (batch < 1) fail(QSV_E_ARG, "batch must be >= 1");
-        HostGroups g = group_terms(H, n_terms, n_qubits);
+        HostGroups g = group_terms(H, n_terms, n_qubits, true);
         hip_check(hipSetDevice(ctx->device), "hipSetDevice");
-        const int n_blocks = 4096;  // cap on the blocks per (batch entry, group)
-        size_t need = sizeof(double) * (size_t)expect_blocks(n_qubits, n_blocks) *
-                      std::max<size_t>(1, g.groups.size()) * (size_t)batch;
+        size_t need = sizeof(double) * (size_t)expect_blocks(n_qubits) * std::max<size_t>(1, g.passes.size()) *
+                      (size_t)batch;
         double *partials = (double *)ctx->ensure(ctx->scratch, ctx->scratch_bytes, need);
+        DevPass *dp = nullptr;
         DevGroup *dg = nullptr;
         DevTerm *dt = nullptr;
-        if (!g.groups.empty()) upload_groups(ctx, g, dg, dt);
-        hip_check(launch_expect(dg, (int)g.groups.size(), dt, n_qubits, batch, (const float2 *)psi_dev, partials,
-                                n_blocks, out_dev, ctx->stream),
+        if (!g.groups.empty()) upload_groups(ctx, g, dp, dg, dt);
+        hip_check(launch_expect(dp, (int)g.passes.size(), dg, dt, n_qubits, batch, (const float2 *)psi_dev, partials,
+                                out_dev, ctx->stream),
                   "expect launch");
     });
 }
@@ -839,55 +891,34 @@ qsv_status qsv_expect_noalloc(qsv_ctx *ctx, const qsv_pauli_term *H, int32_t n_t
         if (!ctx || !psi_dev || !out_dev) fail(QSV_E_ARG, "null argument");
         if (n_qubits < 1 || n_qubits > MAX_DEVICE_QUBITS) fail(QSV_E_ARG, "n_qubits must be in [1, 35]");
         if (batch < 1) fail(QSV_E_ARG, "batch must be >= 1");
-        if (n_terms < 0 || (n_terms > 0 && !H)) fail(QSV_E_ARG, "null or negative Pauli sum");
+        check_terms(H, n_terms, n_qubits);
         if (n_terms > NOALLOC_MAX_TERMS) fail(QSV_E_RANGE, "qsv_expect_noalloc takes at most 4096 Pauli terms");
-        const uint64_t full = n_qubits >= 64 ? ~0ull : ((1ull << n_qubits) - 1);
-        for (int t = 0; t < n_terms; ++t)
-            if ((H[t].x_mask & ~full) || (H[t].z_mask & ~full)) fail(QSV_E_ARG, "Pauli mask beyond n_qubits");
-        // the grouping of qsv_expect (groups by increasing X mask, terms in input
-        // order inside a group) without containers: an in-place sort of indices
-        int idx[NOALLOC_MAX_TERMS];
-        for (int t = 0; t < n_terms; ++t) idx[t] = t;
-        std::sort(idx, idx + n_terms, [&](int a, int b) {
-            return H[a].x_mask != H[b].x_mask ? H[a].x_mask < H[b].x_mask : a < b;
-        });
-        int n_groups = 0;
-        for (int i = 0; i < n_terms; ++i)
-            if (i == 0 || H[idx[i]].x_mask != H[idx[i - 1]].x_mask) ++n_groups;
-        const int n_blocks = 4096;  // the cap qsv_expect uses
-        const size_t partials = sizeof(double) * (size_t)expect_blocks(n_qubits, n_blocks) *
-                                (size_t)std::max(1, n_groups) * (size_t)batch;
-        if (partials > NOALLOC_SCRATCH_BYTES - NOALLOC_TERMS_BYTES)
-            fail(QSV_E_RANGE, "qsv_expect_noalloc: " + std::to_string(partials) + " bytes of partial sums exceed its " +
-                                  std::to_string(NOALLOC_SCRATCH_BYTES - NOALLOC_TERMS_BYTES) + "-byte scratch");
         hip_check(hipSetDevice(ctx->device), "hipSetDevice");
         char *dev = (char *)noalloc_scratch(ctx->device);
         if (!dev) fail(QSV_E_STATE, "static scratch not set up on this device");
-        const size_t gb = (size_t)n_groups * sizeof(DevGroup), toff = (gb + 15) & ~size_t(15);
-        const size_t bytes = toff + (size_t)n_terms * sizeof(DevTerm);
+        // the staging buffer is free again once the previous call's copy has run;
+        // the grouping of qsv_expect is written straight into it (groups and terms
+        // at the offsets of a layout sized for n_terms passes, then the passes)
+        hip_check(hipEventSynchronize(ctx->na_staging_ready), "hipEventSynchronize");
+        const TermLayout L0 = term_layout((size_t)n_terms, (size_t)n_terms, (size_t)n_terms);
+        char *h = (char *)ctx->na_staging;
+        int idx[NOALLOC_MAX_TERMS];
+        const int n_groups = group_into(H, n_terms, idx, (DevGroup *)(h + L0.groups), (DevTerm *)(h + L0.terms));
+        const int n_passes = plan_expect_passes(n_qubits, (DevGroup *)(h + L0.groups), n_groups,
+                                                (DevTerm *)(h + L0.terms), (DevPass *)h);
+        const size_t partials = sizeof(double) * (size_t)expect_blocks(n_qubits) * (size_t)std::max(1, n_passes) *
+                                (size_t)batch;
+        if (partials > NOALLOC_SCRATCH_BYTES - NOALLOC_TERMS_BYTES)
+            fail(QSV_E_RANGE, "qsv_expect_noalloc: " + std::to_string(partials) + " bytes of partial sums exceed its " +
+                                  std::to_string(NOALLOC_SCRATCH_BYTES - NOALLOC_TERMS_BYTES) + "-byte scratch");
         if (n_terms > 0) {
-            // the staging buffer is free again once the previous call's copy has run
-            hip_check(hipEventSynchronize(ctx->na_staging_ready), "hipEventSynchronize");
-            DevGroup *hg = (DevGroup *)ctx->na_staging;
-            DevTerm *ht = (DevTerm *)((char *)ctx->na_staging + toff);
-            int g = -1;
-            for (int i = 0; i < n_terms; ++i) {
-                const qsv_pauli_term &h = H[idx[i]];
-                if (g < 0 || h.x_mask != hg[g].x_mask) {
-                    ++g;
-                    hg[g].x_mask = h.x_mask;
-                    hg[g].term_begin = i;
-                }
-                hg[g].term_end = i + 1;
-                ht[i] = dev_term(h);
-            }
-            hip_check(hipMemcpyAsync(dev, ctx->na_staging, bytes, hipMemcpyHostToDevice, ctx->stream), "hipMemcpyAsync");
+            hip_check(hipMemcpyAsync(dev, h, L0.end, hipMemcpyHostToDevice, ctx->stream), "hipMemcpyAsync");
             hip_check(hipEventRecord(ctx->na_staging_ready, ctx->stream), "hipEventRecord");
         }
-        hip_check(launch_expect(n_groups ? (const DevGroup *)dev : nullptr, n_groups,
-                                n_groups ? (const DevTerm *)(dev + toff) : nullptr, n_qubits, batch,
-                                (const float2 *)psi_dev, (double *)(dev + NOALLOC_TERMS_BYTES), n_blocks, out_dev,
-                                ctx->stream),
+        hip_check(launch_expect(n_passes ? (const DevPass *)dev : nullptr, n_passes,
+                                n_groups ? (const DevGroup *)(dev + L0.groups) : nullptr,
+                                n_groups ? (const DevTerm *)(dev + L0.terms) : nullptr, n_qubits, batch,
+                                (const float2 *)psi_dev, (double *)(dev + NOALLOC_TERMS_BYTES), out_dev, ctx->stream),
                   "expect launch");
     });
 }
@@ -901,7 +932,8 @@ qsv_status qsv_adjoint_grad(qsv_ctx *ctx, const qsv_plan *plan, const qsv_pauli_
         if (!energy_dev) fail(QSV_E_ARG, "energy is null");
         if (plan->n_params > 0 && (!theta_dev || !grad_dev)) fail(QSV_E_ARG, "theta or grad is null");
         if (plan->device != ctx->device) fail(QSV_E_STATE, "plan has no device tables on this context's device");
-        HostGroups g = group_terms(H, n_terms, plan->n);
+        HostGroups g = group_terms(H, n_terms, plan->n, false);
+        DevPass *dp_unused = nullptr;
         hip_check(hipSetDevice(ctx->device), "hipSetDevice");
         if (plan->n_circuits > 1) {
             const int64_t n_slots = (int64_t)plan->grad_param.size();
@@ -909,7 +941,7 @@ qsv_status qsv_adjoint_grad(qsv_ctx *ctx, const qsv_plan *plan, const qsv_pauli_
             double *gpart = (double *)ctx->ensure(ctx->scratch, ctx->scratch_bytes, need);
             DevGroup *dg = nullptr;
             DevTerm *dt = nullptr;
-            if (!g.groups.empty()) upload_groups(ctx, g, dg, dt);
+            if (!g.groups.empty()) upload_groups(ctx, g, dp_unused, dg, dt);
             hip_check(launch_batched(*plan, dg, (int)g.groups.size(), dt, theta_dev, nullptr, (const float2 *)psi_final_dev,
                                      energy_dev, grad_dev, gpart, ctx->ensure_queue(), true,
                                      ctx->grid_batched(plan->n_circuits), ctx->stream),
@@ -939,7 +971,7 @@ qsv_status qsv_adjoint_grad(qsv_ctx *ctx, const qsv_plan *plan, const qsv_pauli_
         double *slot_sum = (double *)(scr + sl_off);
         DevGroup *dg = nullptr;
         DevTerm *dt = nullptr;
-        if (!g.groups.empty()) upload_groups(ctx, g, dg, dt);
+        if (!g.groups.empty()) upload_groups(ctx, g, dp_unused, dg, dt);
         hip_check(launch_materialize(*plan, theta_dev, ctx->stream), "materialize");
         hip_check(launch_apply_h(dg, (int)g.groups.size(), dt, n, (const float2 *)psi_final_dev, lam, partials,
                                  n_blocks, energy_dev, ctx->stream),

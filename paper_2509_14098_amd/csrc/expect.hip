@@ -3,8 +3,15 @@
 // A Pauli string P with X/Y mask xm and Z/Y mask zm maps |x> to
 // i^{#Y} (-1)^{|x & zm|} |x ^ xm>, so
 //   <psi|P|psi> = sum_x conj(psi_{x^xm}) psi_x i^{#Y} (-1)^{|x & zm|}.
-// Terms are grouped by xm; a group with xm != 0 is summed over pairs
-// (x, x^xm), each amplitude read once per group.  Products are formed and
+// Terms are grouped by xm.  The groups, in increasing xm order, are cut into
+// passes over the state: a pass has a set S of at most 12 tile qubits (qubits
+// 0-3, for 128-byte runs, the X masks of its groups, then the lowest free
+// qubits) and handles every group whose mask lies in S.  A workgroup reads a
+// tile, the 2^|S| amplitudes with the other qubits fixed, into LDS, where the
+// partner x ^ xm of each amplitude x then is; one pass reads the state once
+// for all its groups.  (On the 20-qubit ansatz's H = sum Z_i Z_i+1 + sum X_i
+// the 21 groups take two passes.)  A group whose mask does not fit a tile
+// with the low qubits reads its partners from HBM.  Products are formed and
 // accumulated in float64; block sums go to a partials array and a second
 // kernel adds them in a fixed order, so results do not depend on timing.
 #include <hip/hip_runtime.h>
@@ -34,104 +41,152 @@ __device__ __forceinline__ double block_sum(double v, double *sh)
 
 __device__ __forceinline__ double parity_sign(uint64_t v) { return (__popcll(v) & 1) ? -1.0 : 1.0; }
 
-// partials[(b * n_groups + g) * gridDim.x + block] for the groups g = g0 + blockIdx.y
-__global__ __launch_bounds__(RED_THREADS) void expect_kernel(const DevGroup *__restrict__ groups, int g0,
-                                                              int n_groups, const DevTerm *__restrict__ terms, int n,
+// One launch covers every pass: workgroup (x, pass, b) walks tiles x, x +
+// gridDim.x, ... of state b with the pass's tile qubits.  A thread holds 8
+// amplitude pairs of the tile (positions 2 tid + j + 512 it, j < 2, it < 8),
+// read as 16-byte pairs (qubit 0 is always a tile qubit).  Partner amplitudes
+// of the pass's X/Y groups come from the LDS copy of the tile, those of wide
+// groups (masks that do not fit a tile with the low qubits) from HBM.
+// partials[(b * n_passes + pass) * gridDim.x + block]
+__global__ __launch_bounds__(RED_THREADS) void expect_kernel(const DevPass *__restrict__ passes, int p0,
+                                                              int n_passes, const DevGroup *__restrict__ groups,
+                                                              const DevTerm *__restrict__ terms, int n,
                                                               const float2 *__restrict__ psi,
                                                               double *__restrict__ partials)
 {
+    typedef float nf4 __attribute__((ext_vector_type(4)));  // a vector type the builtin accepts
+    __shared__ float4 lds4[(1 << EXPECT_TILE_QUBITS) / 2];
     __shared__ double sh[RED_THREADS];
-    const int gi = g0 + (int)blockIdx.y;
+    const float2 *lds = reinterpret_cast<const float2 *>(lds4);
+    const int pi = p0 + (int)blockIdx.y;
+    const DevPass PS = passes[pi];
     const int64_t b = blockIdx.z;
-    const DevGroup G = groups[gi];
     const float2 *__restrict__ s = psi + ((uint64_t)b << n);
-    const uint64_t stride = (uint64_t)gridDim.x * RED_THREADS;
+    const uint32_t tid = threadIdx.x;
+    const int t = n < EXPECT_TILE_QUBITS ? n : EXPECT_TILE_QUBITS;
+    const uint32_t tdim = 1u << t;
+    // the qubit (as a one-bit mask) at each tile position, in increasing order
+    uint64_t posbit[EXPECT_TILE_QUBITS];
+    {
+        uint64_t m = PS.tile_mask;
+#pragma unroll
+        for (int c = 0; c < EXPECT_TILE_QUBITS; ++c) {
+            posbit[c] = m & (~m + 1);
+            m &= m - 1;
+        }
+    }
+    uint64_t xthr = 0;  // positions 2 tid: tile positions 1..8
+#pragma unroll
+    for (int c = 1; c <= 8; ++c)
+        if ((tid >> (c - 1)) & 1u) xthr |= posbit[c];
+    uint64_t row[EXPECT_PAIRS];  // positions 512 it: tile positions 9..11
+#pragma unroll
+    for (int it = 0; it < EXPECT_PAIRS; ++it) {
+        uint64_t r = 0;
+#pragma unroll
+        for (int c = 9; c < EXPECT_TILE_QUBITS; ++c)
+            if ((it >> (c - 9)) & 1) r |= posbit[c];
+        row[it] = r;
+    }
+    const uint64_t full = (1ull << n) - 1;
+    const uint64_t outside = full & ~PS.tile_mask;
+    const uint64_t n_tiles = 1ull << (n - t);
     double acc = 0.0;
-    if (G.x_mask == 0) {
-        // diagonal group: amplitudes read as 16-byte pairs, eight pairs in flight per
-        // thread, with non-temporal loads (the state is read once)
-        auto weight = [&](uint64_t x) __attribute__((always_inline)) {
-            double w = 0.0;
-            for (int t = G.term_begin; t < G.term_end; ++t) w += terms[t].cre * parity_sign(x & terms[t].z_mask);
-            return w;
-        };
-        auto pair = [&](uint64_t i, float4 v) __attribute__((always_inline)) {
-            const double p0 = (double)v.x * v.x + (double)v.y * v.y, p1 = (double)v.z * v.z + (double)v.w * v.w;
-            return p0 * weight(2 * i) + p1 * weight(2 * i + 1);
-        };
-        if (n == 1) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) acc = pair(0, *reinterpret_cast<const float4 *>(s));
-        } else {
-            const uint64_t n2 = 1ull << (n - 1);
-            const float4 *__restrict__ s4 = reinterpret_cast<const float4 *>(s);
-            uint64_t i = (uint64_t)blockIdx.x * RED_THREADS + threadIdx.x;
-            for (; i + 7 * stride < n2; i += 8 * stride) {
-                typedef float nf4 __attribute__((ext_vector_type(4)));  // a vector type the builtin accepts
-                const nf4 *__restrict__ n4 = reinterpret_cast<const nf4 *>(s4);
-                nf4 v[8];
+    for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        // the tile index's bits on the qubits outside the tile, in increasing order
+        uint64_t base = 0, tl = tile;
+        for (uint64_t f = outside; f && tl; f &= f - 1, tl >>= 1)
+            if (tl & 1) base |= f & (~f + 1);
+        float4 v[EXPECT_PAIRS];
+        uint64_t x[EXPECT_PAIRS];  // index of the pair's first amplitude (qubit 0 clear)
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] = __builtin_nontemporal_load(n4 + i + u * stride);
-                // the 16 weights with the term loop outside: 16 independent float64
-                // sums per term (one chain per amplitude would leave the lanes
-                // waiting on each add); each weight still adds its terms in order
-                double w[16];
+        for (int it = 0; it < EXPECT_PAIRS; ++it) {
+            x[it] = base | xthr | row[it];
+            v[it] = float4{0.f, 0.f, 0.f, 0.f};
+            if (2 * tid + 512u * it < tdim) {
+                const nf4 w = __builtin_nontemporal_load(reinterpret_cast<const nf4 *>(s + x[it]));
+                v[it] = float4{w.x, w.y, w.z, w.w};
+            }
+        }
+        if (PS.has_x) {
+            __syncthreads();  // the previous tile's partner reads are done
 #pragma unroll
-                for (int u = 0; u < 16; ++u) w[u] = 0.0;
-                for (int t = G.term_begin; t < G.term_end; ++t) {
-                    const double c = terms[t].cre;
-                    const uint64_t zm = terms[t].z_mask;
+            for (int it = 0; it < EXPECT_PAIRS; ++it)
+                if (2 * tid + 512u * it < tdim) lds4[tid + 256 * it] = v[it];
+            __syncthreads();
+        }
+        for (int g = PS.g_begin; g < PS.g_end; ++g) {
+            const DevGroup G = groups[g];
+            if (G.x_mask == 0) {
+                // diagonal group: the 16 weights with the term loop outside (16
+                // independent float64 sums); each weight adds its terms in order
+                double w[2 * EXPECT_PAIRS];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const uint64_t x = 2 * (i + u * stride);
-                        w[2 * u] += c * parity_sign(x & zm);
-                        w[2 * u + 1] += c * parity_sign((x + 1) & zm);
+                for (int u = 0; u < 2 * EXPECT_PAIRS; ++u) w[u] = 0.0;
+                for (int k = G.term_begin; k < G.term_end; ++k) {
+                    const double c = terms[k].cre;
+                    const uint64_t zm = terms[k].z_mask;
+#pragma unroll
+                    for (int it = 0; it < EXPECT_PAIRS; ++it) {
+                        w[2 * it] += c * parity_sign(x[it] & zm);
+                        w[2 * it + 1] += c * parity_sign((x[it] | 1ull) & zm);
                     }
                 }
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const double p0 = (double)v[u].x * v[u].x + (double)v[u].y * v[u].y;
-                    const double p1 = (double)v[u].z * v[u].z + (double)v[u].w * v[u].w;
-                    acc += p0 * w[2 * u] + p1 * w[2 * u + 1];
+                for (int it = 0; it < EXPECT_PAIRS; ++it) {
+                    const double p0v = (double)v[it].x * v[it].x + (double)v[it].y * v[it].y;
+                    const double p1v = (double)v[it].z * v[it].z + (double)v[it].w * v[it].w;
+                    acc += p0v * w[2 * it] + p1v * w[2 * it + 1];
+                }
+            } else if (G.xt >= 0) {
+                // partners in the LDS tile: the pairs (p0, p1 = p0 ^ xt) of tile
+                // positions with bit lb of p0 clear, k = tid + 256 i enumerating
+                // them; per term, with z = conj(psi_p1) psi_p0 and signs from
+                // the term's Z mask on the tile (zt) and outside it (base):
+                //   s0 Re[c z] + s1 Re[c conj(z)]
+                const uint32_t xt = (uint32_t)G.xt;
+                const int lb = __builtin_ctz(xt);
+                const uint32_t below = (1u << lb) - 1;
+#pragma unroll
+                for (int i = 0; i < EXPECT_PAIRS; ++i) {
+                    const uint32_t k = tid + 256u * i;
+                    if (k >= (tdim >> 1)) continue;
+                    const uint32_t p0 = ((k >> lb) << (lb + 1)) | (k & below);
+                    const float2 a = lds[p0], c = lds[p0 ^ xt];
+                    const double zr = (double)c.x * a.x + (double)c.y * a.y;
+                    const double zi = (double)c.x * a.y - (double)c.y * a.x;
+                    for (int q = G.term_begin; q < G.term_end; ++q) {
+                        const DevTerm T = terms[q];
+                        const uint32_t s0 = (__popc(p0 & T.zt) + __popcll(base & T.z_mask)) & 1u;
+                        const uint32_t s1 = s0 ^ (__popc(xt & T.zt) & 1u);
+                        const double re = T.cre * zr - T.cim * zi, rc = T.cre * zr + T.cim * zi;
+                        acc += (s0 ? -re : re) + (s1 ? -rc : rc);
+                    }
+                }
+            } else {
+                // a wide group: partners from HBM, every amplitude x of the tile
+                //   sum_t Re[c_t (-1)^{|x & z_t|} conj(psi_{x ^ m}) psi_x]
+#pragma unroll
+                for (int it = 0; it < EXPECT_PAIRS; ++it) {
+                    if (2 * tid + 512u * it >= tdim) continue;
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        const float2 a = j ? float2{v[it].z, v[it].w} : float2{v[it].x, v[it].y};
+                        const uint64_t xj = x[it] | (uint64_t)j;
+                        const float2 c = s[xj ^ G.x_mask];
+                        const double zr = (double)c.x * a.x + (double)c.y * a.y;
+                        const double zi = (double)c.x * a.y - (double)c.y * a.x;
+                        for (int q = G.term_begin; q < G.term_end; ++q) {
+                            const DevTerm T = terms[q];
+                            acc += parity_sign(xj & T.z_mask) * (T.cre * zr - T.cim * zi);
+                        }
+                    }
                 }
             }
-            for (; i < n2; i += stride) acc += pair(i, s4[i]);
-        }
-    } else {
-        const int lb = __builtin_ctzll(G.x_mask);
-        const uint64_t low = 1ull << lb;
-        const uint64_t half = 1ull << (n - 1);
-        auto term_sum = [&](uint64_t x, float2 a, float2 c) __attribute__((always_inline)) {
-            const uint64_t y = x ^ G.x_mask;
-            // z = conj(psi_y) psi_x
-            const double zr = (double)c.x * a.x + (double)c.y * a.y;
-            const double zi = (double)c.x * a.y - (double)c.y * a.x;
-            for (int t = G.term_begin; t < G.term_end; ++t) {
-                const DevTerm T = terms[t];
-                const double sx = parity_sign(x & T.z_mask), sy = parity_sign(y & T.z_mask);
-                acc += sx * (T.cre * zr - T.cim * zi) + sy * (T.cre * zr + T.cim * zi);
-            }
-        };
-        auto first = [&](uint64_t k) __attribute__((always_inline)) { return ((k >> lb) << (lb + 1)) | (k & (low - 1)); };
-        uint64_t k = (uint64_t)blockIdx.x * RED_THREADS + threadIdx.x;
-        // four pairs' loads in flight per thread, then their sums in the order of the plain loop
-        for (; k + 3 * stride < half; k += 4 * stride) {
-            float2 a[4], c[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const uint64_t x = first(k + u * stride);
-                a[u] = s[x];
-                c[u] = s[x ^ G.x_mask];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) term_sum(first(k + u * stride), a[u], c[u]);
-        }
-        for (; k < half; k += stride) {
-            const uint64_t x = first(k);
-            term_sum(x, s[x], s[x ^ G.x_mask]);
         }
     }
     const double tot = block_sum(acc, sh);
-    if (threadIdx.x == 0) partials[((uint64_t)b * n_groups + gi) * gridDim.x + blockIdx.x] = tot;
+    if (threadIdx.x == 0) partials[((uint64_t)b * n_passes + pi) * gridDim.x + blockIdx.x] = tot;
 }
 
 // out[b] = sum of per_batch partials, fixed order
@@ -194,13 +249,132 @@ __global__ __launch_bounds__(RED_THREADS) void apply_h_kernel(const DevGroup *__
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
-static int blocks_for(uint64_t work, int cap)
+int expect_blocks(int n)
 {
-    uint64_t b = (work + RED_THREADS * 16 - 1) / (RED_THREADS * 16);
-    return (int)std::max<uint64_t>(1, std::min<uint64_t>(b, (uint64_t)cap));
+    const int t = std::min(n, EXPECT_TILE_QUBITS);
+    return (int)std::min<uint64_t>(1ull << (n - t), EXPECT_MAX_BLOCKS);
 }
 
-int expect_blocks(int n, int cap) { return blocks_for(1ull << n, cap); }
+int plan_expect_passes(int n, DevGroup *groups, int n_groups, DevTerm *terms, DevPass *passes)
+{
+    const int t = std::min(n, EXPECT_TILE_QUBITS);
+    const uint64_t low = (1ull << std::min(n, 4)) - 1;  // qubits 0-3: 128-byte runs of the state
+    auto compress = [&](uint64_t S, uint64_t m) {     // m on the tile positions of S
+        uint32_t r = 0;
+        for (int q = 0, c = 0; q < n; ++q)
+            if ((S >> q) & 1) {
+                if ((m >> q) & 1) r |= 1u << c;
+                ++c;
+            }
+        return r;
+    };
+    int np = 0, begin = 0;
+    uint64_t S = 0;
+    auto close = [&](int end) {
+        for (int q = 0; q < n && __builtin_popcountll(S) < t; ++q) S |= 1ull << q;
+        DevPass &P = passes[np++];
+        P.tile_mask = S;
+        P.g_begin = begin;
+        P.g_end = end;
+        P.has_x = 0;
+        P.pad = 0;
+        for (int g = begin; g < end; ++g) {
+            DevGroup &G = groups[g];
+            G.pad = 0;
+            for (int k = G.term_begin; k < G.term_end; ++k) {
+                terms[k].zt = G.xt < 0 ? 0u : compress(S, terms[k].z_mask);
+                terms[k].pad = 0;
+            }
+            if (G.xt < 0) continue;  // wide: partners from HBM
+            G.xt = (int32_t)compress(S, G.x_mask);
+        }
+    };
+    for (int g = 0; g < n_groups; ++g) {
+        const uint64_t xm = groups[g].x_mask;
+        const bool wide = __builtin_popcountll(low | xm) > t;
+        groups[g].xt = wide ? -1 : 0;
+        const uint64_t need = wide ? low : (low | xm);
+        if (g > begin && __builtin_popcountll(S | need) > t) {
+            close(g);
+            begin = g;
+            S = 0;
+        }
+        S |= need;
+    }
+    if (n_groups > 0) close(n_groups);
+    // few tiles (small states): split passes by their groups, so that the
+    // launch has EXPECT_MIN_BLOCKS workgroups; in place, last pass first (the
+    // parts of pass p land at indices >= p)
+    const int64_t blocks = (int64_t)expect_blocks(n) * np;
+    if (np > 0 && blocks < EXPECT_MIN_BLOCKS) {
+        const int want = (int)((EXPECT_MIN_BLOCKS + blocks - 1) / blocks);
+        int total = 0;
+        for (int p = 0; p < np; ++p) total += std::min(want, passes[p].g_end - passes[p].g_begin);
+        int out = total;
+        for (int p = np - 1; p >= 0; --p) {
+            const DevPass P = passes[p];
+            const int ng = P.g_end - P.g_begin, c = std::min(want, ng);
+            out -= c;
+            for (int i = 0; i < c; ++i) {
+                DevPass &Q = passes[out + i];
+                Q = P;
+                Q.g_begin = P.g_begin + (int)((int64_t)ng * i / c);
+                Q.g_end = P.g_begin + (int)((int64_t)ng * (i + 1) / c);
+            }
+        }
+        np = total;
+    }
+    for (int p = 0; p < np; ++p) {
+        passes[p].has_x = 0;
+        for (int g = passes[p].g_begin; g < passes[p].g_end; ++g)
+            if (groups[g].x_mask && groups[g].xt >= 0) passes[p].has_x = 1;
+    }
+    return np;
+}
+
+hipError_t launch_expect(const DevPass *passes, int n_passes, const DevGroup *groups, const DevTerm *terms, int n,
+                         int64_t batch, const float2 *psi, double *partials, double *out, hipStream_t s)
+{
+    if (n_passes == 0) {  // empty sum: zeros
+        hipLaunchKernelGGL(final_sum_kernel, dim3((uint32_t)batch), dim3(RED_THREADS), 0, s, partials, 0, out);
+        return hipGetLastError();
+    }
+    const int nb = expect_blocks(n);
+    const int64_t lim = 65535;  // grid y and z limits: passes and batches beyond them go in chunks
+    for (int64_t b0 = 0; b0 < batch; b0 += lim) {
+        const int64_t nz = std::min<int64_t>(lim, batch - b0);
+        for (int p0 = 0; p0 < n_passes; p0 += (int)lim) {
+            const int ny = (int)std::min<int64_t>(lim, n_passes - p0);
+            hipLaunchKernelGGL(expect_kernel, dim3(nb, ny, (uint32_t)nz), dim3(RED_THREADS), 0, s, passes, p0,
+                               n_passes, groups, terms, n, psi + ((uint64_t)b0 << n),
+                               partials + (uint64_t)b0 * n_passes * nb);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+    }
+    hipLaunchKernelGGL(final_sum_kernel, dim3((uint32_t)batch), dim3(RED_THREADS), 0, s, partials, nb * n_passes, out);
+    return hipGetLastError();
+}
+
+int apply_h_blocks(int n, int cap)
+{
+    // one amplitude per thread: each amplitude walks every Pauli group with a
+    // dependent table load and gather, so many waves are needed to cover them
+    const uint64_t b = std::max<uint64_t>(1, (1ull << n) / RED_THREADS);
+    return (int)std::min<uint64_t>(b, (uint64_t)std::max(cap, 1));
+}
+
+hipError_t launch_apply_h(const DevGroup *groups, int n_groups, const DevTerm *terms, int n, const float2 *psi,
+                          float2 *lam, double *partials, int n_blocks, double *energy, hipStream_t s)
+{
+    const int nb = apply_h_blocks(n, n_blocks);
+    hipLaunchKernelGGL(apply_h_kernel, dim3(nb), dim3(RED_THREADS), 0, s, groups, n_groups, terms, n, psi, lam,
+                       partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(RED_THREADS), 0, s, partials, nb, energy);
+    return hipGetLastError();
+}
 
 // Scratch of qsv_expect_noalloc: one fixed array per device, in the code
 // object's own device memory, so the entry point never allocates.  Host code
@@ -233,49 +407,6 @@ void *noalloc_scratch(int device)
     if (device < 0 || device >= NOALLOC_MAX_DEVICES) return nullptr;
     std::lock_guard<std::mutex> lock(g_scratch_mutex);
     return g_scratch_dev[device];
-}
-
-hipError_t launch_expect(const DevGroup *groups, int n_groups, const DevTerm *terms, int n, int64_t batch,
-                         const float2 *psi, double *partials, int n_blocks, double *out, hipStream_t s)
-{
-    if (n_groups == 0) {  // empty sum: zeros
-        hipLaunchKernelGGL(final_sum_kernel, dim3((uint32_t)batch), dim3(RED_THREADS), 0, s, partials, 0, out);
-        return hipGetLastError();
-    }
-    const int nb = blocks_for(1ull << n, n_blocks);
-    const int64_t lim = 65535;  // grid y and z limits: groups and batches beyond them go in chunks
-    for (int64_t b0 = 0; b0 < batch; b0 += lim) {
-        const int64_t nz = std::min<int64_t>(lim, batch - b0);
-        for (int g0 = 0; g0 < n_groups; g0 += (int)lim) {
-            const int ny = (int)std::min<int64_t>(lim, n_groups - g0);
-            hipLaunchKernelGGL(expect_kernel, dim3(nb, ny, (uint32_t)nz), dim3(RED_THREADS), 0, s, groups, g0, n_groups,
-                               terms, n, psi + ((uint64_t)b0 << n), partials + (uint64_t)b0 * n_groups * nb);
-            hipError_t e = hipGetLastError();
-            if (e != hipSuccess) return e;
-        }
-    }
-    hipLaunchKernelGGL(final_sum_kernel, dim3((uint32_t)batch), dim3(RED_THREADS), 0, s, partials, nb * n_groups, out);
-    return hipGetLastError();
-}
-
-int apply_h_blocks(int n, int cap)
-{
-    // one amplitude per thread: each amplitude walks every Pauli group with a
-    // dependent table load and gather, so many waves are needed to cover them
-    const uint64_t b = std::max<uint64_t>(1, (1ull << n) / RED_THREADS);
-    return (int)std::min<uint64_t>(b, (uint64_t)std::max(cap, 1));
-}
-
-hipError_t launch_apply_h(const DevGroup *groups, int n_groups, const DevTerm *terms, int n, const float2 *psi,
-                          float2 *lam, double *partials, int n_blocks, double *energy, hipStream_t s)
-{
-    const int nb = apply_h_blocks(n, n_blocks);
-    hipLaunchKernelGGL(apply_h_kernel, dim3(nb), dim3(RED_THREADS), 0, s, groups, n_groups, terms, n, psi, lam,
-                       partials);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(RED_THREADS), 0, s, partials, nb, energy);
-    return hipGetLastError();
 }
 
 }  // namespace qsv

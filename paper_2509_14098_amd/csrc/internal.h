@@ -37,6 +37,7 @@ struct CircuitPlan {
     std::vector<Part> parts;          // level 1 (tile / LDS)
     std::vector<std::vector<Part>> stages;  // level 2 (registers), per partition
     int32_t part_begin = 0;           // index of its first DevPart
+    int32_t shares = -1;              // batched: the circuit whose tables this one reuses, or -1
 };
 
 // A run of the plan's gate list partitioned on its own at the tile level:
@@ -75,6 +76,8 @@ struct Plan {
     std::vector<int32_t> param_off, param_slots;  // theta index -> its grad slots (CSR, slot order)
     // batched plans: per-circuit stage ranges (single tile per circuit)
     std::vector<int32_t> batch_order; // circuits sorted by decreasing op count
+    std::vector<int32_t> circ_pool_delta;  // batched: pool offset of a circuit against the tables it uses
+    std::vector<int32_t> circ_slot_delta;  // batched: gradient slot offset likewise
     // distributed plans (n_global > 0): the circuit's level above the tile
     int n_global = 0;
     std::vector<Part> dist_parts;     // distributed partitions: local set (logical qubits) and logical gates
@@ -103,6 +106,8 @@ struct Plan {
     int32_t *d_circ_part = nullptr;    // batched: circuit -> its DevPart
     int64_t *d_circ_theta = nullptr;   // batched: theta offset per circuit
     int64_t *d_circ_npar = nullptr;    // batched: parameter count per circuit
+    int32_t *d_circ_pool_delta = nullptr;  // batched: per circuit
+    int32_t *d_circ_slot_delta = nullptr;  // batched: per circuit
 };
 
 // planner.cpp

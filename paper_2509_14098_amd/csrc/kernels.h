@@ -14,24 +14,45 @@ hipError_t launch_materialize(const Plan &plan, const double *theta, hipStream_t
 struct DevTerm {
     double cre, cim;      // coeff * i^{#Y}
     uint64_t z_mask;
+    uint32_t zt;          // expectation passes: the Z/Y mask on the pass's tile positions
+    int32_t pad;
 };
 struct DevGroup {
     uint64_t x_mask;
     int32_t term_begin, term_end;
+    int32_t xt;           // expectation passes: X mask in tile positions, -1 for partners read from HBM
+    int32_t pad;
+};
+// One pass of qsv_expect over the state: tile qubits and the groups it handles.
+struct DevPass {
+    uint64_t tile_mask;
+    int32_t g_begin, g_end;
+    int32_t has_x;        // a group needs partner amplitudes from the LDS tile
+    int32_t pad;
 };
 
 // expect.hip
-// Blocks per (batch entry, Pauli group) that launch_expect uses for 2^n amplitudes and a cap.
-int expect_blocks(int n, int cap);
-hipError_t launch_expect(const DevGroup *groups, int n_groups, const DevTerm *terms, int n, int64_t batch,
-                         const float2 *psi, double *partials, int n_blocks, double *out, hipStream_t s);
+constexpr int EXPECT_TILE_QUBITS = 12;   // tiles of 4096 amplitudes, 32 KiB of LDS
+constexpr int EXPECT_PAIRS = 8;         // amplitude pairs per thread (256 threads)
+constexpr int EXPECT_MAX_BLOCKS = 1024; // workgroups per (pass, batch entry)
+constexpr int EXPECT_MIN_BLOCKS = 2048; // passes are split by groups until they fill this many workgroups
+// Workgroups per (pass, batch entry): partial sums of launch_expect are
+// n_passes x expect_blocks(n) x batch doubles.
+int expect_blocks(int n);
+// Cuts groups (sorted by increasing X mask) into passes (at most n_groups),
+// sets each group's xt and each of its terms' zt; returns the number of
+// passes.  Allocates nothing.
+int plan_expect_passes(int n, DevGroup *groups, int n_groups, DevTerm *terms, DevPass *passes);
+hipError_t launch_expect(const DevPass *passes, int n_passes, const DevGroup *groups, const DevTerm *terms, int n,
+                         int64_t batch, const float2 *psi, double *partials, double *out, hipStream_t s);
 // The fixed scratch of qsv_expect_noalloc (one per device): the grouped
 // Pauli terms, then the per-block partial sums.
 constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(4) << 20;
-constexpr size_t NOALLOC_TERMS_BYTES = size_t(256) << 10;
-constexpr int NOALLOC_MAX_TERMS = 4096;   // 4096 x (DevTerm + DevGroup) fit NOALLOC_TERMS_BYTES
+constexpr size_t NOALLOC_TERMS_BYTES = size_t(512) << 10;
+constexpr int NOALLOC_MAX_TERMS = 4096;   // 4096 x (DevTerm + DevGroup + DevPass) fit NOALLOC_TERMS_BYTES
 constexpr int NOALLOC_MAX_DEVICES = 64;
-static_assert(NOALLOC_MAX_TERMS * (sizeof(DevTerm) + sizeof(DevGroup)) + 16 <= NOALLOC_TERMS_BYTES, "terms region");
+static_assert(NOALLOC_MAX_TERMS * (sizeof(DevTerm) + sizeof(DevGroup) + sizeof(DevPass)) + 32 <= NOALLOC_TERMS_BYTES,
+              "terms region");
 // Looks up the array's address on `device`, which must be the current device;
 // once per device (later calls return at once).
 hipError_t noalloc_scratch_init(int device);

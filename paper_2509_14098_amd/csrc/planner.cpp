@@ -15,6 +15,7 @@
 #include <functional>
 #include <set>
 #include <stdexcept>
+#include <unordered_map>
 
 #include "internal.h"
 
@@ -779,27 +780,102 @@ void build_plan(Plan &P)
     P.meta.resize(P.gates.size());
     for (size_t i = 0; i < P.gates.size(); ++i) P.meta[i] = classify(P.gates[i]);
 
-    // matrix pool entries, one per gate
+    // matrix pool entries, one per gate, laid out circuit by circuit: a
+    // circuit's gate matrices, then the entries its lowering adds (folded
+    // diagonals and layers), so that circuits of the same structure have the
+    // same pool layout at different bases
     std::vector<int32_t> mat_of(P.gates.size(), -1);
-    for (size_t i = 0; i < P.gates.size(); ++i) {
-        const GateMeta &m = P.meta[i];
-        if (m.op == OP_CX || m.op == OP_CZ || m.op == OP_SWAP) continue;
-        int len = m.op == OP_U2 ? 32 : 8;
-        mat_of[i] = (int32_t)P.pool.size();
-        if (m.op == OP_D2) {  // diagonal entries j = b(q0) + 2 b(q1)
-            for (int j = 0; j < 4; ++j) {
-                P.pool.push_back((float)m.m[2 * (j * 4 + j)]);
-                P.pool.push_back((float)m.m[2 * (j * 4 + j) + 1]);
+    auto add_matrices = [&](int64_t g0, int64_t g1) {
+        for (int64_t i = g0; i < g1; ++i) {
+            const GateMeta &m = P.meta[i];
+            if (m.op == OP_CX || m.op == OP_CZ || m.op == OP_SWAP) continue;
+            int len = m.op == OP_U2 ? 32 : 8;
+            mat_of[i] = (int32_t)P.pool.size();
+            if (m.op == OP_D2) {  // diagonal entries j = b(q0) + 2 b(q1)
+                for (int j = 0; j < 4; ++j) {
+                    P.pool.push_back((float)m.m[2 * (j * 4 + j)]);
+                    P.pool.push_back((float)m.m[2 * (j * 4 + j) + 1]);
+                }
+            } else {
+                for (int j = 0; j < len; ++j) P.pool.push_back((float)m.m[j]);
             }
-        } else {
-            for (int j = 0; j < len; ++j) P.pool.push_back((float)m.m[j]);
         }
-    }
+    };
 
     P.flops = 0;
     P.bytes = 0;
     const double dim = std::ldexp(1.0, n);
-    for (auto &C : P.circ) {
+    // batched plans: circuits whose gate records are identical (kinds, qubits,
+    // parameter indices relative to the circuit, fixed angles and matrices)
+    // share the partition, stage and op tables of the first of them; they
+    // differ only in their pool base (their own rotation matrices) and their
+    // gradient slots, both by a constant offset
+    const bool batched = P.circ.size() > 1;
+    std::unordered_map<uint64_t, std::vector<int>> by_hash;
+    struct Span { int32_t pool0 = 0, pool1 = 0, slot0 = 0, slot1 = 0; double flops = 0; };
+    std::vector<Span> span(P.circ.size());
+    P.circ_pool_delta.assign(P.circ.size(), 0);
+    P.circ_slot_delta.assign(P.circ.size(), 0);
+    for (size_t ci = 0; ci < P.circ.size(); ++ci) {
+        CircuitPlan &C = P.circ[ci];
+        int first = -1;
+        uint64_t key = 0;
+        if (batched) {
+            const unsigned char *b = reinterpret_cast<const unsigned char *>(P.gates.data() + C.g0);
+            const size_t len = (size_t)(C.g1 - C.g0) * sizeof(qsv_gate);
+            key = 1469598103934665603ull ^ len;  // FNV-1a over the gate records
+            for (size_t i = 0; i < len; ++i) key = (key ^ b[i]) * 1099511628211ull;
+            for (int e : by_hash[key]) {
+                const CircuitPlan &E = P.circ[e];
+                if (E.g1 - E.g0 == C.g1 - C.g0 &&
+                    std::memcmp(P.gates.data() + E.g0, P.gates.data() + C.g0, len) == 0) {
+                    first = e;
+                    break;
+                }
+            }
+        }
+        span[ci].pool0 = (int32_t)P.pool.size();
+        span[ci].slot0 = (int32_t)P.grad_param.size();
+        if (first >= 0) {  // reuse the tables of circuit `first`
+            const CircuitPlan &E = P.circ[first];
+            const Span &se = span[first];
+            const int64_t dg = C.g0 - E.g0;
+            for (int32_t i = se.pool0; i < se.pool1; ++i) P.pool.push_back(P.pool[i]);
+            for (int64_t g = C.g0; g < C.g1; ++g)
+                if (mat_of[g - dg] >= 0) mat_of[g] = mat_of[g - dg] - se.pool0 + span[ci].pool0;
+            for (int32_t sl = se.slot0; sl < se.slot1; ++sl)
+                P.grad_param.push_back((int32_t)(P.grad_param[sl] - E.theta_off + C.theta_off));
+            P.circ_pool_delta[ci] = span[ci].pool0 - se.pool0;
+            P.circ_slot_delta[ci] = span[ci].slot0 - se.slot0;
+            for (int64_t g = C.g0; g < C.g1; ++g) {
+                if (P.meta[g].param) {
+                    ParamGate pg;
+                    pg.mat = mat_of[g];
+                    pg.kind = P.gates[g].kind;
+                    pg.theta_index = (int32_t)(C.theta_off + P.gates[g].param);
+                    pg.pad = 0;
+                    P.pgates.push_back(pg);
+                }
+            }
+            C.parts = E.parts;
+            for (auto &pt : C.parts)
+                for (int &g : pt.gates) g += (int)dg;
+            C.stages = E.stages;
+            for (auto &st : C.stages)
+                for (auto &pt : st)
+                    for (int &g : pt.gates) g += (int)dg;
+            C.part_begin = E.part_begin;
+            C.shares = first;
+            span[ci].pool1 = (int32_t)P.pool.size();
+            span[ci].slot1 = (int32_t)P.grad_param.size();
+            span[ci].flops = se.flops;
+            P.flops += se.flops;
+            P.bytes += 16.0 * dim * (double)C.parts.size();
+            continue;
+        }
+        if (batched) by_hash[key].push_back((int)ci);
+        const double flops_c0 = P.flops;
+        add_matrices(C.g0, C.g1);
         for (int64_t g = C.g0; g < C.g1; ++g) {
             if (P.meta[g].param) {
                 ParamGate pg;
@@ -909,6 +985,9 @@ void build_plan(Plan &P)
             P.parts.push_back(dp);
             P.bytes += 16.0 * dim;
         }
+        span[ci].pool1 = (int32_t)P.pool.size();
+        span[ci].slot1 = (int32_t)P.grad_param.size();
+        span[ci].flops = P.flops - flops_c0;
     }
     // batched plans: longest circuits first in the work queue
     P.batch_order.resize(P.circ.size());

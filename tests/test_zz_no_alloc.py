@@ -80,10 +80,19 @@ def test_noalloc_expect_rejects_beyond_its_scratch(sim):
     with pytest.raises(Q.QsvError) as e:
         Q.qsv_expect_noalloc(sim.ctx, too_many, 20, 1, psi, out)
     assert "4096" in str(e.value)
-    # 2000 distinct X masks at 20 qubits: 2000 x 256 blocks of partial sums > 3840 KiB
-    masks = W.pauli_sum([(1.0, {q: "X" for q in range(20) if (m >> q) & 1}) for m in range(1, 2001)])
+    # 300 X strings on 8 distinct qubits above qubit 3 each: every one needs a
+    # 12-qubit tile pass of its own, so 300 passes x 256 blocks x batch 8 of
+    # float64 partial sums (4.9 MB) exceed the 3.5 MiB the scratch holds
+    rng = np.random.default_rng(9)
+    highs = set()
+    while len(highs) < 300:
+        highs.add(tuple(sorted(rng.choice(np.arange(4, 20), size=8, replace=False).tolist())))
+    wide = W.pauli_sum([(1.0, {int(q): "X" for q in h}) for h in sorted(highs)])
+    psi8 = torch.zeros((8, 1 << 20), dtype=torch.complex64, device="cuda")
+    out8 = torch.zeros(8, dtype=torch.float64, device="cuda")
     with pytest.raises(Q.QsvError) as e:
-        Q.qsv_expect_noalloc(sim.ctx, masks, 20, 1, psi, out)
+        Q.qsv_expect_noalloc(sim.ctx, wide, 20, 8, psi8, out8)
     assert "scratch" in str(e.value)
+    Q.qsv_expect_noalloc(sim.ctx, wide, 20, 1, psi8[0], out8[:1])  # 600 KiB: within the scratch
     torch.cuda.synchronize()
-    assert float(out[0]) == 0.0  # untouched on error
+    assert float(out8[0]) == 0.0 and float(out[0]) == 0.0
