@@ -348,6 +348,22 @@ def bench_batched(sim, args):
     dtf = timed(lambda: Q.qsv_apply(sim.ctx, plan.handle, theta, psi))
     dtg = timed(lambda: Q.qsv_adjoint_grad(sim.ctx, plan.handle, H, theta, psi, None, energy, grad))
     dt = timed(lambda: Q.qsv_adjoint_grad(sim.ctx, plan.handle, H, theta, None, None, energy, grad))
+    # load balance of one more launch of each kind: each workgroup's exit on the
+    # device clock, from the first workgroup's start
+    balance = {}
+    Q.qsv_set_timing(sim.ctx, True)
+    for kind, fn in (("forward", lambda: Q.qsv_apply(sim.ctx, plan.handle, theta, psi)),
+                     ("fwd_energy_grad", lambda: Q.qsv_adjoint_grad(sim.ctx, plan.handle, H, theta, None, None,
+                                                                    energy, grad))):
+        fn()
+        clk, hz = Q.qsv_last_batch_clock(sim.ctx)
+        if len(clk) and hz > 0:
+            start = clk[:, 0].astype(np.float64).min()
+            ends = (clk[:, 1].astype(np.float64) - start) / hz * 1e3
+            balance[kind] = dict(workgroups=int(len(clk)), last_exit_ms=round(float(ends.max()), 3),
+                                 mean_exit_ms=round(float(ends.mean()), 3), first_exit_ms=round(float(ends.min()), 3),
+                                 tail_frac=round(float((ends.max() - ends.mean()) / ends.max()), 4))
+    Q.qsv_set_timing(sim.ctx, False)
     info = plan.info
     plan.close()
     offs = np.concatenate([[0], np.cumsum([len(t) for t in thetas])])
@@ -356,7 +372,7 @@ def bench_batched(sim, args):
     checked = dict(energy=e_np[:n_check], grad=[g_np[offs[b]:offs[b + 1]] for b in range(n_check)])
     fwd_flops = algorithmic_flops(gates, n)  # every instance's gate list on its 2^n amplitudes
     return dict(_checked=checked, instances=B, n_qubits=n, gates=int(len(gates)), params=int(len(theta)),
-                forward_alg_tflops=round(fwd_flops / dtf / 1e12, 2),
+                load_balance=balance, forward_alg_tflops=round(fwd_flops / dtf / 1e12, 2),
                 forward_frac_of_fp32_peak=round(fwd_flops / dtf / 1e12 / FP32_VECTOR_PEAK, 4),
                 forward_ms=round(dtf * 1e3, 3), grad_ms=round(dtg * 1e3, 3), grad_over_forward=round(dtg / dtf, 3),
                 fwd_energy_grad_ms=round(dt * 1e3, 3), fwd_energy_grad_over_forward=round(dt / dtf, 3),
@@ -523,6 +539,40 @@ def oracle_single_core(args, gpu_bytes_per_apply, n_gates_total):
                 cores=1, threads=d["threads"], pinned_cpus=d["cpus"],
                 sample=f"first {d['gates']} of {n_gates_total} gates of the 28-qubit headline circuit on one core, "
                        f"{d['seconds']:.1f} s")
+
+
+def bench_one_shot(sim, args):
+    """End-to-end time of one apply + <H> starting from the gate list (plan,
+    then apply; state allocated beforehand) on the 28-qubit headline circuit and
+    the 32-qubit circuit at k = 10 and the default tile: table-driven, and with
+    the specialised kernels compiled in the background
+    (qsv_plan_specialise_async) while the apply runs, each partition switching
+    to its kernel once that is loaded.  The synchronous policy (tune, compile,
+    then apply) is the sum of the headline's and the C3 leg's own figures."""
+    res = {}
+    for name, n, gates, H in (("c2", 28, W.brickwork_c2(), W.z_on(0)), ("c3", 32, W.brickwork_c3(), W.zz_chain(32))):
+        psi = sim.zero_state(n)
+        out = torch.empty(1, dtype=torch.float64, device=sim.device)
+        r = {}
+        for policy in ("table_driven", "async_specialise"):
+            psi.zero_()
+            psi[0] = 1.0
+            sync()
+            t0 = time.perf_counter()
+            plan = sim.partition(n, gates, 10)  # the default tile, no tuning
+            if policy != "table_driven":
+                sim.specialise_async(plan)
+            sim.apply(plan, psi)
+            Q.qsv_expect(sim.ctx, H, n, 1, psi, out)
+            sync()
+            r[policy + "_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+            if policy != "table_driven":
+                r["specialised_by_the_end"] = bool(plan.refresh()["specialised"])
+            plan.close()  # joins a compile still running (outside the timed region)
+        res[name] = r
+        del psi
+        torch.cuda.empty_cache()
+    return res
 
 
 def bench_oracle(args, gpu_bytes_per_apply, n_gates_total, gpu_results):
@@ -692,6 +742,13 @@ def main():
     if not args.skip_c3:
         line["c3_autotuned"] = bench_c3(sim, args)
         line["planner"] = bench_planner(args)
+        one = bench_one_shot(sim, args)
+        c3 = line["c3_autotuned"]
+        one["c2"]["tune_and_specialise_ms"] = round(
+            (info["plan_seconds"] + (head.get("specialise_s") or 0)) * 1e3 + head["step_ms"], 1)
+        one["c3"]["tune_and_specialise_ms"] = round(
+            (c3["plan_and_tune_s"] + (c3["specialise_s"] or 0)) * 1e3 + c3["apply_expect_ms"], 1)
+        line["one_shot"] = one
     sim.close()
     if not args.skip_cpu:
         line["cpu_baseline"], errs = bench_oracle(args, info["bytes_per_apply"], info["n_gates"], line)

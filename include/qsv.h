@@ -159,8 +159,9 @@ qsv_status qsv_set_stream(qsv_ctx *ctx, void *hip_stream);
  * host-only plan usable with the introspection calls only).
  * k_local == 0 chooses k and the tile shape by timing candidates on the
  * device (autotuner, needs ctx; n_qubits above the default tile): k in
- * {8, 10, 12} below the tile size, six tile shapes (reg_qubits x
- * 2^log_threads: 5 x 256, 4 x 256, 4 x 512, 5 x 512, 4 x 1024, 3 x 256); each
+ * {8, 10, 12} below the tile size, eight tile shapes (reg_qubits x
+ * 2^log_threads: 5 x 256, 4 x 256, 4 x 512, 5 x 512, 4 x 1024, 3 x 256,
+ * 3 x 512, 3 x 1024); each
  * candidate's time is
  * an evenly spaced sample of at most 8 of its partition sweeps on a scratch
  * state (2^n x 8 bytes, freed afterwards) scaled to all partitions.  With
@@ -213,6 +214,27 @@ qsv_status qsv_plan_get_info(const qsv_plan *plan, qsv_plan_info *out);
  * compile or the load failed: qsv_last_error() holds the compiler log).
  */
 qsv_status qsv_plan_specialise(qsv_ctx *ctx, qsv_plan *plan, double *seconds_out);
+/*
+ * qsv_plan_specialise without waiting for the compile (for plans applied a
+ * few times only, where the compile would cost more than it saves): the
+ * programs are generated and compiled on a host thread of the library's own,
+ * a few partitions per program and the last partitions first (an apply that
+ * runs meanwhile reaches them last), and the call returns at once.  Before every sweep, qsv_apply (and qsv_adjoint_grad before its
+ * walk) loads the programs that have finished, on the calling thread; each
+ * partition launches its specialised kernel once its program is loaded and
+ * the table-driven kernel until then.
+ * While a compile is pending, qsv_apply keeps at most two sweeps queued ahead
+ * of the GPU so that later sweeps can switch.  The results are those of
+ * either kernel kind (equal up to the compiler's choice of fused
+ * multiply-adds).  qsv_plan_specialise on the plan waits for the compile
+ * (QSV_E_DEVICE if it failed; the plan then stays table-driven), and
+ * qsv_plan_destroy waits for it and discards it.  The plan must not be used
+ * from two threads at once.  A plan already specialised, or with a compile
+ * pending, is left as it is.
+ * Errors: QSV_E_ARG (null), QSV_E_UNSUPPORTED and QSV_E_STATE as for
+ * qsv_plan_specialise.
+ */
+qsv_status qsv_plan_specialise_async(qsv_ctx *ctx, qsv_plan *plan);
 /* Number of theta entries of circuit c and its offset in the packed theta array. */
 qsv_status qsv_plan_params(const qsv_plan *plan, int32_t circuit, int64_t *offset, int64_t *count);
 /*
@@ -344,6 +366,15 @@ qsv_status qsv_last_sweep_ms(qsv_ctx *ctx, double *total_ms, int64_t *n_launches
  * the same HIP events when timing is enabled; *n_launches = the number of
  * launches (0 when timing was off).  Waits for the last launch to finish. */
 qsv_status qsv_last_sweep_times(qsv_ctx *ctx, float *ms_out, int64_t cap, int64_t *n_launches);
+/* Load balance of the last batched launch on ctx made with timing enabled
+ * (batched plans: one persistent launch, workgroups taking circuits from a
+ * queue): for each of its *n_workgroups workgroups, the device's real-time
+ * clock when it started and when it exited (2 values per workgroup, at most
+ * cap written to ticks_out, host memory); *ticks_per_s (may be NULL) receives
+ * the clock's rate.  Waits for the context's stream.  *n_workgroups is 0 when
+ * the last batched launch ran without timing. */
+qsv_status qsv_last_batch_clock(qsv_ctx *ctx, uint64_t *ticks_out, int64_t cap, int64_t *n_workgroups,
+                                double *ticks_per_s);
 
 #ifdef __cplusplus
 }

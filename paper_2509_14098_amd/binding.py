@@ -51,8 +51,9 @@ _lib = None
 EXPORTS = ["qsv_last_error", "qsv_create", "qsv_destroy", "qsv_set_stream", "qsv_partition", "qsv_plan_destroy",
            "qsv_plan_get_info", "qsv_plan_params", "qsv_plan_partition", "qsv_apply", "qsv_expect",
            "qsv_expect_noalloc",
-           "qsv_adjoint_grad", "qsv_set_timing", "qsv_last_sweep_ms", "qsv_last_sweep_times", "qsv_last_autotune",
-           "qsv_partition_distributed", "qsv_plan_distributed_info", "qsv_plan_specialise"]
+           "qsv_adjoint_grad", "qsv_set_timing", "qsv_last_sweep_ms", "qsv_last_sweep_times", "qsv_last_batch_clock", "qsv_last_autotune",
+           "qsv_partition_distributed", "qsv_plan_distributed_info", "qsv_plan_specialise",
+           "qsv_plan_specialise_async"]
 
 
 def library_path() -> str:
@@ -72,12 +73,12 @@ def load_library():
     sigs = {
         "qsv_create": [I32, V, V], "qsv_destroy": [V], "qsv_set_stream": [V, V],
         "qsv_partition": [V, I32, V, V, I32, I32, U32, V, V], "qsv_plan_destroy": [V],
-        "qsv_plan_get_info": [V, V], "qsv_plan_specialise": [V, V, V], "qsv_plan_params": [V, I32, V, V],
+        "qsv_plan_get_info": [V, V], "qsv_plan_specialise": [V, V, V], "qsv_plan_specialise_async": [V, V], "qsv_plan_params": [V, I32, V, V],
         "qsv_plan_partition": [V, I32, I32, I64, V, V, I64, V],
         "qsv_apply": [V, V, V, V, V], "qsv_expect": [V, V, I32, I32, I64, V, V],
         "qsv_expect_noalloc": [V, V, I32, I32, I64, V, V],
         "qsv_adjoint_grad": [V, V, V, I32, V, V, V, V, V],
-        "qsv_set_timing": [V, I32], "qsv_last_sweep_ms": [V, V, V], "qsv_last_sweep_times": [V, V, I64, V], "qsv_last_autotune": [V, I32],
+        "qsv_set_timing": [V, I32], "qsv_last_sweep_ms": [V, V, V], "qsv_last_sweep_times": [V, V, I64, V], "qsv_last_batch_clock": [V, V, I64, V, V], "qsv_last_autotune": [V, I32],
         "qsv_partition_distributed": [V, I32, V, I64, I32, I32, U32, V, V],
         "qsv_plan_distributed_info": [V, V, V, V, V],
     }
@@ -155,6 +156,17 @@ def qsv_last_sweep_times(ctx):
     return out[:n.value]
 
 
+def qsv_last_batch_clock(ctx):
+    """(start, exit) clock ticks per workgroup of the last timed batched
+    launch, as an (n, 2) uint64 array, and the clock rate in ticks/s."""
+    n, hz = ctypes.c_int64(), ctypes.c_double()
+    _check(load_library().qsv_last_batch_clock(ctx, None, 0, ctypes.byref(n), ctypes.byref(hz)))
+    out = np.zeros((max(n.value, 1), 2), dtype=np.uint64)
+    _check(load_library().qsv_last_batch_clock(ctx, out.ctypes.data_as(ctypes.c_void_p), 2 * n.value,
+                                               ctypes.byref(n), None))
+    return out[:n.value], hz.value
+
+
 def qsv_partition(ctx, n_qubits: int, gates, circ_offsets=None, k_local: int = 0, flags: int = 0, tile=None):
     """gates: numpy array with the qsv_gate layout; circ_offsets: n_circuits+1
     offsets (default: one circuit).  tile: (reg_qubits, log_threads) or None."""
@@ -214,6 +226,12 @@ def qsv_plan_specialise(ctx, plan) -> float:
     secs = ctypes.c_double(0.0)
     _check(load_library().qsv_plan_specialise(ctx, plan, ctypes.byref(secs)))
     return secs.value
+
+
+def qsv_plan_specialise_async(ctx, plan) -> None:
+    """Start compiling the plan's specialised kernels in the background;
+    qsv_apply switches to them once they are ready."""
+    _check(load_library().qsv_plan_specialise_async(ctx, plan))
 
 
 def qsv_plan_params(plan, circuit: int = 0):

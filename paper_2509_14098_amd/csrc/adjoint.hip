@@ -130,7 +130,7 @@ hipError_t launch_reverse(const Plan &plan, int R, int LW, int pidx, const float
 #define QSV_CASE(r, lw) \
     if (R == r && LW == lw) return launch_reverse_t<r, lw>(plan, pidx, psi, lam, gpart, stride, s);
     QSV_CASE(1, 6) QSV_CASE(2, 6) QSV_CASE(3, 6) QSV_CASE(4, 6) QSV_CASE(5, 6)
-    QSV_CASE(3, 8) QSV_CASE(4, 8) QSV_CASE(5, 8) QSV_CASE(4, 9)
+    QSV_CASE(3, 8) QSV_CASE(4, 8) QSV_CASE(5, 8) QSV_CASE(3, 9) QSV_CASE(4, 9) QSV_CASE(3, 10)
 #undef QSV_CASE
     return hipErrorInvalidValue;
 }

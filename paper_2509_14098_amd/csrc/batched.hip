@@ -37,6 +37,7 @@ struct BatchArgs {
     double *gpart;              // [n_slots][waves] scratch
     int *queue;
     int adjoint;
+    uint64_t *wg_clock;         // null, or per workgroup the real-time clock at its start and at its exit
 };
 
 // Registers in the layout (toff, roff) -> LDS -> registers in the layout (toff2,
@@ -72,6 +73,7 @@ __global__ __launch_bounds__(1 << LW) void batched_kernel(
     __shared__ double s_red[WAVES];
     const uint32_t tid = threadIdx.x;
     const int wave = tid >> 6;
+    if (A.wg_clock && tid == 0) A.wg_clock[2 * blockIdx.x] = __builtin_amdgcn_s_memrealtime();
     while (true) {
         if (tid == 0) s_item = atomicAdd(A.queue, 1);
         __syncthreads();
@@ -181,6 +183,7 @@ __global__ __launch_bounds__(1 << LW) void batched_kernel(
         }
         __syncthreads();
     }
+    if (A.wg_clock && tid == 0) A.wg_clock[2 * blockIdx.x + 1] = __builtin_amdgcn_s_memrealtime();
 }
 
 __global__ void reset_counter_kernel(int *q)
@@ -204,7 +207,7 @@ static void set_lds_attr()
 
 hipError_t launch_batched(const Plan &plan, const DevGroup *groups, int n_groups, const DevTerm *terms,
                           const double *theta, float2 *psi_out, const float2 *psi_in, double *energy, double *grad,
-                          double *gpart, int *queue, bool adjoint, int grid, hipStream_t s)
+                          double *gpart, int *queue, bool adjoint, int grid, uint64_t *wg_clock, hipStream_t s)
 {
     if (plan.R != BATCH_R || plan.LW != BATCH_LW) return hipErrorInvalidValue;
     hipError_t e = launch_materialize(plan, theta, s);
@@ -223,6 +226,7 @@ hipError_t launch_batched(const Plan &plan, const DevGroup *groups, int n_groups
     A.gpart = gpart;
     A.queue = queue;
     A.adjoint = adjoint ? 1 : 0;
+    A.wg_clock = wg_clock;
     const size_t lds = (size_t)8 << plan.t;
     set_lds_attr<BATCH_R, BATCH_LW>();
     hipLaunchKernelGGL((batched_kernel<BATCH_R, BATCH_LW>), dim3(grid), dim3(1 << BATCH_LW), lds, s, plan.d_parts,

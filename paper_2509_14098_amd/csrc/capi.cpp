@@ -9,8 +9,10 @@
 #include <memory>
 #include <mutex>
 #include <new>
+#include <atomic>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "kernels.h"
@@ -116,12 +118,28 @@ struct qsv_ctx {
     size_t pinned_bytes = 0;
     hipEvent_t pinned_ready = nullptr;
     hipEvent_t handoff = nullptr;  // orders work across a change of stream
+    hipEvent_t pace[2] = {nullptr, nullptr};  // qsv_apply's sweeps in flight while a compile is pending
     // qsv_expect_noalloc: pinned staging of the grouped terms, allocated once by qsv_create
     void *na_staging = nullptr;
     hipEvent_t na_staging_ready = nullptr;
     int *queue = nullptr;
     int n_cu = 0;
 
+    // batched launches with timing on: per workgroup its start and exit on the
+    // device's real-time clock
+    uint64_t *wg_clock = nullptr;
+    int wg_clock_n = 0;   // workgroups of the last timed batched launch
+    uint64_t *batch_clock(int grid)
+    {
+        if (!timing) {
+            wg_clock_n = 0;
+            return nullptr;
+        }
+        if (!wg_clock && hipMalloc((void **)&wg_clock, sizeof(uint64_t) * 2 * 4096) != hipSuccess)
+            fail(QSV_E_NOMEM, "clock buffer allocation failed");
+        wg_clock_n = std::min(grid, 4096);
+        return grid <= 4096 ? wg_clock : nullptr;
+    }
     int *ensure_queue()
     {
         if (!queue && hipMalloc((void **)&queue, 256) != hipSuccess) fail(QSV_E_NOMEM, "queue allocation failed");
@@ -302,9 +320,12 @@ qsv_status qsv_destroy(qsv_ctx *ctx)
         dev_free(ctx->lam);
         dev_free(ctx->terms_dev);
         dev_free(ctx->queue);
+        dev_free(ctx->wg_clock);
         if (ctx->pinned) (void)hipHostFree(ctx->pinned);
         if (ctx->pinned_ready) (void)hipEventDestroy(ctx->pinned_ready);
         if (ctx->handoff) (void)hipEventDestroy(ctx->handoff);
+        for (hipEvent_t e : ctx->pace)
+            if (e) (void)hipEventDestroy(e);
         if (ctx->na_staging) (void)hipHostFree(ctx->na_staging);
         if (ctx->na_staging_ready) (void)hipEventDestroy(ctx->na_staging_ready);
         for (auto e : ctx->events) (void)hipEventDestroy(e);
@@ -352,6 +373,25 @@ qsv_status qsv_last_sweep_ms(qsv_ctx *ctx, double *total_ms, int64_t *n_launches
         }
         *total_ms = ctx->last_ms;
         *n_launches = ctx->last_launches;
+    });
+}
+
+qsv_status qsv_last_batch_clock(qsv_ctx *ctx, uint64_t *ticks_out, int64_t cap, int64_t *n_workgroups,
+                                double *ticks_per_s)
+{
+    return guarded([&] {
+        if (!ctx || !n_workgroups || cap < 0 || (cap > 0 && !ticks_out)) fail(QSV_E_ARG, "null argument");
+        *n_workgroups = ctx->wg_clock_n;
+        if (ticks_per_s) {
+            int hz = 0;  // kHz
+            hip_check(hipDeviceGetAttribute(&hz, hipDeviceAttributeWallClockRate, ctx->device), "attr");
+            *ticks_per_s = 1e3 * hz;
+        }
+        if (ctx->wg_clock_n > 0 && cap > 0) {
+            hip_check(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+            const int64_t n = std::min<int64_t>(cap, 2 * (int64_t)ctx->wg_clock_n);
+            hip_check(hipMemcpy(ticks_out, ctx->wg_clock, sizeof(uint64_t) * n, hipMemcpyDeviceToHost), "hipMemcpy");
+        }
     });
 }
 
@@ -491,6 +531,93 @@ static void load_spec(Plan &plan, const std::vector<SpecChunk> &chunks, bool rev
     plan.spec_modules = std::move(mods);
 }
 
+}  // extern "C"
+
+// A compile of a plan's specialised kernels running on a host thread of its own
+// (the compiler itself runs in helper processes), program by program.  The thread only reads the plan and publishes each finished
+// program; the programs are loaded, and the plan changed, on the caller's
+// thread.
+struct qsv::AsyncSpecialise {
+    std::thread worker;
+    std::atomic<bool> done{false};
+    std::atomic<bool> sized{false};               // chunks and ready are sized
+    std::vector<SpecChunk> chunks;
+    std::unique_ptr<std::atomic<bool>[]> ready;   // program c's code object is in chunks[c]
+    std::vector<char> loaded;                     // caller's thread only
+    size_t n_loaded = 0;
+    bool rev = false;
+    std::string err;
+    std::chrono::steady_clock::time_point t0;
+};
+
+extern "C" {
+
+// Loads one program of specialised kernels into the plan (current device):
+// the forward and, with rev, the reverse kernel of each of its partitions.
+static void load_chunk(Plan &plan, const SpecChunk &c, bool rev)
+{
+    hipModule_t m = nullptr;
+    if (hipModuleLoadData(&m, c.code.data()) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(QSV_E_DEVICE, "hipModuleLoadData failed");
+    }
+    std::vector<void *> fn, rfn;
+    for (int p = c.p0; p < c.p1; ++p)
+        for (int r = 0; r < (rev ? 2 : 1); ++r) {
+            hipFunction_t f = nullptr;
+            const std::string name = (r ? "qsv_rspec_" : "qsv_spec_") + std::to_string(p);
+            if (hipModuleGetFunction(&f, m, name.c_str()) != hipSuccess) {
+                (void)hipGetLastError();
+                (void)hipModuleUnload(m);
+                fail(QSV_E_DEVICE, "hipModuleGetFunction " + name);
+            }
+            (r ? rfn : fn).push_back((void *)f);
+        }
+    plan.spec_modules.push_back((void *)m);
+    for (int p = c.p0; p < c.p1; ++p) {
+        plan.spec_fn[p] = fn[p - c.p0];
+        if (rev) plan.spec_rev_fn[p] = rfn[p - c.p0];
+    }
+}
+
+// Takes up what a background compile of `plan` has finished: loads every
+// program that is ready (its partitions launch their specialised kernels from
+// then on); with wait, first waits for the whole compile.  When the compile is
+// over the plan is marked specialised (or, if it failed, keeps the programs
+// loaded so far and the error for qsv_plan_specialise).  Returns whether a
+// compile is still pending.
+static bool finish_async(Plan &plan, bool wait)
+{
+    if (!plan.async_spec) return false;
+    AsyncSpecialise &a = *plan.async_spec;
+    if (wait && a.worker.joinable()) a.worker.join();
+    const bool done = a.done.load(std::memory_order_acquire);
+    if (a.sized.load(std::memory_order_acquire)) {
+        const size_t n = a.chunks.size();
+        if (a.loaded.size() != n) {
+            a.loaded.assign(n, 0);
+            plan.spec_fn.assign(plan.parts.size(), nullptr);
+            plan.spec_rev_fn.assign(a.rev ? plan.parts.size() : 0, nullptr);
+        }
+        for (size_t c = 0; c < n; ++c)
+            if (!a.loaded[c] && a.ready[c].load(std::memory_order_acquire)) {
+                load_chunk(plan, a.chunks[c], a.rev);
+                a.loaded[c] = 1;
+                ++a.n_loaded;
+            }
+    }
+    if (!done) return true;
+    if (a.worker.joinable()) a.worker.join();
+    std::shared_ptr<AsyncSpecialise> keep = std::move(plan.async_spec);
+    if (!a.err.empty() || a.n_loaded != a.chunks.size()) {
+        plan.specialise_error = a.err.empty() ? "background compile incomplete" : a.err;
+        return false;
+    }
+    plan.specialised = true;
+    plan.specialise_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - a.t0).count();
+    return false;
+}
+
 static TuneChoice autotune(qsv_ctx *ctx, int n, const qsv_gate *gates, const std::vector<int64_t> &off, uint32_t flags,
                            int k_fixed)
 {
@@ -526,7 +653,7 @@ static TuneChoice autotune(qsv_ctx *ctx, int n, const qsv_gate *gates, const std
     hip_check(hipEventCreate(&e0), "hipEventCreate");
     hip_check(hipEventCreate(&e1), "hipEventCreate");
     // (3, 8): 11-qubit tiles, twice the workgroups of (4, 8) for states of ~20 qubits
-    const int shapes[][2] = {{5, 8}, {4, 8}, {4, 9}, {5, 9}, {4, 10}, {3, 8}};
+    const int shapes[][2] = {{5, 8}, {4, 8}, {4, 9}, {5, 9}, {4, 10}, {3, 8}, {3, 9}, {3, 10}};
     for (auto &sh : shapes) {
         const int R = sh[0], LW = sh[1], t = R + LW;
         if ((flags & QSV_PLAN_GRAD) && t > 13) continue;
@@ -649,6 +776,7 @@ qsv_status qsv_plan_destroy(qsv_plan *plan)
 {
     return guarded([&] {
         if (!plan) return;
+        if (plan->async_spec) plan->async_spec->worker.join();  // its compile is discarded
         if (plan->device >= 0) (void)hipSetDevice(plan->device);
         dev_free(plan->d_ops);
         dev_free(plan->d_stages);
@@ -710,6 +838,13 @@ qsv_status qsv_plan_specialise(qsv_ctx *ctx, qsv_plan *plan, double *seconds_out
         if (((size_t)8 << plan->t) > (size_t)64 * 1024)
             fail(QSV_E_UNSUPPORTED, "specialised sweeps take tiles of at most 64 KiB of LDS (13 qubits)");
         if (ctx && plan->device != ctx->device) fail(QSV_E_STATE, "plan has no device tables on this context's device");
+        if (ctx && plan->async_spec) {  // a background compile is running: wait for it
+            hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+            finish_async(*plan, true);
+            if (!plan->specialised) fail(QSV_E_DEVICE, plan->specialise_error);
+            if (seconds_out) *seconds_out = plan->specialise_seconds;
+            return;
+        }
         const auto t0 = std::chrono::steady_clock::now();
         std::vector<SpecChunk> chunks;
         const std::string err = specialise_compile(*plan, chunks, 16);
@@ -722,6 +857,42 @@ qsv_status qsv_plan_specialise(qsv_ctx *ctx, qsv_plan *plan, double *seconds_out
         plan->specialised = true;
         plan->specialise_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         if (seconds_out) *seconds_out = plan->specialise_seconds;
+    });
+}
+
+qsv_status qsv_plan_specialise_async(qsv_ctx *ctx, qsv_plan *plan)
+{
+    return guarded([&] {
+        if (!ctx || !plan) fail(QSV_E_ARG, "null argument");
+        if (plan->specialised || plan->async_spec) return;
+        if (plan->n_circuits != 1) fail(QSV_E_UNSUPPORTED, "only single-circuit plans are specialised");
+        if (((size_t)8 << plan->t) > (size_t)64 * 1024)
+            fail(QSV_E_UNSUPPORTED, "specialised sweeps take tiles of at most 64 KiB of LDS (13 qubits)");
+        if (plan->device != ctx->device) fail(QSV_E_STATE, "plan has no device tables on this context's device");
+        auto a = std::make_shared<AsyncSpecialise>();
+        a->t0 = std::chrono::steady_clock::now();
+        a->rev = specialise_reverse(*plan);
+        AsyncSpecialise *ap = a.get();
+        const Plan *pp = plan;
+        // small programs (about 48, 16 compiling at a time), the last partitions
+        // first: an apply running meanwhile reaches them last
+        const int per = std::max(1, ((int)plan->parts.size() + 47) / 48);
+        a->worker = std::thread([ap, pp, per] {
+            try {
+                ap->err = specialise_compile(
+                    *pp, ap->chunks, 16, nullptr, per,
+                    [ap](size_t c) { ap->ready[c].store(true, std::memory_order_release); },
+                    [ap](size_t n) {
+                        ap->ready.reset(new std::atomic<bool>[std::max<size_t>(n, 1)]);
+                        for (size_t i = 0; i < n; ++i) ap->ready[i].store(false, std::memory_order_relaxed);
+                        ap->sized.store(true, std::memory_order_release);
+                    });
+            } catch (const std::exception &e) {
+                ap->err = std::string("specialise: ") + e.what();
+            }
+            ap->done.store(true, std::memory_order_release);
+        });
+        plan->async_spec = std::move(a);
     });
 }
 
@@ -833,13 +1004,15 @@ qsv_status qsv_apply(qsv_ctx *ctx, const qsv_plan *plan, const double *theta_dev
         if (plan->n_params > 0 && !theta_dev) fail(QSV_E_ARG, "theta is null");
         hip_check(hipSetDevice(ctx->device), "hipSetDevice");
         if (plan->n_circuits > 1) {
+            const int grid = ctx->grid_batched(plan->n_circuits);
             hip_check(launch_batched(*plan, nullptr, 0, nullptr, theta_dev, (float2 *)psi_dev, nullptr, nullptr, nullptr,
-                                     nullptr, ctx->ensure_queue(), false, ctx->grid_batched(plan->n_circuits),
-                                     ctx->stream),
+                                     nullptr, ctx->ensure_queue(), false, grid, ctx->batch_clock(grid), ctx->stream),
                       "batched launch");
             ctx->last_launches = 0;
             return;
         }
+        Plan &mp = const_cast<qsv_plan &>(*plan);
+        bool pending = finish_async(mp, false);
         hip_check(launch_materialize(*plan, theta_dev, ctx->stream), "materialize");
         const int np = (int)plan->parts.size();
         if (ctx->timing) {
@@ -852,11 +1025,22 @@ qsv_status qsv_apply(qsv_ctx *ctx, const qsv_plan *plan, const double *theta_dev
         float2 *psi = (float2 *)psi_dev;
         float2 *ckpt = (float2 *)ckpt_dev;
         const size_t dim = (size_t)1 << plan->n;
+        // a background compile (qsv_plan_specialise_async) may finish during the
+        // apply: while it runs, at most two sweeps are queued ahead of the GPU, and
+        // each later sweep launches the specialised kernel once it is loaded
+        if (pending && !ctx->pace[0]) {
+            for (hipEvent_t &e : ctx->pace) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+        }
         for (int p = 0; p < np; ++p) {
+            if (pending && p >= 2) {
+                hip_check(hipEventSynchronize(ctx->pace[p % 2]), "hipEventSynchronize");
+                pending = finish_async(mp, false);
+            }
             float2 *ck = (ckpt && p < np - 1) ? ckpt + (size_t)p * dim : nullptr;
             if (ctx->timing) hip_check(hipEventRecord(ctx->events[2 * p], ctx->stream), "hipEventRecord");
             hip_check(launch_sweep(*plan, plan->R, plan->LW, p, psi, ck, ctx->stream), "sweep launch");
             if (ctx->timing) hip_check(hipEventRecord(ctx->events[2 * p + 1], ctx->stream), "hipEventRecord");
+            if (pending) hip_check(hipEventRecord(ctx->pace[p % 2], ctx->stream), "hipEventRecord");
         }
         ctx->last_launches = ctx->timing ? np : 0;
     });
@@ -932,6 +1116,7 @@ qsv_status qsv_adjoint_grad(qsv_ctx *ctx, const qsv_plan *plan, const qsv_pauli_
         if (!energy_dev) fail(QSV_E_ARG, "energy is null");
         if (plan->n_params > 0 && (!theta_dev || !grad_dev)) fail(QSV_E_ARG, "theta or grad is null");
         if (plan->device != ctx->device) fail(QSV_E_STATE, "plan has no device tables on this context's device");
+        finish_async(const_cast<qsv_plan &>(*plan), false);  // reverse kernels of a finished background compile
         HostGroups g = group_terms(H, n_terms, plan->n, false);
         DevPass *dp_unused = nullptr;
         hip_check(hipSetDevice(ctx->device), "hipSetDevice");
@@ -942,9 +1127,10 @@ qsv_status qsv_adjoint_grad(qsv_ctx *ctx, const qsv_plan *plan, const qsv_pauli_
             DevGroup *dg = nullptr;
             DevTerm *dt = nullptr;
             if (!g.groups.empty()) upload_groups(ctx, g, dp_unused, dg, dt);
+            const int grid = ctx->grid_batched(plan->n_circuits);
             hip_check(launch_batched(*plan, dg, (int)g.groups.size(), dt, theta_dev, nullptr, (const float2 *)psi_final_dev,
-                                     energy_dev, grad_dev, gpart, ctx->ensure_queue(), true,
-                                     ctx->grid_batched(plan->n_circuits), ctx->stream),
+                                     energy_dev, grad_dev, gpart, ctx->ensure_queue(), true, grid,
+                                     ctx->batch_clock(grid), ctx->stream),
                       "batched launch");
             return;
         }

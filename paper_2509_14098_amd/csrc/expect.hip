@@ -25,12 +25,13 @@ namespace qsv {
 
 constexpr int RED_THREADS = 256;
 
+template <int THREADS = RED_THREADS>
 __device__ __forceinline__ double block_sum(double v, double *sh)
 {
     const int tid = threadIdx.x;
     sh[tid] = v;
     __syncthreads();
-    for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+    for (int s = THREADS / 2; s > 0; s >>= 1) {
         if (tid < s) sh[tid] += sh[tid + s];
         __syncthreads();
     }
@@ -43,12 +44,12 @@ __device__ __forceinline__ double parity_sign(uint64_t v) { return (__popcll(v) 
 
 // One launch covers every pass: workgroup (x, pass, b) walks tiles x, x +
 // gridDim.x, ... of state b with the pass's tile qubits.  A thread holds 8
-// amplitude pairs of the tile (positions 2 tid + j + 512 it, j < 2, it < 8),
+// amplitude pairs of the tile (positions 2 tid + j + 1024 it, j < 2, it < 4),
 // read as 16-byte pairs (qubit 0 is always a tile qubit).  Partner amplitudes
 // of the pass's X/Y groups come from the LDS copy of the tile, those of wide
 // groups (masks that do not fit a tile with the low qubits) from HBM.
 // partials[(b * n_passes + pass) * gridDim.x + block]
-__global__ __launch_bounds__(RED_THREADS) void expect_kernel(const DevPass *__restrict__ passes, int p0,
+__global__ __launch_bounds__(EXPECT_THREADS) void expect_kernel(const DevPass *__restrict__ passes, int p0,
                                                               int n_passes, const DevGroup *__restrict__ groups,
                                                               const DevTerm *__restrict__ terms, int n,
                                                               const float2 *__restrict__ psi,
@@ -56,7 +57,7 @@ __global__ __launch_bounds__(RED_THREADS) void expect_kernel(const DevPass *__re
 {
     typedef float nf4 __attribute__((ext_vector_type(4)));  // a vector type the builtin accepts
     __shared__ float4 lds4[(1 << EXPECT_TILE_QUBITS) / 2];
-    __shared__ double sh[RED_THREADS];
+    __shared__ double sh[EXPECT_THREADS];
     const float2 *lds = reinterpret_cast<const float2 *>(lds4);
     const int pi = p0 + (int)blockIdx.y;
     const DevPass PS = passes[pi];
@@ -75,19 +76,20 @@ __global__ __launch_bounds__(RED_THREADS) void expect_kernel(const DevPass *__re
             m &= m - 1;
         }
     }
-    uint64_t xthr = 0;  // positions 2 tid: tile positions 1..8
+    uint64_t xthr = 0;  // positions 2 tid: tile positions 1..LT
 #pragma unroll
-    for (int c = 1; c <= 8; ++c)
+    for (int c = 1; c <= EXPECT_LOG_THREADS; ++c)
         if ((tid >> (c - 1)) & 1u) xthr |= posbit[c];
-    uint64_t row[EXPECT_PAIRS];  // positions 512 it: tile positions 9..11
+    uint64_t row[EXPECT_PAIRS];  // positions ROW it: the tile positions above
 #pragma unroll
     for (int it = 0; it < EXPECT_PAIRS; ++it) {
         uint64_t r = 0;
 #pragma unroll
-        for (int c = 9; c < EXPECT_TILE_QUBITS; ++c)
-            if ((it >> (c - 9)) & 1) r |= posbit[c];
+        for (int c = EXPECT_LOG_THREADS + 1; c < EXPECT_TILE_QUBITS; ++c)
+            if ((it >> (c - EXPECT_LOG_THREADS - 1)) & 1) r |= posbit[c];
         row[it] = r;
     }
+    constexpr uint32_t ROW = 2u * EXPECT_THREADS;  // tile positions per pair row
     const uint64_t full = (1ull << n) - 1;
     const uint64_t outside = full & ~PS.tile_mask;
     const uint64_t n_tiles = 1ull << (n - t);
@@ -103,7 +105,7 @@ __global__ __launch_bounds__(RED_THREADS) void expect_kernel(const DevPass *__re
         for (int it = 0; it < EXPECT_PAIRS; ++it) {
             x[it] = base | xthr | row[it];
             v[it] = float4{0.f, 0.f, 0.f, 0.f};
-            if (2 * tid + 512u * it < tdim) {
+            if (2 * tid + ROW * it < tdim) {
                 const nf4 w = __builtin_nontemporal_load(reinterpret_cast<const nf4 *>(s + x[it]));
                 v[it] = float4{w.x, w.y, w.z, w.w};
             }
@@ -112,13 +114,13 @@ __global__ __launch_bounds__(RED_THREADS) void expect_kernel(const DevPass *__re
             __syncthreads();  // the previous tile's partner reads are done
 #pragma unroll
             for (int it = 0; it < EXPECT_PAIRS; ++it)
-                if (2 * tid + 512u * it < tdim) lds4[tid + 256 * it] = v[it];
+                if (2 * tid + ROW * it < tdim) lds4[tid + EXPECT_THREADS * it] = v[it];
             __syncthreads();
         }
         for (int g = PS.g_begin; g < PS.g_end; ++g) {
             const DevGroup G = groups[g];
             if (G.x_mask == 0) {
-                // diagonal group: the 16 weights with the term loop outside (16
+                // diagonal group: the 8 weights with the term loop outside (8
                 // independent float64 sums); each weight adds its terms in order
                 double w[2 * EXPECT_PAIRS];
 #pragma unroll
@@ -140,7 +142,7 @@ __global__ __launch_bounds__(RED_THREADS) void expect_kernel(const DevPass *__re
                 }
             } else if (G.xt >= 0) {
                 // partners in the LDS tile: the pairs (p0, p1 = p0 ^ xt) of tile
-                // positions with bit lb of p0 clear, k = tid + 256 i enumerating
+                // positions with bit lb of p0 clear, k = tid + 512 i enumerating
                 // them; per term, with z = conj(psi_p1) psi_p0 and signs from
                 // the term's Z mask on the tile (zt) and outside it (base):
                 //   s0 Re[c z] + s1 Re[c conj(z)]
@@ -149,7 +151,7 @@ __global__ __launch_bounds__(RED_THREADS) void expect_kernel(const DevPass *__re
                 const uint32_t below = (1u << lb) - 1;
 #pragma unroll
                 for (int i = 0; i < EXPECT_PAIRS; ++i) {
-                    const uint32_t k = tid + 256u * i;
+                    const uint32_t k = tid + (uint32_t)EXPECT_THREADS * i;
                     if (k >= (tdim >> 1)) continue;
                     const uint32_t p0 = ((k >> lb) << (lb + 1)) | (k & below);
                     const float2 a = lds[p0], c = lds[p0 ^ xt];
@@ -168,7 +170,7 @@ __global__ __launch_bounds__(RED_THREADS) void expect_kernel(const DevPass *__re
                 //   sum_t Re[c_t (-1)^{|x & z_t|} conj(psi_{x ^ m}) psi_x]
 #pragma unroll
                 for (int it = 0; it < EXPECT_PAIRS; ++it) {
-                    if (2 * tid + 512u * it >= tdim) continue;
+                    if (2 * tid + ROW * it >= tdim) continue;
 #pragma unroll
                     for (int j = 0; j < 2; ++j) {
                         const float2 a = j ? float2{v[it].z, v[it].w} : float2{v[it].x, v[it].y};
@@ -185,7 +187,7 @@ __global__ __launch_bounds__(RED_THREADS) void expect_kernel(const DevPass *__re
             }
         }
     }
-    const double tot = block_sum(acc, sh);
+    const double tot = block_sum<EXPECT_THREADS>(acc, sh);
     if (threadIdx.x == 0) partials[((uint64_t)b * n_passes + pi) * gridDim.x + blockIdx.x] = tot;
 }
 
@@ -345,7 +347,7 @@ hipError_t launch_expect(const DevPass *passes, int n_passes, const DevGroup *gr
         const int64_t nz = std::min<int64_t>(lim, batch - b0);
         for (int p0 = 0; p0 < n_passes; p0 += (int)lim) {
             const int ny = (int)std::min<int64_t>(lim, n_passes - p0);
-            hipLaunchKernelGGL(expect_kernel, dim3(nb, ny, (uint32_t)nz), dim3(RED_THREADS), 0, s, passes, p0,
+            hipLaunchKernelGGL(expect_kernel, dim3(nb, ny, (uint32_t)nz), dim3(EXPECT_THREADS), 0, s, passes, p0,
                                n_passes, groups, terms, n, psi + ((uint64_t)b0 << n),
                                partials + (uint64_t)b0 * n_passes * nb);
             hipError_t e = hipGetLastError();

@@ -2,6 +2,8 @@
 // launchers.  Not part of the public interface.
 #pragma once
 #include <cstdint>
+#include <functional>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -91,6 +93,11 @@ struct Plan {
     std::vector<void *> spec_modules; // hipModule_t, unloaded with the plan
     bool specialised = false;
     double specialise_seconds = 0;
+    // qsv_plan_specialise_async: the compile running in the background (null
+    // when none is pending); its kernels are loaded by the next call on the plan
+    // that finds it finished
+    std::shared_ptr<struct AsyncSpecialise> async_spec;
+    std::string specialise_error;     // the error of a failed background compile
 
     // device copies (null for host-only plans)
     int device = -1;
@@ -136,7 +143,14 @@ bool specialise_reverse(const Plan &plan);
 // where specialise_reverse holds, reverse kernels; or only the forward kernels
 // of the listed partitions, one program each) in up to max_procs compiler
 // processes; returns "" or the error (with the compiler log).
+// Incremental use (qsv_plan_specialise_async): with chunk_partitions > 0 the
+// partitions are cut into programs of that many partitions, compiled last
+// partitions first; on_sized(n) is called once chunks holds all n programs
+// (before any compile), and on_chunk(c), on the calling thread, as soon as
+// program c's code object is in chunks[c].
 std::string specialise_compile(const Plan &plan, std::vector<SpecChunk> &chunks, int max_procs,
-                               const std::vector<int> *subset = nullptr);
+                               const std::vector<int> *subset = nullptr, int chunk_partitions = 0,
+                               const std::function<void(size_t)> &on_chunk = nullptr,
+                               const std::function<void(size_t)> &on_sized = nullptr);
 
 }  // namespace qsv

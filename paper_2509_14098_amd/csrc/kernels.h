@@ -33,7 +33,9 @@ struct DevPass {
 
 // expect.hip
 constexpr int EXPECT_TILE_QUBITS = 12;   // tiles of 4096 amplitudes, 32 KiB of LDS
-constexpr int EXPECT_PAIRS = 8;         // amplitude pairs per thread (256 threads)
+constexpr int EXPECT_LOG_THREADS = 9;   // 512 threads per workgroup
+constexpr int EXPECT_THREADS = 1 << EXPECT_LOG_THREADS;
+constexpr int EXPECT_PAIRS = (1 << EXPECT_TILE_QUBITS) / (2 * EXPECT_THREADS);  // amplitude pairs per thread: 4
 constexpr int EXPECT_MAX_BLOCKS = 1024; // workgroups per (pass, batch entry)
 constexpr int EXPECT_MIN_BLOCKS = 2048; // passes are split by groups until they fill this many workgroups
 // Workgroups per (pass, batch entry): partial sums of launch_expect are
@@ -72,7 +74,7 @@ hipError_t launch_grad_reduce(const Plan &plan, const double *gpart, int64_t n_s
 // batched.hip
 hipError_t launch_batched(const Plan &plan, const DevGroup *groups, int n_groups, const DevTerm *terms,
                           const double *theta, float2 *psi_out, const float2 *psi_in, double *energy, double *grad,
-                          double *gpart, int *queue, bool adjoint, int grid, hipStream_t s);
+                          double *gpart, int *queue, bool adjoint, int grid, uint64_t *wg_clock, hipStream_t s);
 int batched_waves();
 
 }  // namespace qsv

@@ -22,6 +22,7 @@
 #include <cstdlib>
 #include <deque>
 #include <fstream>
+#include <functional>
 #include <iterator>
 #include <string>
 #include <thread>
@@ -90,7 +91,9 @@ struct TempDir {
 }  // namespace
 
 std::string specialise_compile(const Plan &plan, std::vector<SpecChunk> &chunks, int max_procs,
-                               const std::vector<int> *subset)
+                               const std::vector<int> *subset, int chunk_partitions,
+                               const std::function<void(size_t)> &on_chunk,
+                               const std::function<void(size_t)> &on_sized)
 {
     const int np = (int)plan.parts.size();
     chunks.clear();
@@ -117,6 +120,17 @@ std::string specialise_compile(const Plan &plan, std::vector<SpecChunk> &chunks,
         }
         p = np;
     }
+    if (chunk_partitions > 0) {
+        // chunk_partitions per program, the last partitions first: an apply that
+        // starts while they compile reaches the late partitions last
+        for (int q = np; q > 0; q -= chunk_partitions) {
+            SpecChunk ch;
+            ch.p0 = std::max(0, q - chunk_partitions);
+            ch.p1 = q;
+            chunks.push_back(ch);
+        }
+        p = np;
+    }
     for (int c = 0; c < nc && p < np; ++c) {
         SpecChunk ch;
         ch.p0 = p;
@@ -127,6 +141,7 @@ std::string specialise_compile(const Plan &plan, std::vector<SpecChunk> &chunks,
         ch.p1 = p;
         chunks.push_back(ch);
     }
+    if (on_sized) on_sized(chunks.size());
 
     TempDir tmp;
     const char *td = std::getenv("TMPDIR");
@@ -140,6 +155,7 @@ std::string specialise_compile(const Plan &plan, std::vector<SpecChunk> &chunks,
     const std::string cache = cdir && *cdir ? cdir : "";
     const char *conly = std::getenv("QSV_KERNEL_CACHE_ONLY");
     const bool cache_only = !cache.empty() && conly && *conly && std::string(conly) != "0";
+    if (!cache.empty() && !cache_only) (void)mkdir(cache.c_str(), 0777);  // the cache directory itself, if missing
     std::vector<std::string> src(n), out(n), log(n), cached(n);
     std::vector<size_t> todo;
     for (size_t c = 0; c < n; ++c) {
@@ -149,6 +165,7 @@ std::string specialise_compile(const Plan &plan, std::vector<SpecChunk> &chunks,
             const std::string code = read_file(cached[c]);
             if (!code.empty()) {
                 chunks[c].code.assign(code.begin(), code.end());
+                if (on_chunk) on_chunk(c);
                 continue;
             }
             if (cache_only) return "kernel not in the cache (QSV_KERNEL_CACHE_ONLY is set): " + cached[c];
@@ -198,11 +215,12 @@ std::string specialise_compile(const Plan &plan, std::vector<SpecChunk> &chunks,
             err = "kernel compile failed for partitions " + std::to_string(chunks[c].p0) + ".." +
                   std::to_string(chunks[c].p1 - 1) + ": " + l;
         }
-    }
-    if (!err.empty()) return err;
-    for (size_t c : todo) {
+        if (!err.empty()) continue;
         const std::string code = read_file(out[c]);
-        if (code.empty()) return "no code object from the compiler helper for chunk " + std::to_string(c);
+        if (code.empty()) {
+            err = "no code object from the compiler helper for chunk " + std::to_string(c);
+            continue;
+        }
         chunks[c].code.assign(code.begin(), code.end());
         if (!cached[c].empty()) {  // publish by rename, so readers see whole files only
             const std::string part = cached[c] + "." + std::to_string(getpid()) + ".tmp";
@@ -211,8 +229,9 @@ std::string specialise_compile(const Plan &plan, std::vector<SpecChunk> &chunks,
             f.close();
             if (!f || std::rename(part.c_str(), cached[c].c_str()) != 0) std::remove(part.c_str());
         }
+        if (on_chunk) on_chunk(c);
     }
-    return "";
+    return err;
 }
 
 }  // namespace qsv

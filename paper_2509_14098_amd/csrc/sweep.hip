@@ -89,7 +89,8 @@ static hipError_t launch_sweep_t(const Plan &plan, int pidx, float2 *psi, float2
 
 bool kernel_shape_supported(int R, int LW)
 {
-    return (LW == 6 && R >= 1 && R <= 5) || (LW == 8 && R >= 3 && R <= 5) || (LW == 9 && (R == 4 || R == 5)) || (LW == 10 && R == 4);
+    return (LW == 6 && R >= 1 && R <= 5) || (LW == 8 && R >= 3 && R <= 5) || (LW == 9 && R >= 3 && R <= 5) ||
+           (LW == 10 && (R == 3 || R == 4));
 }
 
 hipError_t launch_sweep(const Plan &plan, int R, int LW, int pidx, float2 *psi, float2 *ckpt, hipStream_t s)
@@ -98,7 +99,7 @@ hipError_t launch_sweep(const Plan &plan, int R, int LW, int pidx, float2 *psi, 
     if (R == r && LW == lw) return launch_sweep_t<r, lw>(plan, pidx, psi, ckpt, s);
     QSV_CASE(1, 6) QSV_CASE(2, 6) QSV_CASE(3, 6) QSV_CASE(4, 6) QSV_CASE(5, 6)
     QSV_CASE(3, 8) QSV_CASE(4, 8) QSV_CASE(5, 8)
-    QSV_CASE(4, 9) QSV_CASE(5, 9) QSV_CASE(4, 10)
+    QSV_CASE(3, 9) QSV_CASE(4, 9) QSV_CASE(5, 9) QSV_CASE(3, 10) QSV_CASE(4, 10)
 #undef QSV_CASE
     return hipErrorInvalidValue;
 }

@@ -32,6 +32,10 @@ class Plan:
                 return out
             p += 1
 
+    def refresh(self):
+        self.info = B.qsv_plan_info(self.handle)
+        return self.info
+
     def close(self):
         if self.handle is not None:
             B.qsv_plan_destroy(self.handle)
@@ -60,6 +64,11 @@ class Simulator:
         secs = B.qsv_plan_specialise(self.ctx, plan.handle)
         plan.info = B.qsv_plan_info(plan.handle)
         return secs
+
+    def specialise_async(self, plan: Plan) -> None:
+        """Compile the plan's specialised kernels in the background; applies
+        switch to them once loaded (plan.refresh() shows when)."""
+        B.qsv_plan_specialise_async(self.ctx, plan.handle)
 
     def zero_state(self, n_qubits, batch=1):
         psi = torch.zeros((batch, 1 << n_qubits) if batch > 1 else (1 << n_qubits,), dtype=torch.complex64,

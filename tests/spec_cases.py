@@ -8,4 +8,4 @@ RANDOM_CASES = [(3, 60, 2, (3, 6)), (7, 100, 5, (4, 6)), (11, 200, 7, (4, 8)), (
 
 # every kernel shape whose tile fits 64 KiB of LDS (at most 13 qubits):
 # (reg_qubits, log_threads) -> a circuit on reg_qubits + log_threads + 2 qubits
-SHAPES = [(1, 6), (2, 6), (3, 6), (4, 6), (5, 6), (3, 8), (4, 8), (5, 8), (4, 9)]
+SHAPES = [(1, 6), (2, 6), (3, 6), (4, 6), (5, 6), (3, 8), (4, 8), (5, 8), (3, 9), (4, 9), (3, 10)]

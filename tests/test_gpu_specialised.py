@@ -317,3 +317,66 @@ def test_specialise_errors(sim):
         assert e.value.code == -5
     finally:
         Q.qsv_plan_destroy(host)
+
+
+def test_specialise_async_switches_during_applies(sim):
+    """qsv_plan_specialise_async: applies run at once (table-driven while the
+    compile is pending, specialised sweeps once it has finished, possibly
+    within one apply); every state equals the oracle's, the plan ends up
+    specialised, and qsv_plan_specialise then returns without compiling."""
+    n = 24
+    gates = W.brickwork_c3(n=n, layers=30, seed=21)
+    ref = oracle.apply(n, gates)
+    plan = sim.partition(n, gates, 10, 0, (4, 9))
+    try:
+        sim.specialise_async(plan)
+        seen = set()
+        for _ in range(400):  # bounded: the compile takes seconds, an apply milliseconds
+            psi = sim.zero_state(n)
+            sim.apply(plan, psi)
+            torch.cuda.synchronize()
+            assert maxabs(psi.cpu().numpy(), ref) <= TOL
+            spec = plan.refresh()["specialised"]
+            seen.add(spec)
+            if spec:
+                break
+        if not plan.info["specialised"]:
+            sim.specialise(plan)  # waits for the compile
+        assert plan.refresh()["specialised"] == 1
+        psi = sim.zero_state(n)
+        sim.apply(plan, psi)
+        torch.cuda.synchronize()
+        assert maxabs(psi.cpu().numpy(), ref) <= TOL
+        print(f"async specialise: table-driven applies seen {0 in seen}", flush=True)
+    finally:
+        plan.close()
+
+
+def test_specialise_async_gradient_and_destroy_while_pending(sim):
+    """A gradient plan specialised in the background gives the oracle's
+    gradient before and after its kernels arrive; a plan destroyed while its
+    compile runs waits for it."""
+    n = 12
+    gates, npar = W.ansatz(n, 4)
+    theta = W.ansatz_params(npar, seed=8)
+    H = W.zz_chain_plus_x(n, 0.5)
+    e_ref, g_ref = oracle.adjoint(n, gates, theta, H)
+    plan = sim.partition(n, gates, 8, Q.PLAN_GRAD, (3, 6))
+    th = sim.theta(theta)
+    try:
+        sim.specialise_async(plan)
+        for _ in range(2):
+            psi = sim.zero_state(n)
+            ckpt = sim.checkpoints(plan)
+            sim.apply(plan, psi, th, ckpt)
+            e, g = sim.adjoint_grad(plan, H, th, psi, ckpt)
+            torch.cuda.synchronize()
+            assert abs(float(e[0]) - e_ref) < 1e-5
+            assert float(np.max(np.abs(g.cpu().numpy() - g_ref))) < 1e-4
+            sim.specialise(plan)
+            assert plan.refresh()["specialised"] == 1
+    finally:
+        plan.close()
+    other = sim.partition(n, gates, 8, Q.PLAN_GRAD, (3, 6))
+    sim.specialise_async(other)
+    other.close()  # joins the pending compile

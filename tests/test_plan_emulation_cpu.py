@@ -52,7 +52,7 @@ def emu(tmp_path_factory):
     return run
 
 
-SHAPES = [(1, 6), (2, 6), (3, 6), (4, 6), (5, 6), (3, 8), (4, 8), (5, 8), (4, 9), (5, 9), (4, 10)]
+SHAPES = [(1, 6), (2, 6), (3, 6), (4, 6), (5, 6), (3, 8), (4, 8), (5, 8), (3, 9), (4, 9), (5, 9), (3, 10), (4, 10)]
 
 
 @pytest.mark.parametrize("R,LW", SHAPES)
