@@ -48,8 +48,8 @@ __global__ __launch_bounds__(1 << LW) void reverse_kernel(const float2 *__restri
         float2 a[NA], l[NA];
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
-            a[i] = active ? lds_psi[toff ^ roff[i]] : float2{0.f, 0.f};
-            l[i] = active ? lds_lam[toff ^ roff[i]] : float2{0.f, 0.f};
+            a[i] = active ? lds_ref(lds_psi, toff ^ roff[i]) : float2{0.f, 0.f};
+            l[i] = active ? lds_ref(lds_lam, toff ^ roff[i]) : float2{0.f, 0.f};
         }
         for (int k = S->op_end - 1; k >= S->op_begin; --k) {
             const DevOp o = ops[k];
@@ -63,8 +63,8 @@ __global__ __launch_bounds__(1 << LW) void reverse_kernel(const float2 *__restri
             asm volatile("" : "+v"(toff));  // recompute the write-back addresses instead of keeping 2^R live
 #pragma unroll
             for (int i = 0; i < NA; ++i) {
-                lds_psi[toff ^ roff[i]] = a[i];
-                lds_lam[toff ^ roff[i]] = l[i];
+                lds_ref(lds_psi, toff ^ roff[i]) = a[i];
+                lds_ref(lds_lam, toff ^ roff[i]) = l[i];
             }
         }
         __syncthreads();

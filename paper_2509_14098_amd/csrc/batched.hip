@@ -49,12 +49,12 @@ __device__ __forceinline__ void remap(float2 (&v)[1 << R], float2 *lds, bool act
     __syncthreads();
     if (active) {
 #pragma unroll
-        for (int i = 0; i < (1 << R); ++i) lds[toff ^ roff[i]] = v[i];
+        for (int i = 0; i < (1 << R); ++i) lds_ref(lds, toff ^ roff[i]) = v[i];
     }
     __syncthreads();
     if (active) {
 #pragma unroll
-        for (int i = 0; i < (1 << R); ++i) v[i] = lds[toff2 ^ roff2[i]];
+        for (int i = 0; i < (1 << R); ++i) v[i] = lds_ref(lds, toff2 ^ roff2[i]);
     }
 }
 
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(1 << LW) void batched_kernel(
             a[i] = float2{0.f, 0.f};
             l[i] = float2{0.f, 0.f};
             if (active) {
-                const uint32_t sx = toff ^ roff[i];  // swizzled slot of amplitude x
+                const uint32_t sx = (toff ^ roff[i]) >> 3;  // swizzled slot of amplitude x
                 const uint32_t x = swz(sx);          // swz is an involution here: recovers x
                 a[i] = lds[sx];
                 double lr = 0.0, li = 0.0;

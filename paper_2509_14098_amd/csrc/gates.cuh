@@ -707,21 +707,28 @@ __device__ __forceinline__ double wave_sum(double v)
 // are swizzled in scalar registers.
 __device__ __forceinline__ uint32_t swz(uint32_t c) { return c ^ ((c >> 5) & 31u) ^ ((c >> 10) & 31u); }
 
-// Swizzled LDS offsets of a stage layout: the thread's own part and the
-// register-index parts (uniform).
+// Swizzled LDS byte offsets of a stage layout: the thread's own part and the
+// register-index parts (uniform).  An amplitude's slot is at byte toff ^ roff[i]
+// (lds_ref): in bytes, so that each access costs one XOR and no shift.
 template <int R>
 __device__ __forceinline__ void stage_offsets(const DevStage *__restrict__ S, int w, uint32_t tid, uint32_t &toff,
                                               uint32_t (&roff)[1 << R])
 {
     uint32_t t = 0;
     for (int b = 0; b < w; ++b) t |= ((tid >> b) & 1u) << S->thrpos[b];
-    toff = swz(t);
+    toff = swz(t) << 3;
     uint32_t r[1 << R];
     r[0] = 0;
 #pragma unroll
     for (int i = 1; i < (1 << R); ++i) r[i] = r[i & (i - 1)] | (1u << S->regpos[__builtin_ctz(i)]);
 #pragma unroll
-    for (int i = 0; i < (1 << R); ++i) roff[i] = swz(r[i]);
+    for (int i = 0; i < (1 << R); ++i) roff[i] = swz(r[i]) << 3;
+}
+
+// The LDS slot at a byte offset.
+__device__ __forceinline__ float2 &lds_ref(float2 *lds, uint32_t byte)
+{
+    return *reinterpret_cast<float2 *>(reinterpret_cast<char *>(lds) + byte);
 }
 
 // Run the register stages [s0, s1) of a tile held in LDS.
@@ -739,11 +746,11 @@ __device__ __forceinline__ void run_stages(float2 *lds, const DevStage *__restri
             stage_offsets<R>(S, w, tid, toff, roff);
             float2 a[NA];
 #pragma unroll
-            for (int i = 0; i < NA; ++i) a[i] = lds[toff ^ roff[i]];
+            for (int i = 0; i < NA; ++i) a[i] = lds_ref(lds, toff ^ roff[i]);
             for (int k = S->op_begin; k < S->op_end; ++k) apply_op<R, DAG>(a, ops[k], pool, tid, base);
             asm volatile("" : "+v"(toff));  // recompute the write-back addresses instead of keeping 2^R live
 #pragma unroll
-            for (int i = 0; i < NA; ++i) lds[toff ^ roff[i]] = a[i];
+            for (int i = 0; i < NA; ++i) lds_ref(lds, toff ^ roff[i]) = a[i];
         }
         __syncthreads();
     }

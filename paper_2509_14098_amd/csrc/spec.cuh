@@ -110,13 +110,12 @@ __device__ __forceinline__ void spec_stage(float2 *lds, const float *__restrict_
         stage_offsets<R>(&T::stages[S], w, tid, toff, roff);
         float2 a[NA];
 #pragma unroll
-        for (int i = 0; i < NA; ++i) a[i] = lds[toff ^ roff[i]];
+        for (int i = 0; i < NA; ++i) a[i] = lds_ref(lds, toff ^ roff[i]);
         static_for<T::stages[S].op_begin, T::stages[S].op_end>([&](auto K) __attribute__((always_inline)) {
             spec_op<T, std::decay_t<decltype(K)>::value, false>(dpool, tid, base, a);
         });
-        asm volatile("" : "+v"(toff));  // recompute the write-back addresses instead of keeping 2^R live
 #pragma unroll
-        for (int i = 0; i < NA; ++i) lds[toff ^ roff[i]] = a[i];
+        for (int i = 0; i < NA; ++i) lds_ref(lds, toff ^ roff[i]) = a[i];
     }
     __syncthreads();
 }
@@ -179,8 +178,8 @@ __device__ __forceinline__ void spec_reverse_stage(float2 *lds_psi, float2 *lds_
     float2 a[NA], l[NA];
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
-        a[i] = active ? lds_psi[toff ^ roff[i]] : float2{0.f, 0.f};
-        l[i] = active ? lds_lam[toff ^ roff[i]] : float2{0.f, 0.f};
+        a[i] = active ? lds_ref(lds_psi, toff ^ roff[i]) : float2{0.f, 0.f};
+        l[i] = active ? lds_ref(lds_lam, toff ^ roff[i]) : float2{0.f, 0.f};
     }
     static_for<0, k1 - k0>([&](auto J) __attribute__((always_inline)) {
         constexpr int K = k1 - 1 - std::decay_t<decltype(J)>::value;
@@ -191,11 +190,10 @@ __device__ __forceinline__ void spec_reverse_stage(float2 *lds_psi, float2 *lds_
         spec_op<T, K, true>(dpool, tid, base, a, l);
     });
     if (active) {
-        asm volatile("" : "+v"(toff));  // recompute the write-back addresses instead of keeping 2^R live
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
-            lds_psi[toff ^ roff[i]] = a[i];
-            lds_lam[toff ^ roff[i]] = l[i];
+            lds_ref(lds_psi, toff ^ roff[i]) = a[i];
+            lds_ref(lds_lam, toff ^ roff[i]) = l[i];
         }
     }
     __syncthreads();

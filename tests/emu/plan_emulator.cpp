@@ -38,12 +38,12 @@ static void run_part(const Plan &P, int pidx, std::vector<float2> &psi, const st
                 uint32_t toff, roff[1 << R];
                 stage_offsets<R>(&S, w, tid, toff, roff);
                 float2 a[1 << R];
-                for (int i = 0; i < (1 << R); ++i) a[i] = lds[toff ^ roff[i]];
+                for (int i = 0; i < (1 << R); ++i) a[i] = lds_ref(lds.data(), toff ^ roff[i]);
                 if (!DAG)
                     for (int k = S.op_begin; k < S.op_end; ++k) apply_op<R, false>(a, P.ops[k], pool.data(), tid, base);
                 else
                     for (int k = S.op_end - 1; k >= S.op_begin; --k) apply_op<R, true>(a, P.ops[k], pool.data(), tid, base);
-                for (int i = 0; i < (1 << R); ++i) lds[toff ^ roff[i]] = a[i];
+                for (int i = 0; i < (1 << R); ++i) lds_ref(lds.data(), toff ^ roff[i]) = a[i];
             }
         }
         for (uint32_t c = 0; c < (1u << t); ++c) psi[gidx(c)] = lds[swz(c)];
