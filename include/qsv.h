@@ -301,6 +301,8 @@ qsv_status qsv_apply(qsv_ctx *ctx, const qsv_plan *plan, const double *theta_dev
  * Expectation values out_b = sum_t coeff_t <psi_b|P_t|psi_b> for b < batch,
  * computed with float64 accumulation into out_dev (float64[batch], device).
  * H = one term with empty masks and coeff 1 gives the squared norm.
+ * The context keeps the grouped tables of the last sum on the device: a call
+ * with the same terms (byte for byte) and n_qubits skips grouping and upload.
  * Errors: QSV_E_ARG (n_qubits out of range, masks beyond n_qubits, nulls).
  */
 qsv_status qsv_expect(qsv_ctx *ctx, const qsv_pauli_term *H, int32_t n_terms, int32_t n_qubits, int64_t batch,

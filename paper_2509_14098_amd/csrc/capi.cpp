@@ -114,6 +114,15 @@ struct qsv_ctx {
     size_t lam_bytes = 0;
     void *terms_dev = nullptr;
     size_t terms_bytes = 0;
+    // qsv_expect: the tables of the last sum, kept on the device while the
+    // same terms come again (key: n and the term records)
+    void *expect_dev = nullptr;
+    size_t expect_bytes = 0;
+    std::string expect_key;
+    DevPass *expect_dp = nullptr;
+    DevGroup *expect_dg = nullptr;
+    DevTerm *expect_dt = nullptr;
+    int expect_np = 0;
     void *pinned = nullptr;
     size_t pinned_bytes = 0;
     hipEvent_t pinned_ready = nullptr;
@@ -179,7 +188,7 @@ static DevTerm dev_term(const qsv_pauli_term &h)
     d.cim = ny == 1 ? c : ny == 3 ? -c : 0.0;
     d.z_mask = h.z_mask;
     d.zt = 0;
-    d.pad = 0;
+    d.slot = 0;
     return d;
 }
 
@@ -254,8 +263,10 @@ static TermLayout term_layout(size_t n_passes, size_t n_groups, size_t n_terms)
     return L;
 }
 
-// Upload grouped terms (and passes) into the context (pinned staging + async copy).
-static void upload_groups(qsv_ctx *ctx, const HostGroups &g, DevPass *&dpasses, DevGroup *&dgroups, DevTerm *&dterms)
+// Upload grouped terms (and passes) into a device buffer of the context
+// (pinned staging + async copy): terms_dev unless another is given.
+static void upload_groups(qsv_ctx *ctx, const HostGroups &g, DevPass *&dpasses, DevGroup *&dgroups, DevTerm *&dterms,
+                          void **buf = nullptr, size_t *buf_bytes = nullptr)
 {
     const TermLayout L = term_layout(g.passes.size(), g.groups.size(), g.terms.size());
     const size_t need = L.end + 64;
@@ -266,7 +277,7 @@ static void upload_groups(qsv_ctx *ctx, const HostGroups &g, DevPass *&dpasses, 
         if (hipHostMalloc(&ctx->pinned, need) != hipSuccess) fail(QSV_E_NOMEM, "pinned allocation failed");
         ctx->pinned_bytes = need;
     }
-    char *dev = (char *)ctx->ensure(ctx->terms_dev, ctx->terms_bytes, need);
+    char *dev = buf ? (char *)ctx->ensure(*buf, *buf_bytes, need) : (char *)ctx->ensure(ctx->terms_dev, ctx->terms_bytes, need);
     char *h = (char *)ctx->pinned;
     if (!g.passes.empty()) std::memcpy(h, g.passes.data(), g.passes.size() * sizeof(DevPass));
     if (!g.groups.empty()) std::memcpy(h + L.groups, g.groups.data(), g.groups.size() * sizeof(DevGroup));
@@ -319,6 +330,7 @@ qsv_status qsv_destroy(qsv_ctx *ctx)
         dev_free(ctx->scratch);
         dev_free(ctx->lam);
         dev_free(ctx->terms_dev);
+        dev_free(ctx->expect_dev);
         dev_free(ctx->queue);
         dev_free(ctx->wg_clock);
         if (ctx->pinned) (void)hipHostFree(ctx->pinned);
@@ -1053,17 +1065,28 @@ qsv_status qsv_expect(qsv_ctx *ctx, const qsv_pauli_term *H, int32_t n_terms, in
         if (!ctx || !psi_dev || !out_dev) fail(QSV_E_ARG, "null argument");
         if (n_qubits < 1 || n_qubits > MAX_DEVICE_QUBITS) fail(QSV_E_ARG, "n_qubits must be in [1, 35]");
         if (batch < 1) fail(QSV_E_ARG, "batch must be >= 1");
-        HostGroups g = group_terms(H, n_terms, n_qubits, true);
+        check_terms(H, n_terms, n_qubits);
         hip_check(hipSetDevice(ctx->device), "hipSetDevice");
-        size_t need = sizeof(double) * (size_t)expect_blocks(n_qubits) * std::max<size_t>(1, g.passes.size()) *
+        // the same sum as the last call: its tables are still on the device
+        std::string key((const char *)H, sizeof(qsv_pauli_term) * (size_t)std::max(0, n_terms));
+        key.append((const char *)&n_qubits, sizeof n_qubits);
+        if (key != ctx->expect_key) {
+            ctx->expect_key.clear();
+            HostGroups g = group_terms(H, n_terms, n_qubits, true);
+            ctx->expect_dp = nullptr;
+            ctx->expect_dg = nullptr;
+            ctx->expect_dt = nullptr;
+            if (!g.groups.empty())
+                upload_groups(ctx, g, ctx->expect_dp, ctx->expect_dg, ctx->expect_dt, &ctx->expect_dev,
+                              &ctx->expect_bytes);
+            ctx->expect_np = (int)g.passes.size();
+            ctx->expect_key = std::move(key);
+        }
+        size_t need = sizeof(double) * (size_t)expect_blocks(n_qubits) * std::max<size_t>(1, ctx->expect_np) *
                       (size_t)batch;
         double *partials = (double *)ctx->ensure(ctx->scratch, ctx->scratch_bytes, need);
-        DevPass *dp = nullptr;
-        DevGroup *dg = nullptr;
-        DevTerm *dt = nullptr;
-        if (!g.groups.empty()) upload_groups(ctx, g, dp, dg, dt);
-        hip_check(launch_expect(dp, (int)g.passes.size(), dg, dt, n_qubits, batch, (const float2 *)psi_dev, partials,
-                                out_dev, ctx->stream),
+        hip_check(launch_expect(ctx->expect_dp, ctx->expect_np, ctx->expect_dg, ctx->expect_dt, n_qubits, batch,
+                                (const float2 *)psi_dev, partials, out_dev, ctx->stream),
                   "expect launch");
     });
 }

@@ -13,12 +13,15 @@
 // the 21 groups take two passes.)  A group whose mask does not fit a tile
 // with the low qubits reads its partners from HBM.  Products are formed and
 // accumulated in float64; block sums go to a partials array and a second
-// kernel adds them in a fixed order, so results do not depend on timing.
+// kernel adds them in a fixed order, so results do not depend on timing.  (A
+// last-workgroup-sums variant in one launch was slower: the release fence each
+// workgroup needs before its ticket writes back its XCD's L2.)
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <mutex>
 
+#include "gates.cuh"
 #include "kernels.h"
 
 namespace qsv {
@@ -42,13 +45,32 @@ __device__ __forceinline__ double block_sum(double v, double *sh)
 
 __device__ __forceinline__ double parity_sign(uint64_t v) { return (__popcll(v) & 1) ? -1.0 : 1.0; }
 
+// A table record read by every lane alike (from LDS, into vector registers),
+// moved to scalar registers: its fields then steer uniform branches and loops.
+template <class T>
+__device__ __forceinline__ T uniform(const T &x)
+{
+    static_assert(sizeof(T) % 4 == 0, "32-bit words");
+    uint32_t w[sizeof(T) / 4];
+    __builtin_memcpy(w, &x, sizeof(T));
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+    T r;
+    __builtin_memcpy(&r, w, sizeof(T));
+    return r;
+}
+
 // One launch covers every pass: workgroup (x, pass, b) walks tiles x, x +
 // gridDim.x, ... of state b with the pass's tile qubits.  A thread holds 8
 // amplitude pairs of the tile (positions 2 tid + j + 1024 it, j < 2, it < 4),
 // read as 16-byte pairs (qubit 0 is always a tile qubit).  Partner amplitudes
 // of the pass's X/Y groups come from the LDS copy of the tile, those of wide
-// groups (masks that do not fit a tile with the low qubits) from HBM.
+// groups (masks that do not fit a tile with the low qubits) from HBM.  The
+// pass's group and term tables are copied to LDS first when they fit: on a
+// small state a workgroup sees one tile, and reading them from memory group by
+// group would put one memory latency per group on its critical path.
 // partials[(b * n_passes + pass) * gridDim.x + block]
+template <bool SMALL>
 __global__ __launch_bounds__(EXPECT_THREADS) void expect_kernel(const DevPass *__restrict__ passes, int p0,
                                                               int n_passes, const DevGroup *__restrict__ groups,
                                                               const DevTerm *__restrict__ terms, int n,
@@ -57,7 +79,9 @@ __global__ __launch_bounds__(EXPECT_THREADS) void expect_kernel(const DevPass *_
 {
     typedef float nf4 __attribute__((ext_vector_type(4)));  // a vector type the builtin accepts
     __shared__ float4 lds4[(1 << EXPECT_TILE_QUBITS) / 2];
-    __shared__ double sh[EXPECT_THREADS];
+    __shared__ DevGroup s_groups[EXPECT_LDS_GROUPS];
+    __shared__ DevTerm s_terms[EXPECT_LDS_TERMS];
+    __shared__ double s_wave[EXPECT_THREADS / 64];
     const float2 *lds = reinterpret_cast<const float2 *>(lds4);
     const int pi = p0 + (int)blockIdx.y;
     const DevPass PS = passes[pi];
@@ -66,6 +90,15 @@ __global__ __launch_bounds__(EXPECT_THREADS) void expect_kernel(const DevPass *_
     const uint32_t tid = threadIdx.x;
     const int t = n < EXPECT_TILE_QUBITS ? n : EXPECT_TILE_QUBITS;
     const uint32_t tdim = 1u << t;
+    int t_base = 0;  // index of the pass's first term
+    if (PS.staged) {
+        const int ng = PS.g_end - PS.g_begin;
+        t_base = groups[PS.g_begin].term_begin;
+        const int nt = groups[PS.g_end - 1].term_end - t_base;
+        for (int i = (int)tid; i < ng; i += EXPECT_THREADS) s_groups[i] = groups[PS.g_begin + i];
+        for (int i = (int)tid; i < nt; i += EXPECT_THREADS) s_terms[i] = terms[t_base + i];
+        __syncthreads();
+    }
     // the qubit (as a one-bit mask) at each tile position, in increasing order
     uint64_t posbit[EXPECT_TILE_QUBITS];
     {
@@ -106,8 +139,12 @@ __global__ __launch_bounds__(EXPECT_THREADS) void expect_kernel(const DevPass *_
             x[it] = base | xthr | row[it];
             v[it] = float4{0.f, 0.f, 0.f, 0.f};
             if (2 * tid + ROW * it < tdim) {
-                const nf4 w = __builtin_nontemporal_load(reinterpret_cast<const nf4 *>(s + x[it]));
-                v[it] = float4{w.x, w.y, w.z, w.w};
+                if (SMALL) {  // a state that stays in the caches (read by several passes)
+                    v[it] = *reinterpret_cast<const float4 *>(s + x[it]);
+                } else {
+                    const nf4 w = __builtin_nontemporal_load(reinterpret_cast<const nf4 *>(s + x[it]));
+                    v[it] = float4{w.x, w.y, w.z, w.w};
+                }
             }
         }
         if (PS.has_x) {
@@ -117,78 +154,124 @@ __global__ __launch_bounds__(EXPECT_THREADS) void expect_kernel(const DevPass *_
                 if (2 * tid + ROW * it < tdim) lds4[tid + EXPECT_THREADS * it] = v[it];
             __syncthreads();
         }
-        for (int g = PS.g_begin; g < PS.g_end; ++g) {
-            const DevGroup G = groups[g];
-            if (G.x_mask == 0) {
-                // diagonal group: the 8 weights with the term loop outside (8
-                // independent float64 sums); each weight adds its terms in order
-                double w[2 * EXPECT_PAIRS];
+        // the pass's groups g0..g1 of the tables GP (group g at GP[g - g0]) and
+        // TP (term k at TP[k - tb])
+        auto walk = [&](const DevGroup *__restrict__ GP, const DevTerm *__restrict__ TP, int tb) {
+            for (int g = 0; g < PS.g_end - PS.g_begin; ++g) {
+                const DevGroup G = uniform(GP[g]);
+                if (G.x_mask == 0) {
+                    // diagonal group: the weight w(x) = sum_t c_t (-1)^{|x & z_t|} of
+                    // each of the thread's 8 amplitudes.  With x = base | 2 tid | slot
+                    // u (u's bits at tile positions 0, 10, 11), the sign splits into
+                    // a per-thread part and chi_t(u) = (-1)^{|u & slot_t|}.  The terms
+                    // come sorted by slot_t: a_S = sum of c_t (-1)^{|(base | 2 tid) &
+                    // z_t|} over the terms with slot S, then w(u) += chi_S(u) a_S.
+                    // A term costs a few vector instructions; each of the at most 8
+                    // patterns, 8 additions.
+                    double w[2 * EXPECT_PAIRS];
 #pragma unroll
-                for (int u = 0; u < 2 * EXPECT_PAIRS; ++u) w[u] = 0.0;
-                for (int k = G.term_begin; k < G.term_end; ++k) {
-                    const double c = terms[k].cre;
-                    const uint64_t zm = terms[k].z_mask;
+                    for (int u = 0; u < 2 * EXPECT_PAIRS; ++u) w[u] = 0.0;
+                    auto flush = [&](int pat, double a) {
+#pragma unroll
+                        for (int u = 0; u < 2 * EXPECT_PAIRS; ++u) w[u] += (__popc(pat & u) & 1) ? -a : a;
+                    };
+                    int pat = -1;
+                    double a = 0.0;
+                    for (int k = G.term_begin; k < G.term_end; ++k) {
+                        const DevTerm &T = TP[k - tb];
+                        const int ts = __builtin_amdgcn_readfirstlane(T.slot);
+                        if (ts != pat) {
+                            if (pat >= 0) flush(pat, a);
+                            pat = ts;
+                            a = 0.0;
+                        }
+                        const uint32_t par = (__popcll(base & T.z_mask) + __popc((2u * tid) & T.zt)) & 1u;
+                        a += par ? -T.cre : T.cre;
+                    }
+                    if (pat >= 0) flush(pat, a);
 #pragma unroll
                     for (int it = 0; it < EXPECT_PAIRS; ++it) {
-                        w[2 * it] += c * parity_sign(x[it] & zm);
-                        w[2 * it + 1] += c * parity_sign((x[it] | 1ull) & zm);
+                        const double p0v = (double)v[it].x * v[it].x + (double)v[it].y * v[it].y;
+                        const double p1v = (double)v[it].z * v[it].z + (double)v[it].w * v[it].w;
+                        acc += p0v * w[2 * it] + p1v * w[2 * it + 1];
                     }
-                }
+                } else if (G.xt >= 0) {
+                    // partners in the LDS tile: the pairs (p0, p1 = p0 ^ xt) of tile
+                    // positions with bit lb of p0 clear, k = tid + 512 i enumerating
+                    // them; per term, with z = conj(psi_p1) psi_p0 and signs from
+                    // the term's Z mask on the tile (zt) and outside it (base):
+                    //   s0 Re[c z] + s1 Re[c conj(z)]
+                    const uint32_t xt = (uint32_t)G.xt;
+                    const int lb = __builtin_ctz(xt);
+                    const uint32_t below = (1u << lb) - 1;
+                    const DevTerm T0 = uniform(TP[G.term_begin - tb]);
+                    if (G.term_end - G.term_begin == 1 && T0.z_mask == 0 && T0.cim == 0.0) {
+                        // one real X string: 2 c Re z summed over the pairs
+                        double gz = 0.0;
 #pragma unroll
-                for (int it = 0; it < EXPECT_PAIRS; ++it) {
-                    const double p0v = (double)v[it].x * v[it].x + (double)v[it].y * v[it].y;
-                    const double p1v = (double)v[it].z * v[it].z + (double)v[it].w * v[it].w;
-                    acc += p0v * w[2 * it] + p1v * w[2 * it + 1];
-                }
-            } else if (G.xt >= 0) {
-                // partners in the LDS tile: the pairs (p0, p1 = p0 ^ xt) of tile
-                // positions with bit lb of p0 clear, k = tid + 512 i enumerating
-                // them; per term, with z = conj(psi_p1) psi_p0 and signs from
-                // the term's Z mask on the tile (zt) and outside it (base):
-                //   s0 Re[c z] + s1 Re[c conj(z)]
-                const uint32_t xt = (uint32_t)G.xt;
-                const int lb = __builtin_ctz(xt);
-                const uint32_t below = (1u << lb) - 1;
-#pragma unroll
-                for (int i = 0; i < EXPECT_PAIRS; ++i) {
-                    const uint32_t k = tid + (uint32_t)EXPECT_THREADS * i;
-                    if (k >= (tdim >> 1)) continue;
-                    const uint32_t p0 = ((k >> lb) << (lb + 1)) | (k & below);
-                    const float2 a = lds[p0], c = lds[p0 ^ xt];
-                    const double zr = (double)c.x * a.x + (double)c.y * a.y;
-                    const double zi = (double)c.x * a.y - (double)c.y * a.x;
-                    for (int q = G.term_begin; q < G.term_end; ++q) {
-                        const DevTerm T = terms[q];
-                        const uint32_t s0 = (__popc(p0 & T.zt) + __popcll(base & T.z_mask)) & 1u;
-                        const uint32_t s1 = s0 ^ (__popc(xt & T.zt) & 1u);
-                        const double re = T.cre * zr - T.cim * zi, rc = T.cre * zr + T.cim * zi;
-                        acc += (s0 ? -re : re) + (s1 ? -rc : rc);
+                        for (int i = 0; i < EXPECT_PAIRS; ++i) {
+                            const uint32_t k = tid + (uint32_t)EXPECT_THREADS * i;
+                            if (k >= (tdim >> 1)) continue;
+                            const uint32_t q0 = ((k >> lb) << (lb + 1)) | (k & below);
+                            const float2 a = lds[q0], c = lds[q0 ^ xt];
+                            gz += (double)c.x * a.x + (double)c.y * a.y;
+                        }
+                        acc += 2.0 * T0.cre * gz;
+                        continue;
                     }
-                }
-            } else {
-                // a wide group: partners from HBM, every amplitude x of the tile
-                //   sum_t Re[c_t (-1)^{|x & z_t|} conj(psi_{x ^ m}) psi_x]
 #pragma unroll
-                for (int it = 0; it < EXPECT_PAIRS; ++it) {
-                    if (2 * tid + ROW * it >= tdim) continue;
-#pragma unroll
-                    for (int j = 0; j < 2; ++j) {
-                        const float2 a = j ? float2{v[it].z, v[it].w} : float2{v[it].x, v[it].y};
-                        const uint64_t xj = x[it] | (uint64_t)j;
-                        const float2 c = s[xj ^ G.x_mask];
+                    for (int i = 0; i < EXPECT_PAIRS; ++i) {
+                        const uint32_t k = tid + (uint32_t)EXPECT_THREADS * i;
+                        if (k >= (tdim >> 1)) continue;
+                        const uint32_t q0 = ((k >> lb) << (lb + 1)) | (k & below);
+                        const float2 a = lds[q0], c = lds[q0 ^ xt];
                         const double zr = (double)c.x * a.x + (double)c.y * a.y;
                         const double zi = (double)c.x * a.y - (double)c.y * a.x;
                         for (int q = G.term_begin; q < G.term_end; ++q) {
-                            const DevTerm T = terms[q];
-                            acc += parity_sign(xj & T.z_mask) * (T.cre * zr - T.cim * zi);
+                            const DevTerm T = uniform(TP[q - tb]);
+                            const uint32_t s0 = (__popc(q0 & T.zt) + __popcll(base & T.z_mask)) & 1u;
+                            const uint32_t s1 = s0 ^ (__popc(xt & T.zt) & 1u);
+                            const double re = T.cre * zr - T.cim * zi, rc = T.cre * zr + T.cim * zi;
+                            acc += (s0 ? -re : re) + (s1 ? -rc : rc);
+                        }
+                    }
+                } else {
+                    // a wide group: partners from HBM, every amplitude x of the tile
+                    //   sum_t Re[c_t (-1)^{|x & z_t|} conj(psi_{x ^ m}) psi_x]
+#pragma unroll
+                    for (int it = 0; it < EXPECT_PAIRS; ++it) {
+                        if (2 * tid + ROW * it >= tdim) continue;
+#pragma unroll
+                        for (int j = 0; j < 2; ++j) {
+                            const float2 a = j ? float2{v[it].z, v[it].w} : float2{v[it].x, v[it].y};
+                            const uint64_t xj = x[it] | (uint64_t)j;
+                            const float2 c = s[xj ^ G.x_mask];
+                            const double zr = (double)c.x * a.x + (double)c.y * a.y;
+                            const double zi = (double)c.x * a.y - (double)c.y * a.x;
+                            for (int q = G.term_begin; q < G.term_end; ++q) {
+                                const DevTerm T = uniform(TP[q - tb]);
+                                acc += parity_sign(xj & T.z_mask) * (T.cre * zr - T.cim * zi);
+                            }
                         }
                     }
                 }
             }
-        }
+        };
+        if (PS.staged)
+            walk(s_groups, s_terms, t_base);
+        else
+            walk(groups + PS.g_begin, terms, 0);
     }
-    const double tot = block_sum<EXPECT_THREADS>(acc, sh);
-    if (threadIdx.x == 0) partials[((uint64_t)b * n_passes + pi) * gridDim.x + blockIdx.x] = tot;
+    // the workgroup's sum: waves in order
+    const double wv = wave_sum(acc);
+    if ((tid & 63) == 0) s_wave[tid >> 6] = wv;
+    __syncthreads();
+    if (tid == 0) {
+        double tot = 0.0;
+#pragma unroll
+        for (int i = 0; i < EXPECT_THREADS / 64; ++i) tot += s_wave[i];
+        partials[((uint64_t)b * n_passes + pi) * gridDim.x + blockIdx.x] = tot;
+    }
 }
 
 // out[b] = sum of per_batch partials, fixed order
@@ -279,14 +362,19 @@ int plan_expect_passes(int n, DevGroup *groups, int n_groups, DevTerm *terms, De
         P.g_begin = begin;
         P.g_end = end;
         P.has_x = 0;
-        P.pad = 0;
+        P.staged = 0;
         for (int g = begin; g < end; ++g) {
             DevGroup &G = groups[g];
             G.pad = 0;
             for (int k = G.term_begin; k < G.term_end; ++k) {
-                terms[k].zt = G.xt < 0 ? 0u : compress(S, terms[k].z_mask);
-                terms[k].pad = 0;
+                DevTerm &T = terms[k];
+                T.zt = G.xt < 0 ? 0u : compress(S, T.z_mask);
+                // bits of zt at the positions of a thread's 8 amplitudes (0, 10, 11)
+                T.slot = (int32_t)((T.zt & 1u) | ((T.zt >> 9) & 2u) | ((T.zt >> 9) & 4u));
             }
+            if (G.x_mask == 0)  // diagonal: terms of equal slot pattern together
+                std::stable_sort(terms + G.term_begin, terms + G.term_end,
+                                 [](const DevTerm &a, const DevTerm &b) { return a.slot < b.slot; });
             if (G.xt < 0) continue;  // wide: partners from HBM
             G.xt = (int32_t)compress(S, G.x_mask);
         }
@@ -327,9 +415,15 @@ int plan_expect_passes(int n, DevGroup *groups, int n_groups, DevTerm *terms, De
         np = total;
     }
     for (int p = 0; p < np; ++p) {
-        passes[p].has_x = 0;
-        for (int g = passes[p].g_begin; g < passes[p].g_end; ++g)
-            if (groups[g].x_mask && groups[g].xt >= 0) passes[p].has_x = 1;
+        DevPass &P = passes[p];
+        P.has_x = 0;
+        bool contiguous = true;  // the groups' terms form one run (they do for grouped sums)
+        for (int g = P.g_begin; g < P.g_end; ++g) {
+            if (groups[g].x_mask && groups[g].xt >= 0) P.has_x = 1;
+            if (g > P.g_begin && groups[g].term_begin != groups[g - 1].term_end) contiguous = false;
+        }
+        const int nt = groups[P.g_end - 1].term_end - groups[P.g_begin].term_begin;
+        P.staged = contiguous && P.g_end - P.g_begin <= EXPECT_LDS_GROUPS && nt <= EXPECT_LDS_TERMS;
     }
     return np;
 }
@@ -342,14 +436,14 @@ hipError_t launch_expect(const DevPass *passes, int n_passes, const DevGroup *gr
         return hipGetLastError();
     }
     const int nb = expect_blocks(n);
+    auto kernel = n <= EXPECT_CACHED_QUBITS ? expect_kernel<true> : expect_kernel<false>;
     const int64_t lim = 65535;  // grid y and z limits: passes and batches beyond them go in chunks
     for (int64_t b0 = 0; b0 < batch; b0 += lim) {
         const int64_t nz = std::min<int64_t>(lim, batch - b0);
         for (int p0 = 0; p0 < n_passes; p0 += (int)lim) {
             const int ny = (int)std::min<int64_t>(lim, n_passes - p0);
-            hipLaunchKernelGGL(expect_kernel, dim3(nb, ny, (uint32_t)nz), dim3(EXPECT_THREADS), 0, s, passes, p0,
-                               n_passes, groups, terms, n, psi + ((uint64_t)b0 << n),
-                               partials + (uint64_t)b0 * n_passes * nb);
+            hipLaunchKernelGGL(kernel, dim3(nb, ny, (uint32_t)nz), dim3(EXPECT_THREADS), 0, s, passes, p0, n_passes,
+                               groups, terms, n, psi + ((uint64_t)b0 << n), partials + (uint64_t)b0 * n_passes * nb);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }

@@ -15,7 +15,7 @@ struct DevTerm {
     double cre, cim;      // coeff * i^{#Y}
     uint64_t z_mask;
     uint32_t zt;          // expectation passes: the Z/Y mask on the pass's tile positions
-    int32_t pad;
+    int32_t slot;         // expectation passes, diagonal groups: zt's bits at tile positions 0, 10, 11 (3 bits)
 };
 struct DevGroup {
     uint64_t x_mask;
@@ -28,7 +28,7 @@ struct DevPass {
     uint64_t tile_mask;
     int32_t g_begin, g_end;
     int32_t has_x;        // a group needs partner amplitudes from the LDS tile
-    int32_t pad;
+    int32_t staged;       // its groups and terms fit EXPECT_LDS_GROUPS / EXPECT_LDS_TERMS (read from LDS copies)
 };
 
 // expect.hip
@@ -37,7 +37,10 @@ constexpr int EXPECT_LOG_THREADS = 9;   // 512 threads per workgroup
 constexpr int EXPECT_THREADS = 1 << EXPECT_LOG_THREADS;
 constexpr int EXPECT_PAIRS = (1 << EXPECT_TILE_QUBITS) / (2 * EXPECT_THREADS);  // amplitude pairs per thread: 4
 constexpr int EXPECT_MAX_BLOCKS = 1024; // workgroups per (pass, batch entry)
-constexpr int EXPECT_MIN_BLOCKS = 2048; // passes are split by groups until they fill this many workgroups
+constexpr int EXPECT_MIN_BLOCKS = 512;  // passes are split by groups until they fill this many workgroups
+constexpr int EXPECT_LDS_GROUPS = 128;  // a pass's group and term tables are copied to LDS up to these sizes
+constexpr int EXPECT_LDS_TERMS = 256;
+constexpr int EXPECT_CACHED_QUBITS = 24;  // states up to 128 MiB are read through the caches (several passes)
 // Workgroups per (pass, batch entry): partial sums of launch_expect are
 // n_passes x expect_blocks(n) x batch doubles.
 int expect_blocks(int n);
