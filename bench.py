@@ -319,15 +319,11 @@ def bench_gradient(sim, args):
     return res
 
 
-def bench_batched(sim, args):
-    """2048 instances of the 14-qubit ansatz (depths U{4..16}), energy and
-    gradient of every instance in one persistent launch."""
-    n, B = 14, 2048
-    t0 = time.perf_counter()
-    plan, circs, thetas, H = batched_plan(sim, B, n)
-    plan_s = time.perf_counter() - t0
-    gates = np.concatenate(circs)
-    theta = torch.as_tensor(np.concatenate(thetas), device=sim.device)
+def batched_timings(sim, plan, theta, H, B, n):
+    """Forward (final states of every instance), adjoint from those states,
+    and forward + energy + adjoint from |0>, each averaged over 5 calls; the
+    load balance of one more forward and forward + energy + adjoint (each
+    workgroup's exit on the device clock, from the first workgroup's start)."""
     energy = torch.empty(B, dtype=torch.float64, device=sim.device)
     grad = torch.empty(len(theta), dtype=torch.float64, device=sim.device)
     psi = torch.empty((B, 1 << n), dtype=torch.complex64, device=sim.device)
@@ -343,13 +339,9 @@ def bench_batched(sim, args):
         sync()
         return (time.perf_counter() - t0) / reps
 
-    # forward (final states of every instance), adjoint from those states,
-    # and forward + energy + adjoint in one launch
     dtf = timed(lambda: Q.qsv_apply(sim.ctx, plan.handle, theta, psi))
     dtg = timed(lambda: Q.qsv_adjoint_grad(sim.ctx, plan.handle, H, theta, psi, None, energy, grad))
     dt = timed(lambda: Q.qsv_adjoint_grad(sim.ctx, plan.handle, H, theta, None, None, energy, grad))
-    # load balance of one more launch of each kind: each workgroup's exit on the
-    # device clock, from the first workgroup's start
     balance = {}
     Q.qsv_set_timing(sim.ctx, True)
     for kind, fn in (("forward", lambda: Q.qsv_apply(sim.ctx, plan.handle, theta, psi)),
@@ -364,19 +356,60 @@ def bench_batched(sim, args):
                                  mean_exit_ms=round(float(ends.mean()), 3), first_exit_ms=round(float(ends.min()), 3),
                                  tail_frac=round(float((ends.max() - ends.mean()) / ends.max()), 4))
     Q.qsv_set_timing(sim.ctx, False)
+    return dtf, dtg, dt, balance, energy, grad
+
+
+def start_batched_specialise(sim, B=2048, n=14):
+    """The batched plan of bench_batched, its specialised kernel compiling in
+    the background (helper process) while the other legs run."""
+    plan, circs, thetas, H = batched_plan(sim, B, n)
+    sim.specialise_async(plan)
+    return plan, circs, thetas, H, time.perf_counter()
+
+
+def bench_batched(sim, args, spec=None):
+    """2048 instances of the 14-qubit ansatz (depths U{4..16}), energy and
+    gradient of every instance.  Table-driven kernel, then (spec given) the
+    plan whose kernel specialised for its 13 circuit structures was compiled
+    in the background: its forward launches run specialised, the adjoint walk
+    table-driven from the forward's final states."""
+    n, B = 14, 2048
+    t0 = time.perf_counter()
+    plan, circs, thetas, H = batched_plan(sim, B, n)
+    plan_s = time.perf_counter() - t0
+    gates = np.concatenate(circs)
+    theta = torch.as_tensor(np.concatenate(thetas), device=sim.device)
+    dtf, dtg, dt, balance, energy, grad = batched_timings(sim, plan, theta, H, B, n)
     info = plan.info
     plan.close()
+    fwd_flops = algorithmic_flops(gates, n)  # every instance's gate list on its 2^n amplitudes
+    table = dict(forward_ms=round(dtf * 1e3, 3), grad_ms=round(dtg * 1e3, 3),
+                 fwd_energy_grad_ms=round(dt * 1e3, 3), forward_frac_of_fp32_peak=round(
+                     fwd_flops / dtf / 1e12 / FP32_VECTOR_PEAK, 4), load_balance=balance)
+    kernel = "table-driven"
+    spec_info = {}
+    if spec is not None:
+        splan, _, _, _, started = spec
+        t1 = time.perf_counter()
+        secs = sim.specialise(splan)  # waits for the background compile
+        spec_info = dict(specialise_s=round(secs, 2), waited_s=round(time.perf_counter() - t1, 2),
+                         started_s_before=round(t1 - started, 2))
+        dtf, dtg, dt, balance, energy, grad = batched_timings(sim, splan, theta, H, B, n)
+        splan.close()
+        kernel = "specialised forward (one kernel, every circuit structure compiled in), table-driven adjoint"
     offs = np.concatenate([[0], np.cumsum([len(t) for t in thetas])])
     n_check = 64  # instances compared with the oracle in the CPU leg
     e_np, g_np = energy.cpu().numpy(), grad.cpu().numpy()
     checked = dict(energy=e_np[:n_check], grad=[g_np[offs[b]:offs[b + 1]] for b in range(n_check)])
-    fwd_flops = algorithmic_flops(gates, n)  # every instance's gate list on its 2^n amplitudes
-    return dict(_checked=checked, instances=B, n_qubits=n, gates=int(len(gates)), params=int(len(theta)),
-                load_balance=balance, forward_alg_tflops=round(fwd_flops / dtf / 1e12, 2),
-                forward_frac_of_fp32_peak=round(fwd_flops / dtf / 1e12 / FP32_VECTOR_PEAK, 4),
-                forward_ms=round(dtf * 1e3, 3), grad_ms=round(dtg * 1e3, 3), grad_over_forward=round(dtg / dtf, 3),
-                fwd_energy_grad_ms=round(dt * 1e3, 3), fwd_energy_grad_over_forward=round(dt / dtf, 3),
-                instances_per_s=round(B / dt, 1), register_stages=info["n_stages"], plan_seconds=round(plan_s, 3))
+    res = dict(_checked=checked, instances=B, n_qubits=n, gates=int(len(gates)), params=int(len(theta)),
+               kernel=kernel, load_balance=balance, forward_alg_tflops=round(fwd_flops / dtf / 1e12, 2),
+               forward_frac_of_fp32_peak=round(fwd_flops / dtf / 1e12 / FP32_VECTOR_PEAK, 4),
+               forward_ms=round(dtf * 1e3, 3), grad_ms=round(dtg * 1e3, 3), grad_over_forward=round(dtg / dtf, 3),
+               fwd_energy_grad_ms=round(dt * 1e3, 3), fwd_energy_grad_over_forward=round(dt / dtf, 3),
+               instances_per_s=round(B / dt, 1), register_stages=info["n_stages"], plan_seconds=round(plan_s, 3))
+    if spec is not None:
+        res.update(spec_info, table_driven=table)
+    return res
 
 
 def bench_qft(sim, args):
@@ -668,6 +701,8 @@ def main():
               f"build", file=sys.stderr)
         sys.exit(2)
     sim = Q.Simulator(0)
+    # the batched plan's specialised kernel compiles in the background meanwhile
+    bspec = None if args.skip_batched or args.no_specialise else start_batched_specialise(sim)
     head = bench_headline(sim, args)
     info = head["plan"]
     value = head["step_bytes"] / (head["step_ms"] * 1e-3) / 1e9
@@ -735,7 +770,7 @@ def main():
         line["adjoint"] = {k: (round(v, 4) if isinstance(v, float) and not k.startswith("_") else v)
                            for k, v in bench_gradient(sim, args).items()}
     if not args.skip_batched:
-        line["batched"] = bench_batched(sim, args)
+        line["batched"] = bench_batched(sim, args, bspec)
     if not args.skip_gbg:
         line["qft"] = bench_qft(sim, args)
         line["distributed"] = bench_distributed(sim, args)

@@ -200,6 +200,15 @@ qsv_status qsv_plan_get_info(const qsv_plan *plan, qsv_plan_info *out);
  * kernel per partition, which qsv_adjoint_grad then launches; other plans
  * keep the table-driven reverse walk.  The forward it starts from (qsv_apply
  * with checkpoints) uses the specialised sweeps.
+ * Batched plans (several circuits): one program, holding a version of the
+ * persistent batched kernel with the register stages of every circuit
+ * structure compiled in (circuits with identical gate records share one;
+ * the kernel switches on a circuit's structure).  qsv_apply on the plan then
+ * launches it; qsv_adjoint_grad keeps the table-driven reverse walk, from the
+ * given final states or (psi_final NULL) from those of a specialised forward
+ * launch into a scratch batch of states.  Its compile grows with the total op
+ * count of the structures (about two minutes for 13 ansatz structures of 4-16
+ * layers on 14 qubits): qsv_plan_specialise_async overlaps it with other work.
  * ctx NULL: generate and compile only, load nothing (a check that needs no
  * GPU); the plan is unchanged.  The compile runs in the helper executable
  * qsv_rtc next to this library.  Environment: QSV_KERNEL_CACHE=<dir> keeps
@@ -207,9 +216,10 @@ qsv_status qsv_plan_get_info(const qsv_plan *plan, qsv_plan_info *out);
  * device headers and the compile options, and reuses it; with
  * QSV_KERNEL_CACHE_ONLY=1 as well, a program missing from the cache is an
  * error (QSV_E_DEVICE) and no compiler process is started.  A plan that is
- * already specialised is left as it is.  seconds_out (may be NULL) receives the host time taken.
- * Errors: QSV_E_ARG (plan null), QSV_E_UNSUPPORTED (a plan of several
- * circuits, or tiles above 13 qubits, i.e. beyond 64 KiB of LDS), QSV_E_STATE
+ * already specialised is left as it is.  seconds_out (may be NULL) receives the host time taken
+ * (after a background compile: the compile's own duration).
+ * Errors: QSV_E_ARG (plan null), QSV_E_UNSUPPORTED (a single-circuit plan
+ * with tiles above 13 qubits, i.e. beyond 64 KiB of LDS), QSV_E_STATE
  * (plan without device tables on the context's device), QSV_E_DEVICE (the
  * compile or the load failed: qsv_last_error() holds the compiler log).
  */
@@ -230,7 +240,8 @@ qsv_status qsv_plan_specialise(qsv_ctx *ctx, qsv_plan *plan, double *seconds_out
  * (QSV_E_DEVICE if it failed; the plan then stays table-driven), and
  * qsv_plan_destroy waits for it and discards it.  The plan must not be used
  * from two threads at once.  A plan already specialised, or with a compile
- * pending, is left as it is.
+ * pending, is left as it is.  A batched plan compiles its one program this
+ * way; its launches stay table-driven until the program is loaded.
  * Errors: QSV_E_ARG (null), QSV_E_UNSUPPORTED and QSV_E_STATE as for
  * qsv_plan_specialise.
  */

@@ -1,0 +1,232 @@
+// The batched persistent kernel's body: many small circuits (n <= 14) with
+// uneven depths, each run entirely on chip by one workgroup.  Shared by the
+// library's table-driven kernel (batched.hip) and the kernels that
+// qsv_plan_specialise generates for a batched plan, which differ only in how a
+// circuit's register stages are walked (the Walk policy below).
+//
+// The grid holds one workgroup per compute unit.  A workgroup takes the next
+// circuit from a device queue (circuits ordered by decreasing work, so the
+// longest start first) until the queue is empty; every workgroup reaches that
+// exit.  Per circuit:
+//   forward  — |0..0> in LDS, the register stages of the circuit (one
+//              partition covers the whole state), final state optionally
+//              written out;
+//   energy   — lambda = H psi in the last stage's register layout, reading the
+//              partner amplitudes of each Pauli group from LDS; <H> reduced in
+//              float64 in a fixed order;
+//   adjoint  — stages walked backwards with psi and lambda both in registers,
+//              remapped between stage layouts through LDS; for every
+//              parameterised rotation Im <lambda|P|psi> is summed per wave
+//              (float64) before U^dagger is applied to both states; the
+//              circuit's gradient entries are then reduced in a fixed order.
+#pragma once
+#include "gates.cuh"
+
+namespace qsv {
+
+struct BatchArgs {
+    int n_groups;
+    int n_circuits;
+    int n;
+    float2 *psi_out;            // forward only: final states (may be null)
+    const float2 *psi_in;       // adjoint only: final states of the forward (null: recompute them)
+    double *energy;             // [n_circuits] (adjoint only)
+    double *grad;               // [n_params]   (adjoint only)
+    double *gpart;              // [n_slots][waves] scratch
+    int *queue;
+    int adjoint;
+    uint64_t *wg_clock;         // null, or per workgroup the real-time clock at its start and at its exit
+};
+
+// Registers in the layout (toff, roff) -> LDS -> registers in the layout (toff2,
+// roff2); offsets are already swizzled.
+template <int R>
+__device__ __forceinline__ void remap(float2 (&v)[1 << R], float2 *lds, bool active, uint32_t toff,
+                                      const uint32_t (&roff)[1 << R], uint32_t toff2, const uint32_t (&roff2)[1 << R])
+{
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < (1 << R); ++i) lds_ref(lds, toff ^ roff[i]) = v[i];
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < (1 << R); ++i) v[i] = lds_ref(lds, toff2 ^ roff2[i]);
+    }
+}
+
+// psi (a) and lambda = H psi (l) in the register layout (toff, roff), psi read
+// from the LDS tile (positions are the qubits in order); the circuit's energy
+// <psi|H|psi> (float64, waves in order) goes to *energy_out.
+template <int R, int LW>
+__device__ __forceinline__ void batch_energy(const float2 *lds, bool active, uint32_t toff,
+                                             const uint32_t (&roff)[1 << R], const DevGroup *__restrict__ groups,
+                                             const DevTerm *__restrict__ terms, int n_groups, float2 (&a)[1 << R],
+                                             float2 (&l)[1 << R], double *s_red, double *energy_out, uint32_t tid)
+{
+    constexpr int NA = 1 << R, WAVES = (1 << LW) / 64;
+    double e_part = 0.0;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+        a[i] = float2{0.f, 0.f};
+        l[i] = float2{0.f, 0.f};
+        if (active) {
+            const uint32_t sx = (toff ^ roff[i]) >> 3;  // swizzled slot of amplitude x
+            const uint32_t x = swz(sx);          // swz is an involution here: recovers x
+            a[i] = lds[sx];
+            double lr = 0.0, li = 0.0;
+            for (int g = 0; g < n_groups; ++g) {
+                const DevGroup G = groups[g];
+                const uint32_t y = x ^ (uint32_t)G.x_mask;
+                const float2 py = lds[swz(y)];
+                double wr = 0.0, wi = 0.0;
+                for (int k = G.term_begin; k < G.term_end; ++k) {
+                    const double sg = (__popcll(y & terms[k].z_mask) & 1) ? -1.0 : 1.0;
+                    wr += sg * terms[k].cre;
+                    wi += sg * terms[k].cim;
+                }
+                lr += wr * py.x - wi * py.y;
+                li += wr * py.y + wi * py.x;
+            }
+            l[i] = float2{(float)lr, (float)li};
+            e_part += (double)a[i].x * lr + (double)a[i].y * li;
+        }
+    }
+    e_part = wave_sum(e_part);
+    if ((tid & 63) == 0) s_red[tid >> 6] = e_part;
+    __syncthreads();
+    if (tid == 0) {
+        double e = 0.0;
+        for (int v = 0; v < WAVES; ++v) e += s_red[v];
+        *energy_out = e;
+    }
+}
+
+// The table-driven walk: the circuit's stage and op tables read at run time.
+template <int R, int LW>
+struct TableWalk {
+    static __device__ __forceinline__ void forward(int, const DevPart *__restrict__ P, float2 *lds,
+                                                   const DevStage *__restrict__ stages,
+                                                   const DevOp *__restrict__ ops, const float *__restrict__ cpool,
+                                                   uint32_t tid)
+    {
+        run_stages<R, false>(lds, stages, ops, cpool, P->stage_begin, P->stage_end, P->t - R, tid, 0);
+    }
+
+    static __device__ __forceinline__ void adjoint(int, const DevPart *__restrict__ P, float2 *lds,
+                                                   const DevStage *__restrict__ stages,
+                                                   const DevOp *__restrict__ ops, const float *__restrict__ cpool,
+                                                   int32_t slot_delta, const DevGroup *__restrict__ groups,
+                                                   const DevTerm *__restrict__ terms, const BatchArgs &A, int c,
+                                                   double *s_red, uint32_t tid)
+    {
+        constexpr int NA = 1 << R, WAVES = (1 << LW) / 64;
+        const int w = P->t - R;
+        const bool active = tid < (1u << w);
+        const int wave = tid >> 6;
+        // lambda = H psi and the energy, in the last stage's layout
+        const int s_last = P->stage_end - 1;
+        uint32_t toff, roff[NA];
+        stage_offsets<R>(stages + s_last, w, tid, toff, roff);
+        float2 a[NA], l[NA];
+        batch_energy<R, LW>(lds, active, toff, roff, groups, terms, A.n_groups, a, l, s_red, A.energy + c, tid);
+        // reverse walk over the stages
+        for (int s = s_last; s >= P->stage_begin; --s) {
+            if (s != s_last) {  // remap psi, then lambda, from the layout of stage s+1 to that of stage s
+                uint32_t toff2, roff2[NA];
+                stage_offsets<R>(stages + s, w, tid, toff2, roff2);
+                remap<R>(a, lds, active, toff, roff, toff2, roff2);
+                remap<R>(l, lds, active, toff, roff, toff2, roff2);
+                toff = toff2;
+#pragma unroll
+                for (int i = 0; i < NA; ++i) roff[i] = roff2[i];
+            }
+            const DevStage *__restrict__ S = stages + s;
+            for (int k = S->op_end - 1; k >= S->op_begin; --k) {
+                const DevOp o = ops[k];
+                if (o.grad_slot >= 0) {
+                    const double v = wave_sum(grad_term<R>(a, l, o, tid, 0));
+                    if ((tid & 63) == 0) A.gpart[(int64_t)(o.grad_slot + slot_delta) * WAVES + wave] = v;
+                }
+                // one array at a time: with 1024 threads a lane has 128 VGPRs, too
+                // few to update psi and lambda together without spilling
+                apply_op<R, true>(a, o, cpool, tid, 0);
+                apply_op<R, true>(l, o, cpool, tid, 0);
+            }
+        }
+    }
+};
+
+// Walk is a policy with two static device functions for circuit c, whose one
+// partition is parts[pidx] and whose matrices sit at cpool (the shared tables'
+// offsets plus the circuit's pool delta):
+//   forward(pidx, P, lds, stages, ops, cpool, tid): the register stages on the
+//       LDS tile, ending with a barrier;
+//   adjoint(pidx, P, lds, stages, ops, cpool, slot_delta, groups, terms, A, c,
+//       s_red, tid): energy and lambda from the LDS tile (batch_energy), then
+//       the reverse walk writing gradient partials to A.gpart.
+template <int R, int LW, class Walk>
+__device__ __forceinline__ void batched_body(
+    const DevPart *__restrict__ parts, const DevStage *__restrict__ stages, const DevOp *__restrict__ ops,
+    const float *__restrict__ pool, const int32_t *__restrict__ order, const int32_t *__restrict__ circ_part,
+    const int64_t *__restrict__ circ_theta, const int64_t *__restrict__ circ_npar,
+    const int32_t *__restrict__ param_off, const int32_t *__restrict__ param_slots,
+    const int32_t *__restrict__ circ_pool_delta, const int32_t *__restrict__ circ_slot_delta,
+    const DevGroup *__restrict__ groups, const DevTerm *__restrict__ terms, const BatchArgs &A)
+{
+    constexpr int WAVES = (1 << LW) / 64;
+    extern __shared__ float2 lds[];
+    __shared__ int s_item;
+    __shared__ double s_red[WAVES];
+    const uint32_t tid = threadIdx.x;
+    if (A.wg_clock && tid == 0) A.wg_clock[2 * blockIdx.x] = __builtin_amdgcn_s_memrealtime();
+    while (true) {
+        if (tid == 0) s_item = atomicAdd(A.queue, 1);
+        __syncthreads();
+        const int item = __builtin_amdgcn_readfirstlane(s_item);  // the same for every thread
+        __syncthreads();
+        if (item >= A.n_circuits) break;
+        const int c = order[item];
+        // circuits of the same structure share their tables: this circuit's own
+        // matrices and gradient slots sit at a constant offset from the ones the
+        // tables name
+        const int pidx = circ_part[c];
+        const DevPart *__restrict__ P = parts + pidx;
+        const float *__restrict__ cpool = pool + circ_pool_delta[c];
+        const int32_t slot_delta = circ_slot_delta[c];
+        const uint32_t dim = 1u << P->t;
+        if (A.psi_in) {  // the forward's final state (positions are the qubits in order)
+            const float2 *src = A.psi_in + (uint64_t)c * dim;
+            for (uint32_t x = tid; x < dim; x += (1u << LW)) lds[swz(x)] = src[x];
+            __syncthreads();
+        } else {  // forward from |0..0>
+            for (uint32_t x = tid; x < dim; x += (1u << LW)) lds[swz(x)] = float2{x == 0 ? 1.f : 0.f, 0.f};
+            __syncthreads();
+            Walk::forward(pidx, P, lds, stages, ops, cpool, tid);
+        }
+        if (A.psi_out) {  // the tile is the whole state and its positions are the qubits in order
+            float2 *dst = A.psi_out + (uint64_t)c * dim;
+            for (uint32_t x = tid; x < dim; x += (1u << LW)) dst[x] = lds[swz(x)];
+        }
+        if (!A.adjoint) {
+            __syncthreads();
+            continue;
+        }
+        Walk::adjoint(pidx, P, lds, stages, ops, cpool, slot_delta, groups, terms, A, c, s_red, tid);
+        // this circuit's gradient entries: slots in slot order, waves in order
+        __threadfence_block();
+        __syncthreads();
+        const int64_t p0 = circ_theta[c], np = circ_npar[c];
+        for (int64_t p = tid; p < np; p += (1 << LW)) {
+            double acc = 0.0;
+            for (int32_t k = param_off[p0 + p]; k < param_off[p0 + p + 1]; ++k)
+                for (int v = 0; v < WAVES; ++v) acc += A.gpart[(int64_t)param_slots[k] * WAVES + v];
+            A.grad[p0 + p] = acc;
+        }
+        __syncthreads();
+    }
+    if (A.wg_clock && tid == 0) A.wg_clock[2 * blockIdx.x + 1] = __builtin_amdgcn_s_memrealtime();
+}
+
+}  // namespace qsv

@@ -559,7 +559,7 @@ struct qsv::AsyncSpecialise {
     size_t n_loaded = 0;
     bool rev = false;
     std::string err;
-    std::chrono::steady_clock::time_point t0;
+    std::chrono::steady_clock::time_point t0, t1;  // compile started, compile over (worker thread)
 };
 
 extern "C" {
@@ -592,6 +592,24 @@ static void load_chunk(Plan &plan, const SpecChunk &c, bool rev)
     }
 }
 
+// Loads the specialised batched kernel qsv_bspec from its code object.
+static void load_batched(Plan &plan, const std::vector<char> &code)
+{
+    hipModule_t m = nullptr;
+    if (hipModuleLoadData(&m, code.data()) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(QSV_E_DEVICE, "hipModuleLoadData failed");
+    }
+    hipFunction_t f = nullptr;
+    if (hipModuleGetFunction(&f, m, "qsv_bspec") != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipModuleUnload(m);
+        fail(QSV_E_DEVICE, "hipModuleGetFunction qsv_bspec");
+    }
+    plan.spec_modules.push_back((void *)m);
+    plan.spec_batch_fn = (void *)f;
+}
+
 // Takes up what a background compile of `plan` has finished: loads every
 // program that is ready (its partitions launch their specialised kernels from
 // then on); with wait, first waits for the whole compile.  When the compile is
@@ -613,7 +631,10 @@ static bool finish_async(Plan &plan, bool wait)
         }
         for (size_t c = 0; c < n; ++c)
             if (!a.loaded[c] && a.ready[c].load(std::memory_order_acquire)) {
-                load_chunk(plan, a.chunks[c], a.rev);
+                if (plan.n_circuits > 1)
+                    load_batched(plan, a.chunks[c].code);
+                else
+                    load_chunk(plan, a.chunks[c], a.rev);
                 a.loaded[c] = 1;
                 ++a.n_loaded;
             }
@@ -626,7 +647,7 @@ static bool finish_async(Plan &plan, bool wait)
         return false;
     }
     plan.specialised = true;
-    plan.specialise_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - a.t0).count();
+    plan.specialise_seconds = std::chrono::duration<double>(a.t1 - a.t0).count();  // the compile's own time
     return false;
 }
 
@@ -846,9 +867,6 @@ qsv_status qsv_plan_specialise(qsv_ctx *ctx, qsv_plan *plan, double *seconds_out
             if (seconds_out) *seconds_out = plan->specialise_seconds;
             return;
         }
-        if (plan->n_circuits != 1) fail(QSV_E_UNSUPPORTED, "only single-circuit plans are specialised");
-        if (((size_t)8 << plan->t) > (size_t)64 * 1024)
-            fail(QSV_E_UNSUPPORTED, "specialised sweeps take tiles of at most 64 KiB of LDS (13 qubits)");
         if (ctx && plan->device != ctx->device) fail(QSV_E_STATE, "plan has no device tables on this context's device");
         if (ctx && plan->async_spec) {  // a background compile is running: wait for it
             hip_check(hipSetDevice(ctx->device), "hipSetDevice");
@@ -857,6 +875,23 @@ qsv_status qsv_plan_specialise(qsv_ctx *ctx, qsv_plan *plan, double *seconds_out
             if (seconds_out) *seconds_out = plan->specialise_seconds;
             return;
         }
+        if (plan->n_circuits > 1) {  // batched: one persistent kernel for all circuit structures
+            const auto t0 = std::chrono::steady_clock::now();
+            std::vector<char> code;
+            const std::string err = specialise_batched_compile(*plan, code);
+            if (!err.empty()) fail(QSV_E_DEVICE, err);
+            const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            if (seconds_out) *seconds_out = secs;
+            if (!ctx) return;  // compile only
+            hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+            load_batched(*plan, code);
+            plan->specialised = true;
+            plan->specialise_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            if (seconds_out) *seconds_out = plan->specialise_seconds;
+            return;
+        }
+        if (((size_t)8 << plan->t) > (size_t)64 * 1024)
+            fail(QSV_E_UNSUPPORTED, "specialised sweeps take tiles of at most 64 KiB of LDS (13 qubits)");
         const auto t0 = std::chrono::steady_clock::now();
         std::vector<SpecChunk> chunks;
         const std::string err = specialise_compile(*plan, chunks, 16);
@@ -877,12 +912,31 @@ qsv_status qsv_plan_specialise_async(qsv_ctx *ctx, qsv_plan *plan)
     return guarded([&] {
         if (!ctx || !plan) fail(QSV_E_ARG, "null argument");
         if (plan->specialised || plan->async_spec) return;
-        if (plan->n_circuits != 1) fail(QSV_E_UNSUPPORTED, "only single-circuit plans are specialised");
-        if (((size_t)8 << plan->t) > (size_t)64 * 1024)
+        if (plan->n_circuits == 1 && ((size_t)8 << plan->t) > (size_t)64 * 1024)
             fail(QSV_E_UNSUPPORTED, "specialised sweeps take tiles of at most 64 KiB of LDS (13 qubits)");
         if (plan->device != ctx->device) fail(QSV_E_STATE, "plan has no device tables on this context's device");
         auto a = std::make_shared<AsyncSpecialise>();
         a->t0 = std::chrono::steady_clock::now();
+        if (plan->n_circuits > 1) {  // batched: the one program of qsv_bspec
+            AsyncSpecialise *ap = a.get();
+            const Plan *pp = plan;
+            ap->chunks.resize(1);
+            ap->ready.reset(new std::atomic<bool>[1]);
+            ap->ready[0].store(false, std::memory_order_relaxed);
+            ap->sized.store(true, std::memory_order_release);
+            a->worker = std::thread([ap, pp] {
+                try {
+                    ap->err = specialise_batched_compile(*pp, ap->chunks[0].code);
+                    if (ap->err.empty()) ap->ready[0].store(true, std::memory_order_release);
+                } catch (const std::exception &e) {
+                    ap->err = std::string("specialise: ") + e.what();
+                }
+                ap->t1 = std::chrono::steady_clock::now();
+            ap->done.store(true, std::memory_order_release);
+            });
+            plan->async_spec = std::move(a);
+            return;
+        }
         a->rev = specialise_reverse(*plan);
         AsyncSpecialise *ap = a.get();
         const Plan *pp = plan;
@@ -902,6 +956,7 @@ qsv_status qsv_plan_specialise_async(qsv_ctx *ctx, qsv_plan *plan)
             } catch (const std::exception &e) {
                 ap->err = std::string("specialise: ") + e.what();
             }
+            ap->t1 = std::chrono::steady_clock::now();
             ap->done.store(true, std::memory_order_release);
         });
         plan->async_spec = std::move(a);
@@ -1016,6 +1071,7 @@ qsv_status qsv_apply(qsv_ctx *ctx, const qsv_plan *plan, const double *theta_dev
         if (plan->n_params > 0 && !theta_dev) fail(QSV_E_ARG, "theta is null");
         hip_check(hipSetDevice(ctx->device), "hipSetDevice");
         if (plan->n_circuits > 1) {
+            finish_async(const_cast<qsv_plan &>(*plan), false);  // a finished background compile
             const int grid = ctx->grid_batched(plan->n_circuits);
             hip_check(launch_batched(*plan, nullptr, 0, nullptr, theta_dev, (float2 *)psi_dev, nullptr, nullptr, nullptr,
                                      nullptr, ctx->ensure_queue(), false, grid, ctx->batch_clock(grid), ctx->stream),
@@ -1151,9 +1207,20 @@ qsv_status qsv_adjoint_grad(qsv_ctx *ctx, const qsv_plan *plan, const qsv_pauli_
             DevTerm *dt = nullptr;
             if (!g.groups.empty()) upload_groups(ctx, g, dp_unused, dg, dt);
             const int grid = ctx->grid_batched(plan->n_circuits);
-            hip_check(launch_batched(*plan, dg, (int)g.groups.size(), dt, theta_dev, nullptr, (const float2 *)psi_final_dev,
-                                     energy_dev, grad_dev, gpart, ctx->ensure_queue(), true, grid,
-                                     ctx->batch_clock(grid), ctx->stream),
+            const float2 *psi_in = (const float2 *)psi_final_dev;
+            if (!psi_in && plan->spec_batch_fn) {
+                // the specialised forward into a scratch batch of states, then the
+                // adjoint walk (table-driven) from them
+                const size_t bytes = ((size_t)plan->n_circuits << plan->n) * sizeof(float2);
+                float2 *states = (float2 *)ctx->ensure(ctx->lam, ctx->lam_bytes, bytes);
+                hip_check(launch_batched(*plan, nullptr, 0, nullptr, theta_dev, states, nullptr, nullptr, nullptr,
+                                         nullptr, ctx->ensure_queue(), false, grid, nullptr, ctx->stream),
+                          "batched launch");
+                psi_in = states;
+            }
+            hip_check(launch_batched(*plan, dg, (int)g.groups.size(), dt, theta_dev, nullptr, psi_in, energy_dev,
+                                     grad_dev, gpart, ctx->ensure_queue(), true, grid, ctx->batch_clock(grid),
+                                     ctx->stream),
                       "batched launch");
             return;
         }

@@ -91,6 +91,7 @@ struct Plan {
     std::vector<void *> spec_fn;
     std::vector<void *> spec_rev_fn;  // the adjoint walk's kernels (gradient plans with tiles of 12 qubits or fewer)
     std::vector<void *> spec_modules; // hipModule_t, unloaded with the plan
+    void *spec_batch_fn = nullptr;    // batched plans: the specialised qsv_bspec (hipFunction_t), or null
     bool specialised = false;
     double specialise_seconds = 0;
     // qsv_plan_specialise_async: the compile running in the background (null
@@ -136,6 +137,11 @@ struct SpecChunk {
     std::vector<char> code;
 };
 std::string specialise_source(const Plan &plan, int p0, int p1, bool with_reverse);
+// The program of a batched plan's specialised kernel qsv_bspec (one program:
+// the persistent kernel switches between the plan's circuit structures).
+std::string specialise_batched_source(const Plan &plan);
+// Compiles it (one helper process, through the code-object cache); "" or the error.
+std::string specialise_batched_compile(const Plan &plan, std::vector<char> &code);
 // Whether the adjoint walk is specialised too: gradient plans whose psi and
 // lambda tiles fit 64 KiB of LDS together.
 bool specialise_reverse(const Plan &plan);

@@ -10,27 +10,6 @@ bool kernel_shape_supported(int R, int LW);
 hipError_t launch_sweep(const Plan &plan, int R, int LW, int pidx, float2 *psi, float2 *ckpt, hipStream_t s);
 hipError_t launch_materialize(const Plan &plan, const double *theta, hipStream_t s);
 
-// Pauli sums grouped by X mask, in the form the reduction kernels read.
-struct DevTerm {
-    double cre, cim;      // coeff * i^{#Y}
-    uint64_t z_mask;
-    uint32_t zt;          // expectation passes: the Z/Y mask on the pass's tile positions
-    int32_t slot;         // expectation passes, diagonal groups: zt's bits at tile positions 0, 10, 11 (3 bits)
-};
-struct DevGroup {
-    uint64_t x_mask;
-    int32_t term_begin, term_end;
-    int32_t xt;           // expectation passes: X mask in tile positions, -1 for partners read from HBM
-    int32_t pad;
-};
-// One pass of qsv_expect over the state: tile qubits and the groups it handles.
-struct DevPass {
-    uint64_t tile_mask;
-    int32_t g_begin, g_end;
-    int32_t has_x;        // a group needs partner amplitudes from the LDS tile
-    int32_t staged;       // its groups and terms fit EXPECT_LDS_GROUPS / EXPECT_LDS_TERMS (read from LDS copies)
-};
-
 // expect.hip
 constexpr int EXPECT_TILE_QUBITS = 12;   // tiles of 4096 amplitudes, 32 KiB of LDS
 constexpr int EXPECT_LOG_THREADS = 9;   // 512 threads per workgroup

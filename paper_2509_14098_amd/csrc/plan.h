@@ -79,6 +79,27 @@ struct DevPart {
     int32_t gq[48];       // qubit at tile-index bit b, b < n - t
 };
 
+// Pauli sums grouped by X mask, in the form the reduction kernels read.
+struct DevTerm {
+    double cre, cim;      // coeff * i^{#Y}
+    uint64_t z_mask;
+    uint32_t zt;          // expectation passes: the Z/Y mask on the pass's tile positions
+    int32_t slot;         // expectation passes, diagonal groups: zt's bits at tile positions 0, 10, 11 (3 bits)
+};
+struct DevGroup {
+    uint64_t x_mask;
+    int32_t term_begin, term_end;
+    int32_t xt;           // expectation passes: X mask in tile positions, -1 for partners read from HBM
+    int32_t pad;
+};
+// One pass of qsv_expect over the state: tile qubits and the groups it handles.
+struct DevPass {
+    uint64_t tile_mask;
+    int32_t g_begin, g_end;
+    int32_t has_x;        // a group needs partner amplitudes from the LDS tile
+    int32_t staged;       // its groups and terms fit EXPECT_LDS_GROUPS / EXPECT_LDS_TERMS (read from LDS copies)
+};
+
 // Matrix pool layout: a 2x2 gate takes 8 floats (row-major re,im), a 4x4
 // gate 32 floats (local index j = b(q0) + 2 b(q1)), a register diagonal 2^R
 // complex entries; every entry starts at a multiple of 8 floats.  OP_LAYER:

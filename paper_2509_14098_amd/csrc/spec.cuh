@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 #endif
 
+#include "batched.cuh"
 #include "gates.cuh"
 #include "tile.cuh"
 
@@ -223,6 +224,36 @@ __device__ __forceinline__ void spec_reverse(const float2 *__restrict__ psi_src,
                                                                                        base);
     });
     store_pairs<T::LW>(lam, lds_lam, P, base, tid);
+}
+
+// Batched plans: the circuits of one structure share a table type T (the
+// structure's one partition covers the whole state, so T::part.t = n).  The
+// forward walk of such a circuit on its LDS tile, ending with a barrier.
+template <class T, int S0, int S1>
+__device__ __noinline__ void spec_bchunk(float2 *lds, const float *__restrict__ cpool, uint32_t tid)
+{
+    static_for<S0, S1>([&](auto S) __attribute__((always_inline)) {
+        // a fresh copy of tid per stage: with 1024 threads a lane has 128
+        // registers, too few to keep every stage's addresses computed ahead
+        uint32_t t = tid;
+        asm volatile("" : "+v"(t));
+        spec_stage<T, std::decay_t<decltype(S)>::value>(lds, cpool, t, 0);
+    });
+}
+
+// Stages in chunks of BCHUNK, each chunk a function of its own: the compile
+// time of one long straight-line function grows faster than its length.
+constexpr int BCHUNK = 4;
+
+template <class T>
+__device__ __forceinline__ void spec_bforward(float2 *lds, const float *__restrict__ cpool, uint32_t tid)
+{
+    constexpr int s0 = T::part.stage_begin, s1 = T::part.stage_end;
+    static_for<0, (s1 - s0 + BCHUNK - 1) / BCHUNK>([&](auto C) __attribute__((always_inline)) {
+        constexpr int a = s0 + BCHUNK * std::decay_t<decltype(C)>::value;
+        constexpr int b = a + BCHUNK < s1 ? a + BCHUNK : s1;
+        spec_bchunk<T, a, b>(lds, cpool, tid);
+    });
 }
 
 }  // namespace qsv

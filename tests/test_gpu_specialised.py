@@ -287,18 +287,9 @@ def test_autotuner_times_specialised_candidates(sim):
 
 
 def test_specialise_errors(sim):
-    """Batched plans and tiles above 64 KiB of LDS are not specialised; a
-    host-only plan has nothing to load on a device.  Each error leaves the
-    plan usable by the table-driven sweep."""
-    gates, npar = W.ansatz(6, 2)
-    batch = np.concatenate([gates, gates])
-    bp = sim.partition(6, batch, 0, 0, None, [0, len(gates), 2 * len(gates)])
-    try:
-        with pytest.raises(Q.QsvError) as e:
-            sim.specialise(bp)
-        assert e.value.code == -6
-    finally:
-        bp.close()
+    """Tiles above 64 KiB of LDS are not specialised; a host-only plan has
+    nothing to load on a device.  Each error leaves the plan usable by the
+    table-driven sweep."""
     big = sim.partition(16, W.random_circuit(16, 50, seed=3), 12, 0, (5, 9))
     try:
         with pytest.raises(Q.QsvError) as e:
@@ -380,3 +371,90 @@ def test_specialise_async_gradient_and_destroy_while_pending(sim):
     other = sim.partition(n, gates, 8, Q.PLAN_GRAD, (3, 6))
     sim.specialise_async(other)
     other.close()  # joins the pending compile
+
+
+# ---------------------------------------------------------------- batched plans
+
+def _batched_case(n, seed):
+    """Circuits of several structures in one batch: ansatz instances of
+    depths 1-3 (each depth twice, so instances share tables), an empty
+    circuit, and random circuits over every gate kind with parameters."""
+    rng = np.random.default_rng(seed)
+    circs, thetas = [], []
+    for d in (1, 2, 3, 2, 1, 3):
+        g, npar = W.ansatz(n, d)
+        circs.append(g)
+        thetas.append(rng.uniform(-np.pi, np.pi, size=npar))
+    a, _ = W.ansatz(n, 1)
+    circs.append(a[:0])
+    thetas.append(np.zeros(0))
+    for i in range(3):
+        circs.append(W.random_circuit(n, 60, seed=seed + i, n_params=3))
+        thetas.append(rng.uniform(-3, 3, size=3))
+    gates = np.concatenate(circs)
+    off = np.concatenate([[0], np.cumsum([len(c) for c in circs])])
+    return circs, thetas, gates, off, np.concatenate(thetas)
+
+
+def test_specialised_batched_forward_and_gradient(sim):
+    """qsv_plan_specialise on a batched plan: one persistent kernel with every
+    circuit structure compiled in runs the forward launches.  Final states
+    against the oracle and against the table-driven kernel; energies and
+    gradients (adjoint walk from the specialised forward's states, in two
+    launches, and from given states) against the oracle's adjoint."""
+    n = 6
+    circs, thetas, gates, off, theta = _batched_case(n, 70)
+    B = len(circs)
+    H = W.zz_chain_plus_x(n, 0.5)
+    plan = sim.partition(n, gates, 0, Q.PLAN_GRAD, None, circ_offsets=off)
+    try:
+        ref_psi = torch.empty((B, 1 << n), dtype=torch.complex64, device="cuda")
+        sim.apply(plan, ref_psi, theta)
+        secs = sim.specialise(plan)
+        assert plan.info["specialised"] == 1 and secs > 0
+        psi = torch.empty((B, 1 << n), dtype=torch.complex64, device="cuda")
+        sim.apply(plan, psi, theta)
+        e1, g1 = sim.adjoint_grad(plan, H, theta)         # specialised forward, then the adjoint walk
+        e2, g2 = sim.adjoint_grad(plan, H, theta, psi)    # from the given final states
+        torch.cuda.synchronize()
+    finally:
+        plan.close()
+    psi, ref_psi = psi.cpu().numpy(), ref_psi.cpu().numpy()
+    assert maxabs(psi, ref_psi) <= SAME
+    assert np.array_equal(e1.cpu().numpy(), e2.cpu().numpy())
+    assert np.array_equal(g1.cpu().numpy(), g2.cpu().numpy())
+    e1, g1 = e1.cpu().numpy(), g1.cpu().numpy()
+    p0 = 0
+    for b in range(B):
+        assert maxabs(psi[b], oracle.apply(n, circs[b], thetas[b])) <= TOL, b
+        e_ref, g_ref = oracle.adjoint(n, circs[b], thetas[b], H)
+        assert abs(e1[b] - e_ref) < 1e-5, b
+        if len(thetas[b]):
+            assert np.max(np.abs(g1[p0:p0 + len(thetas[b])] - g_ref)) < 1e-4, b
+        p0 += len(thetas[b])
+
+
+def test_specialised_batched_in_the_background(sim):
+    """qsv_plan_specialise_async on a batched plan: forward launches run
+    table-driven until the compile has finished, then on the specialised
+    kernel; every launch's states equal the oracle's."""
+    n = 8
+    circs, thetas, gates, off, theta = _batched_case(n, 90)
+    B = len(circs)
+    plan = sim.partition(n, gates, 0, Q.PLAN_GRAD, None, circ_offsets=off)
+    try:
+        sim.specialise_async(plan)
+        psi = torch.empty((B, 1 << n), dtype=torch.complex64, device="cuda")
+        outs = []
+        for _ in range(3):
+            sim.apply(plan, psi, theta)
+            outs.append(psi.cpu().numpy())
+        sim.specialise(plan)  # waits for the compile
+        assert plan.info["specialised"] == 1
+        sim.apply(plan, psi, theta)
+        outs.append(psi.cpu().numpy())
+    finally:
+        plan.close()
+    for out in outs:
+        for b in range(B):
+            assert maxabs(out[b], oracle.apply(n, circs[b], thetas[b])) <= TOL, b

@@ -259,20 +259,30 @@ def test_specialise_compiles_without_a_gpu():
         Q.qsv_plan_destroy(plan)
 
 
-def test_specialise_rejections():
+def test_specialise_batched_compiles_without_a_gpu():
+    """A batched plan's specialised program (one persistent kernel, every
+    circuit structure compiled in) compiles for gfx950."""
     gates, _ = W.ansatz(6, 2)
-    batched = Q.qsv_partition(None, 6, np.concatenate([gates, gates]), [0, len(gates), 2 * len(gates)], 0, 0, None)
+    other, _ = W.ansatz(6, 1)
+    plan = Q.qsv_partition(None, 6, np.concatenate([gates, other, gates]),
+                           [0, len(gates), len(gates) + len(other), 2 * len(gates) + len(other)], 0, Q.PLAN_GRAD, None)
+    try:
+        assert Q.qsv_plan_specialise(None, plan) > 0
+        assert Q.qsv_plan_info(plan)["specialised"] == 0
+    finally:
+        Q.qsv_plan_destroy(plan)
+
+
+def test_specialise_rejections():
     big = Q.qsv_partition(None, 16, W.ghz(16), None, 12, 0, (5, 9))  # 14-qubit tiles: 128 KiB of LDS
     try:
-        for plan in (batched, big):
-            with pytest.raises(Q.QsvError) as e:
-                Q.qsv_plan_specialise(None, plan)
-            assert e.value.code == -6
+        with pytest.raises(Q.QsvError) as e:
+            Q.qsv_plan_specialise(None, big)
+        assert e.value.code == -6
         with pytest.raises(Q.QsvError) as e:
             Q.qsv_plan_specialise(None, None)
         assert e.value.code == -1
     finally:
-        Q.qsv_plan_destroy(batched)
         Q.qsv_plan_destroy(big)
 
 
