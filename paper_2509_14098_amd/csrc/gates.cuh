@@ -692,11 +692,48 @@ __device__ __forceinline__ uint64_t xcd_tile(uint32_t b, uint32_t nblk, const De
     return ((uint64_t)((j >> g) * 8u + x) << g) | (j & (G - 1u));
 }
 
+#if defined(__HIP_DEVICE_COMPILE__)
+// The value of lane sel(i) in lane i (DPP lane exchange, CTRL its control
+// word), 0 in the rows that ROW_MASK leaves out.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    int lo, hi;
+    if constexpr (ROW_MASK == 0xF) {  // every lane written: no initial value needed
+        lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+        hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+    } else {
+        lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROW_MASK, 0xF, false);
+        hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROW_MASK, 0xF, false);
+    }
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+#endif
+
+// Sum over the 64 lanes of a wave (float64, a fixed order), the same value in
+// every lane.  Lane exchanges by DPP (vector ALU, no LDS round trips): quads
+// (lane xor 1, xor 2), halves of a row (mirror), rows of 16 (mirror), then
+// row 0 into row 1 and row 2 into row 3 (broadcast of lane 15), then rows 0-1
+// into row 3 (broadcast of lane 31); the total is read from lane 63.
 __device__ __forceinline__ double wave_sum(double v)
 {
+#if defined(__HIP_DEVICE_COMPILE__)
+    v += dpp_f64<0xB1, 0xF>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_f64<0x4E, 0xF>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_f64<0x141, 0xF>(v);  // row_half_mirror
+    v += dpp_f64<0x140, 0xF>(v);  // row_mirror
+    v += dpp_f64<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_f64<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 63);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+#else
 #pragma unroll
     for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
     return v;
+#endif
 }
 
 // XOR swizzle of an 8-byte LDS slot: bits 5-9 and 10-14 of the tile position
