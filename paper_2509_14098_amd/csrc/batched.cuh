@@ -149,10 +149,9 @@ struct TableWalk {
                     const double v = wave_sum(grad_term<R>(a, l, o, tid, 0));
                     if ((tid & 63) == 0) A.gpart[(int64_t)(o.grad_slot + slot_delta) * WAVES + wave] = v;
                 }
-                // one array at a time: with 1024 threads a lane has 128 VGPRs, too
-                // few to update psi and lambda together without spilling
-                apply_op<R, true>(a, o, cpool, tid, 0);
-                apply_op<R, true>(l, o, cpool, tid, 0);
+                // one dispatch, then psi and lambda one after the other (a
+                // dispatch per array cost 9 % more time)
+                apply_ops<R, true, true>(o, cpool, tid, 0, a, l);
             }
         }
     }

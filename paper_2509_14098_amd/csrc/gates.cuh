@@ -489,38 +489,50 @@ __device__ __forceinline__ void g_swap(float2 (&a)[1 << R])
     }
 }
 
+// After each array of a multi-array op when SEQ holds: the compiler may not
+// interleave the arrays' updates (with 1024 threads a lane has 128 VGPRs, too
+// few for psi and lambda to be updated together).
+template <bool SEQ>
+__device__ __forceinline__ void array_fence()
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (SEQ) __builtin_amdgcn_sched_barrier(0);
+#endif
+}
+
 // Apply one op (or its conjugate transpose) to one or more amplitude arrays of
-// a thread (the adjoint walk applies each op to psi and lambda in one pass).
-// The op kind and the register slots are tested bit by bit on opaque one-hot
-// masks (see opaque()).
-template <int R, bool DAG, typename... Arr>
+// a thread (the adjoint walk applies each op to psi and lambda in one pass:
+// one dispatch; with SEQ one array after the other).  The op kind and the
+// register slots are tested bit by bit on opaque one-hot masks (see opaque()).
+template <int R, bool DAG, bool SEQ = false, typename... Arr>
 __device__ __forceinline__ void apply_ops(const DevOp &o, const float *__restrict__ pool, uint32_t tid,
                                           uint64_t base, Arr &...as)
 {
+    constexpr bool F = SEQ && sizeof...(Arr) > 1;
     const float *__restrict__ m32 = pool + (o.mat < 0 ? 0 : o.mat);
     const uint32_t kb = opaque(1u << o.kind);
     const uint32_t ja = opaque(1u << (o.a & 0x3F)), jb = opaque(1u << (o.b & 0x3F));
 #define QSV_J(x) std::decay_t<decltype(x)>::value
-    if (kb & (1u << OP_LAYER)) (g_layer<R, DAG>(as, m32, (uint32_t)o.a), ...);
-    if (kb & (1u << OP_DREG)) (g_dreg<R, DAG>(as, m32), ...);
+    if (kb & (1u << OP_LAYER)) ((g_layer<R, DAG>(as, m32, (uint32_t)o.a), array_fence<F>()), ...);
+    if (kb & (1u << OP_DREG)) ((g_dreg<R, DAG>(as, m32), array_fence<F>()), ...);
     if (kb & (1u << OP_CZ_RT)) {
         const uint32_t sg = lane_bit(o.b, tid, base) << 31;
-        on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { (g_cz_rt<R, QSV_J(J)>(as, sg), ...); });
+        on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { ((g_cz_rt<R, QSV_J(J)>(as, sg), array_fence<F>()), ...); });
     }
     if (kb & (1u << OP_CZ_TT)) {
         const uint32_t sg = (lane_bit(o.a, tid, base) & lane_bit(o.b, tid, base)) << 31;
-        (g_cz_tt<R>(as, sg), ...);
+        ((g_cz_tt<R>(as, sg), array_fence<F>()), ...);
     }
     if (kb & (1u << OP_CX)) {
         on_slot<R>(ja, [&](auto C) __attribute__((always_inline)) {
             on_slot<R>(jb, [&](auto J) __attribute__((always_inline)) {
-                if constexpr (QSV_J(C) != QSV_J(J)) (g_cx_reg<R, QSV_J(C), QSV_J(J)>(as), ...);
+                if constexpr (QSV_J(C) != QSV_J(J)) ((g_cx_reg<R, QSV_J(C), QSV_J(J)>(as), array_fence<F>()), ...);
             });
         });
     }
     if (kb & (1u << OP_CX_T)) {
         const uint32_t mk = 0u - lane_bit(o.a, tid, base);
-        on_slot<R>(jb, [&](auto J) __attribute__((always_inline)) { (g_cx_lane<R, QSV_J(J)>(as, mk), ...); });
+        on_slot<R>(jb, [&](auto J) __attribute__((always_inline)) { ((g_cx_lane<R, QSV_J(J)>(as, mk), array_fence<F>()), ...); });
     }
     // the kinds that fused stages use least are tested only when one of them is present
     constexpr uint32_t RARE = (1u << OP_U1) | (1u << OP_R1) | (1u << OP_CZ) | (1u << OP_D1) | (1u << OP_D1_T) |
@@ -530,48 +542,48 @@ __device__ __forceinline__ void apply_ops(const DevOp &o, const float *__restric
     const M8 mm = load_m8(pool, o.mat);  // the 8 leading matrix floats, one scalar load
     const float *m = mm.v;
     if (kb & (1u << OP_U1))
-        on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { (g_u1<R, QSV_J(J), DAG>(as, m), ...); });
+        on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { ((g_u1<R, QSV_J(J), DAG>(as, m), array_fence<F>()), ...); });
     if (kb & (1u << OP_R1))
-        on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { (g_r1<R, QSV_J(J), DAG>(as, m), ...); });
+        on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { ((g_r1<R, QSV_J(J), DAG>(as, m), array_fence<F>()), ...); });
     if (kb & (1u << OP_CZ)) {
         const uint32_t p = reg_pattern(o.a & 0x3F) & reg_pattern(o.b & 0x3F);
-        (g_cz<R>(as, p), ...);
+        ((g_cz<R>(as, p), array_fence<F>()), ...);
     }
     if (kb & (1u << OP_D1))
-        on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { (g_d1<R, QSV_J(J), DAG>(as, m), ...); });
+        on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { ((g_d1<R, QSV_J(J), DAG>(as, m), array_fence<F>()), ...); });
     if (kb & (1u << OP_D1_T)) {
         const uint32_t bit = lane_bit(o.a, tid, base);
-        (g_d1_lane<R, DAG>(as, m, bit), ...);
+        ((g_d1_lane<R, DAG>(as, m, bit), array_fence<F>()), ...);
     }
     if (kb & (1u << OP_D2)) {
         const uint32_t pa = loc_pattern(o.a, tid, base), pb = loc_pattern(o.b, tid, base);
-        (g_d2<R, DAG>(as, m, pa, pb), ...);
+        ((g_d2<R, DAG>(as, m, pa, pb), array_fence<F>()), ...);
     }
     if (kb & (1u << OP_D2_RT)) {
         const uint32_t bit = lane_bit(o.b, tid, base);
         const bool lo_one = o.flags & 1;
-        on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { (g_d2_rt<R, QSV_J(J), DAG>(as, m, bit, lo_one), ...); });
+        on_slot<R>(ja, [&](auto J) __attribute__((always_inline)) { ((g_d2_rt<R, QSV_J(J), DAG>(as, m, bit, lo_one), array_fence<F>()), ...); });
     }
     if (kb & (1u << OP_D2_TT)) {
         const uint32_t j = lane_bit(o.a, tid, base) + 2u * lane_bit(o.b, tid, base);
-        (g_d2_tt<R, DAG>(as, m, j), ...);
+        ((g_d2_tt<R, DAG>(as, m, j), array_fence<F>()), ...);
     }
     if (kb & (1u << OP_CU)) {
         const uint32_t pc = loc_pattern(o.a, tid, base);
-        on_slot<R>(jb, [&](auto J) __attribute__((always_inline)) { (g_cu<R, QSV_J(J), DAG>(as, m, pc), ...); });
+        on_slot<R>(jb, [&](auto J) __attribute__((always_inline)) { ((g_cu<R, QSV_J(J), DAG>(as, m, pc), array_fence<F>()), ...); });
     }
     if constexpr (R >= 2) {
         if (kb & (1u << OP_U2)) {
             on_slot<R>(ja, [&](auto JA) __attribute__((always_inline)) {
                 on_slot<R>(jb, [&](auto JB) __attribute__((always_inline)) {
-                    if constexpr (QSV_J(JA) != QSV_J(JB)) (g_u2<R, QSV_J(JA), QSV_J(JB), DAG>(as, m32), ...);
+                    if constexpr (QSV_J(JA) != QSV_J(JB)) ((g_u2<R, QSV_J(JA), QSV_J(JB), DAG>(as, m32), array_fence<F>()), ...);
                 });
             });
         }
         if (kb & (1u << OP_SWAP)) {
             on_slot<R>(ja, [&](auto JA) __attribute__((always_inline)) {
                 on_slot<R>(jb, [&](auto JB) __attribute__((always_inline)) {
-                    if constexpr (QSV_J(JA) != QSV_J(JB)) (g_swap<R, QSV_J(JA), QSV_J(JB)>(as), ...);
+                    if constexpr (QSV_J(JA) != QSV_J(JB)) ((g_swap<R, QSV_J(JA), QSV_J(JB)>(as), array_fence<F>()), ...);
                 });
             });
         }

@@ -294,6 +294,50 @@ def test_expect_more_groups_than_a_grid_row(sim):
     assert abs(got - ref) < 1e-9 * max(1.0, float(np.sum(np.abs(coeff))))
 
 
+@pytest.mark.parametrize("n_terms", [64, 300])
+def test_expect_diagonal_sums_every_slot_pattern(sim, n_terms):
+    """Diagonal sums only (one group): random Z strings over all 14 qubits, so
+    every pattern of Z bits at the tile positions a thread's 8 amplitudes
+    differ in (qubits 0, 10, 11 here), at the thread's own positions and
+    outside the tile occurs; 64 terms fit the LDS copy of the tables, 300 are
+    read from memory."""
+    n = 14
+    rng = np.random.default_rng(n_terms)
+    psi = ((rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)) / np.sqrt(2 << n)).astype(np.complex64)
+    terms = [(float(rng.normal()), {int(q): "Z" for q in np.flatnonzero(rng.random(n) < 0.3)})
+             for _ in range(n_terms)]
+    H = W.pauli_sum(terms)
+    ref = oracle.expect(n, H, psi.astype(np.complex128))
+    got = float(sim.expect(H, torch.as_tensor(psi, device="cuda"), n)[0])
+    assert abs(got - ref) < 1e-9 * max(1.0, float(np.sum(np.abs(H["coeff"]))))
+
+
+def test_expect_many_groups_wide_masks_and_y_terms(sim):
+    """150 X/Y masks on 16 qubits (more groups than the LDS copy of a pass's
+    tables holds), several terms per mask with Z and Y factors, masks too wide
+    for a tile (partners from memory), single real X strings, and a diagonal
+    group."""
+    n = 16
+    rng = np.random.default_rng(77)
+    psi = ((rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)) / np.sqrt(2 << n)).astype(np.complex64)
+    terms = []
+    for _ in range(150):
+        qs = rng.choice(n, size=int(rng.integers(1, 9)), replace=False)
+        base = {int(q): "XY"[int(rng.integers(2))] for q in qs}
+        for _ in range(int(rng.integers(1, 4))):
+            t = dict(base)
+            for q in rng.choice(n, size=2, replace=False):
+                if int(q) not in t:
+                    t[int(q)] = "Z"
+            terms.append((float(rng.normal()), t))
+    terms += [(0.5, {q: "X"}) for q in range(n)]
+    terms += [(1.0, {q: "Z", q + 1: "Z"}) for q in range(n - 1)]
+    H = W.pauli_sum(terms)
+    ref = oracle.expect(n, H, psi.astype(np.complex128))
+    got = float(sim.expect(H, torch.as_tensor(psi, device="cuda"), n)[0])
+    assert abs(got - ref) < 1e-9 * max(1.0, float(np.sum(np.abs(H["coeff"]))))
+
+
 def test_expect_batched(sim):
     n, B = 6, 5
     rng = np.random.default_rng(8)
@@ -471,8 +515,10 @@ def test_autotuner_choice_is_correct(sim):
     torch.cuda.synchronize()
     plan.close()
     assert len(tried) >= 3
-    best = min(tried, key=lambda r: r[3])
-    assert (info["k_local"], info["reg_qubits"], info["log_threads"]) == best[:3]
+    # the tuner keeps the fastest candidate; the record holds whole microseconds,
+    # so candidates within a microsecond of each other tie there
+    chosen = [r for r in tried if tuple(r[:3]) == (info["k_local"], info["reg_qubits"], info["log_threads"])]
+    assert chosen and chosen[0][3] == min(r[3] for r in tried)
     assert_close(psi.cpu().numpy(), oracle.apply(n, gates))
 
 
