@@ -53,10 +53,10 @@ __global__ __launch_bounds__(1 << LW) void reverse_kernel(const float2 *__restri
         }
         for (int k = S->op_end - 1; k >= S->op_begin; --k) {
             const DevOp o = ops[k];
-            if (o.grad_slot >= 0) {
-                const double v = wave_sum(grad_term<R>(a, l, o, tid, base));
-                if ((tid & 63) == 0) gpart[(int64_t)o.grad_slot * slot_stride + part_index] = v;
-            }
+            if (o.grad_slot >= 0)
+                grad_partials<R>(a, l, o, tid, base, [&](int32_t slot, double v) __attribute__((always_inline)) {
+                    if ((tid & 63) == 0) gpart[(int64_t)slot * slot_stride + part_index] = v;
+                });
             apply_op_dag2<R>(a, l, o, pool, tid, base);
         }
         if (active) {

@@ -145,10 +145,10 @@ struct TableWalk {
             const DevStage *__restrict__ S = stages + s;
             for (int k = S->op_end - 1; k >= S->op_begin; --k) {
                 const DevOp o = ops[k];
-                if (o.grad_slot >= 0) {
-                    const double v = wave_sum(grad_term<R>(a, l, o, tid, 0));
-                    if ((tid & 63) == 0) A.gpart[(int64_t)(o.grad_slot + slot_delta) * WAVES + wave] = v;
-                }
+                if (o.grad_slot >= 0)
+                    grad_partials<R>(a, l, o, tid, 0, [&](int32_t slot, double v) __attribute__((always_inline)) {
+                        if ((tid & 63) == 0) A.gpart[(int64_t)(slot + slot_delta) * WAVES + wave] = v;
+                    });
                 // one dispatch, then psi and lambda one after the other (a
                 // dispatch per array cost 9 % more time)
                 apply_ops<R, true, true>(o, cpool, tid, 0, a, l);

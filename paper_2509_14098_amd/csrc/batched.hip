@@ -45,7 +45,9 @@ hipError_t launch_batched(const Plan &plan, const DevGroup *groups, int n_groups
                           double *gpart, int *queue, bool adjoint, int grid, uint64_t *wg_clock, hipStream_t s)
 {
     if (plan.R != BATCH_R || plan.LW != BATCH_LW) return hipErrorInvalidValue;
-    hipError_t e = launch_materialize(plan, theta, s);
+    // the specialised forward applies folded RZ diagonals as their members' own
+    // rotations: their 2^R-entry tables are not needed there
+    hipError_t e = launch_materialize(plan, theta, s, !(plan.spec_batch_fn && !adjoint));
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, queue);
     e = hipGetLastError();

@@ -474,6 +474,7 @@ static qsv_plan *make_plan(qsv_ctx *ctx, int n_qubits, const qsv_gate *gates, co
         pool.resize(pool.size() + 8, 0.f);  // op prefetch reads 8 floats at any offset
         P->d_pool = dev_upload(pool);
         P->d_pgates = dev_upload(P->pgates);
+        P->d_pdiags = dev_upload(P->pdiags);
         P->d_grad_param = dev_upload(P->grad_param);
         P->d_param_off = dev_upload(P->param_off);
         P->d_param_slots = dev_upload(P->param_slots);
@@ -816,6 +817,7 @@ qsv_status qsv_plan_destroy(qsv_plan *plan)
         dev_free(plan->d_parts);
         dev_free(plan->d_pool);
         dev_free(plan->d_pgates);
+        dev_free(plan->d_pdiags);
         dev_free(plan->d_grad_param);
         dev_free(plan->d_param_off);
         dev_free(plan->d_param_slots);

@@ -748,6 +748,29 @@ __device__ __forceinline__ double wave_sum(double v)
 #endif
 }
 
+// The gradient partials of op o (float64, summed over the wave): the one of
+// its rotation, or, for a register diagonal folded from parameterised RZ
+// rotations (OP_DREG with a gradient slot), one per member: the members are
+// the register slots in o.a, member m (in slot order) has slot grad_slot + m.
+// emit(slot, value) is called for each, with the same value in every lane.
+template <int R, typename Emit>
+__device__ __forceinline__ void grad_partials(const float2 (&a)[1 << R], const float2 (&l)[1 << R], const DevOp &o,
+                                              uint32_t tid, uint64_t base, Emit &&emit)
+{
+    if (o.kind == OP_DREG) {
+        uint32_t mask = (uint32_t)o.a;
+        for (int m = 0; mask; ++m, mask &= mask - 1) {
+            double acc = 0.0;
+            on_slot<R>(opaque(mask & (~mask + 1)), [&](auto J) __attribute__((always_inline)) {
+                acc = grad_z_reg<R, std::decay_t<decltype(J)>::value>(a, l);
+            });
+            emit(o.grad_slot + m, wave_sum(acc));
+        }
+    } else {
+        emit(o.grad_slot, wave_sum(grad_term<R>(a, l, o, tid, base)));
+    }
+}
+
 // XOR swizzle of an 8-byte LDS slot: bits 5-9 and 10-14 of the tile position
 // are folded into bits 0-4, so 32 lanes whose positions differ in bits with
 // distinct residues mod 5 hit distinct bank pairs.  swz is linear over GF(2):

@@ -59,6 +59,19 @@ struct ParamGate {                    // a rotation whose matrix is formed from 
     int32_t pad;
 };
 
+// A register diagonal formed on the device from the angles of the RZ rotations
+// it folds (one per member register slot, slots in increasing order): entry u
+// is exp(i/2 sum_m (2 u_{slot m} - 1) theta_m).  Its op is an OP_DREG whose
+// field a holds the member slots' mask and whose gradient slots are
+// grad_slot + m for member m.
+struct ParamDiag {
+    int32_t mat;                      // pool offset of its 2^R complex entries
+    int32_t n;                        // members
+    int32_t slot[MAX_R];
+    int32_t theta[MAX_R];             // absolute theta index of each member
+    int32_t gmat[MAX_R];              // pool offset of each member's own RZ matrix
+};
+
 struct Plan {
     int n = 0, n_circuits = 0, k = 0, t = 0, R = 0, LW = 0;
     uint32_t flags = 0;
@@ -74,6 +87,7 @@ struct Plan {
     std::vector<DevPart> parts;
     std::vector<float> pool;
     std::vector<ParamGate> pgates;
+    std::vector<ParamDiag> pdiags;    // register diagonals folded from parameterised RZ rotations
     std::vector<int32_t> grad_param;  // grad slot -> absolute theta index
     std::vector<int32_t> param_off, param_slots;  // theta index -> its grad slots (CSR, slot order)
     // batched plans: per-circuit stage ranges (single tile per circuit)
@@ -107,6 +121,7 @@ struct Plan {
     DevPart *d_parts = nullptr;
     float *d_pool = nullptr;
     ParamGate *d_pgates = nullptr;
+    ParamDiag *d_pdiags = nullptr;
     int32_t *d_grad_param = nullptr;
     int32_t *d_param_off = nullptr;
     int32_t *d_param_slots = nullptr;

@@ -8,7 +8,9 @@ namespace qsv {
 
 bool kernel_shape_supported(int R, int LW);
 hipError_t launch_sweep(const Plan &plan, int R, int LW, int pidx, float2 *psi, float2 *ckpt, hipStream_t s);
-hipError_t launch_materialize(const Plan &plan, const double *theta, hipStream_t s);
+// Rotation matrices (and, with diags, the register diagonals folded from
+// parameterised RZ rotations) formed from theta in the plan's pool.
+hipError_t launch_materialize(const Plan &plan, const double *theta, hipStream_t s, bool diags = true);
 
 // expect.hip
 constexpr int EXPECT_TILE_QUBITS = 12;   // tiles of 4096 amplitudes, 32 KiB of LDS

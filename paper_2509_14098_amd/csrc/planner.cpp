@@ -386,6 +386,11 @@ struct StageLowering {
     Diag pre, post;
     std::vector<std::pair<int, std::array<double, 4>>> rots;  // (register slot, real matrix)
     uint32_t rot_mask = 0;
+    // parameterised RZ rotations on register slots, pending as one register
+    // diagonal formed on the device (they commute with each other and with
+    // everything that acts on other slots or only diagonally)
+    std::vector<std::pair<int, int>> prz;  // (register slot, gate)
+    uint32_t prz_mask = 0;
 
     StageLowering(Plan &P_, const std::vector<int32_t> &mo, int R_, std::function<int32_t(int)> loc_,
                   const CircuitPlan &C_)
@@ -482,10 +487,66 @@ struct StageLowering {
         pre = post;
         post = Diag(NA);
     }
-    void flush_all(int gate)
+    // the pending fixed block (rotations and diagonals); the pending
+    // parameterised diagonal commutes with it and may stay
+    void flush_fixed(int gate)
     {
         flush_rots(gate);
         emit_diag(pre, gate);
+    }
+    void flush_all(int gate)
+    {
+        flush_fixed(gate);
+        flush_prz();
+    }
+    // the pending parameterised RZ rotations as one OP_DREG: entries formed on
+    // the device (ParamDiag), one gradient slot per member in slot order
+    void flush_prz()
+    {
+        if (prz.empty()) return;
+        std::sort(prz.begin(), prz.end());
+        DevOp o = base_op(OP_DREG, prz[0].second);
+        o.gen = GEN_Z;
+        o.a = (int32_t)prz_mask;
+        o.mat = (int32_t)P.pool.size();
+        P.pool.insert(P.pool.end(), (size_t)2 * NA, 0.f);
+        while (P.pool.size() % 8) P.pool.push_back(0.f);
+        o.grad_slot = (int32_t)P.grad_param.size();
+        ParamDiag pd;
+        std::memset(&pd, 0, sizeof(pd));
+        pd.mat = o.mat;
+        pd.n = (int32_t)prz.size();
+        for (size_t m = 0; m < prz.size(); ++m) {
+            const int32_t th = (int32_t)(C.theta_off + P.gates[prz[m].second].param);
+            pd.slot[m] = prz[m].first;
+            pd.theta[m] = th;
+            pd.gmat[m] = mat_of[prz[m].second];
+            P.grad_param.push_back(th);
+        }
+        P.pdiags.push_back(pd);
+        add(o, 6);
+        prz.clear();
+        prz_mask = 0;
+    }
+    // a parameterised RZ on a register slot: joins the pending diagonal
+    bool is_prz(int g) const
+    {
+        const GateMeta &m = meta[g];
+        return m.param && P.gates[g].kind == QSV_RZ && is_reg(loc(m.q[0]));
+    }
+    // gate g acts non-diagonally on a slot of the pending diagonal (a control
+    // of CX/CU on such a slot does not)
+    bool breaks_prz(int g) const
+    {
+        if (!prz_mask) return false;
+        const GateMeta &m = meta[g];
+        if (m.op == OP_D1 || m.op == OP_D2 || m.op == OP_CZ) return false;
+        auto on = [&](int q) {
+            const int32_t l = loc(q);
+            return is_reg(l) && ((prz_mask >> (l & 0x3F)) & 1u);
+        };
+        if (m.op == OP_CX || m.op == OP_CU) return on(m.tgt);
+        return on(m.q[0]) || (m.nq == 2 && on(m.q[1]));
     }
     // value of a gate's diagonal entry for register index i (all qubits in registers)
     cd diag_value(const GateMeta &m, int32_t la, int32_t lb, int i) const
@@ -547,6 +608,8 @@ struct StageLowering {
     bool absorbs(int g) const
     {
         const GateMeta &m = meta[g];
+        if (is_prz(g)) return !((prz_mask >> (loc(m.q[0]) & 0x3F)) & 1u);
+        if (breaks_prz(g)) return false;
         const bool pending = !rots.empty() || !pre.identity() || !post.identity();
         if (m.param) return !pending;
         if (m.op == OP_D1 || m.op == OP_D2 || m.op == OP_CZ) {
@@ -569,8 +632,17 @@ struct StageLowering {
         const GateMeta &m = meta[g];
         if (!fold) { emit_plain(g); return; }
         const bool diag = m.op == OP_D1 || m.op == OP_D2 || m.op == OP_CZ;
-        if (m.param) {  // matrix formed on the device: ends the block
-            flush_all(g);
+        if (is_prz(g)) {
+            const int j = loc(m.q[0]) & 0x3F;
+            if ((prz_mask >> j) & 1u) flush_prz();   // a second one on the slot: the first goes out
+            if ((rot_mask >> j) & 1u) flush_rots(g); // a pending rotation on the slot comes first
+            prz.push_back({j, g});
+            prz_mask |= 1u << j;
+            return;
+        }
+        if (breaks_prz(g)) flush_prz();  // commutes with everything pending on other slots
+        if (m.param) {  // matrix formed on the device: ends the fixed block
+            flush_fixed(g);
             emit_plain(g);
             return;
         }
@@ -627,7 +699,7 @@ struct StageLowering {
             pre = moved;
             return;
         }
-        flush_all(g);
+        flush_fixed(g);
         emit_plain(g);
     }
 };
@@ -812,7 +884,7 @@ void build_plan(Plan &P)
     // gradient slots, both by a constant offset
     const bool batched = P.circ.size() > 1;
     std::unordered_map<uint64_t, std::vector<int>> by_hash;
-    struct Span { int32_t pool0 = 0, pool1 = 0, slot0 = 0, slot1 = 0; double flops = 0; };
+    struct Span { int32_t pool0 = 0, pool1 = 0, slot0 = 0, slot1 = 0, pd0 = 0, pd1 = 0; double flops = 0; };
     std::vector<Span> span(P.circ.size());
     P.circ_pool_delta.assign(P.circ.size(), 0);
     P.circ_slot_delta.assign(P.circ.size(), 0);
@@ -836,6 +908,7 @@ void build_plan(Plan &P)
         }
         span[ci].pool0 = (int32_t)P.pool.size();
         span[ci].slot0 = (int32_t)P.grad_param.size();
+        span[ci].pd0 = (int32_t)P.pdiags.size();
         if (first >= 0) {  // reuse the tables of circuit `first`
             const CircuitPlan &E = P.circ[first];
             const Span &se = span[first];
@@ -857,6 +930,15 @@ void build_plan(Plan &P)
                     P.pgates.push_back(pg);
                 }
             }
+            span[ci].pd0 = (int32_t)P.pdiags.size();
+            for (int32_t d = se.pd0; d < se.pd1; ++d) {  // its folded diagonals: own pool entries and angles
+                ParamDiag pd = P.pdiags[d];
+                pd.mat += P.circ_pool_delta[ci];
+                for (int m = 0; m < pd.n; ++m) pd.gmat[m] += P.circ_pool_delta[ci];
+                for (int m = 0; m < pd.n; ++m) pd.theta[m] += (int32_t)(C.theta_off - E.theta_off);
+                P.pdiags.push_back(pd);
+            }
+            span[ci].pd1 = (int32_t)P.pdiags.size();
             C.parts = E.parts;
             for (auto &pt : C.parts)
                 for (int &g : pt.gates) g += (int)dg;
@@ -955,7 +1037,8 @@ void build_plan(Plan &P)
                 };
                 ds.op_begin = (int32_t)P.ops.size();
                 // lower with diagonal folding; keep it only if it needs fewer instructions
-                const size_t ops0 = P.ops.size(), pool0 = P.pool.size(), grad0 = P.grad_param.size();
+                const size_t ops0 = P.ops.size(), pool0 = P.pool.size(), grad0 = P.grad_param.size(),
+                             pd0 = P.pdiags.size();
                 const double flops0 = P.flops;
                 double plain_cost = 0, folded_cost = 0;
                 for (int g : s.gates) plain_cost += op_cost(P.meta[g].op) + 2;  // + dispatch
@@ -973,6 +1056,7 @@ void build_plan(Plan &P)
                     P.ops.resize(ops0);
                     P.pool.resize(pool0);
                     P.grad_param.resize(grad0);
+                    P.pdiags.resize(pd0);
                     P.flops = flops0;
                     StageLowering L(P, mat_of, R, loc, C);
                     for (int g : s.gates) L.gate(g, false);
@@ -987,6 +1071,7 @@ void build_plan(Plan &P)
         }
         span[ci].pool1 = (int32_t)P.pool.size();
         span[ci].slot1 = (int32_t)P.grad_param.size();
+        span[ci].pd1 = (int32_t)P.pdiags.size();
         span[ci].flops = P.flops - flops_c0;
     }
     // batched plans: longest circuits first in the work queue

@@ -5,6 +5,7 @@
 // kernel that instantiates spec_sweep (spec.cuh) for it.  rtc_driver.cpp
 // compiles the programs and keeps the optional code-object cache.
 #include <cstdio>
+#include <map>
 #include <set>
 #include <string>
 #include <vector>
@@ -69,7 +70,8 @@ namespace {
 // qsv_gen::P<p> that refers to them (every float as an exact hexadecimal
 // literal).  Matrices written from theta at apply time (dyn_mats) stay in the
 // device pool; the others are copied in.
-void put_tables(std::string &s, const Plan &plan, int p, const std::set<int32_t> &dyn_mats)
+void put_tables(std::string &s, const Plan &plan, int p, const std::set<int32_t> &dyn_mats,
+                const std::map<int32_t, const ParamDiag *> *expand = nullptr, const char *tag = "")
 {
     char b[1024];
     const DevPart &P = plan.parts[p];
@@ -86,6 +88,23 @@ void put_tables(std::string &s, const Plan &plan, int p, const std::set<int32_t>
         st.op_begin = (int32_t)ops.size();
         for (int k = k0; k < k1; ++k) {
             DevOp o = plan.ops[k];
+            if (expand && o.kind == OP_DREG && o.grad_slot >= 0 && expand->count(o.mat)) {
+                // a register diagonal folded from parameterised RZ rotations, as its
+                // members' own rotations (in a forward kernel their separate
+                // matrices take fewer loads than the 2^R entries)
+                const ParamDiag &pd = *expand->at(o.mat);
+                for (int m = 0; m < pd.n; ++m) {
+                    DevOp e = o;
+                    e.kind = OP_D1;
+                    e.a = LOC_REG | pd.slot[m];
+                    e.b = 0;
+                    e.mat = pd.gmat[m];
+                    e.grad_slot = o.grad_slot + m;
+                    ops.push_back(e);
+                    dyn.push_back(1);
+                }
+                continue;
+            }
             const bool d = o.mat >= 0 && dyn_mats.count(o.mat) > 0;
             if (o.mat >= 0 && !d) {
                 const int nf = pool_floats(o.kind, plan.R);
@@ -103,35 +122,35 @@ void put_tables(std::string &s, const Plan &plan, int p, const std::set<int32_t>
     // Namespace-scope constexpr arrays have internal linkage, so the compiler
     // folds every read of them into the code; static data members of the table
     // type would be inline (weak) symbols that it must load at run time.
-    std::snprintf(b, sizeof b, "namespace qsv_gen {\nconstexpr qsv::DevPart part%d = {%d,%d,%d,%d,", p,
+    std::snprintf(b, sizeof b, "namespace qsv_gen {\nconstexpr qsv::DevPart part%s%d = {%d,%d,%d,%d,", tag, p,
                   lp.stage_begin, lp.stage_end, lp.t, lp.n_glb);
     s += b;
     put_ints(s, lp.tq, 16);
     s += ',';
     put_ints(s, lp.gq, 48);
-    std::snprintf(b, sizeof b, "};\nconstexpr qsv::DevStage stages%d[] = {\n", p);
+    std::snprintf(b, sizeof b, "};\nconstexpr qsv::DevStage stages%s%d[] = {\n", tag, p);
     s += b;
     for (const DevStage &st : stages) put_stage(s, st);
-    std::snprintf(b, sizeof b, "{}};\nconstexpr qsv::DevOp ops%d[] = {\n", p);  // arrays end in an unused entry
+    std::snprintf(b, sizeof b, "{}};\nconstexpr qsv::DevOp ops%s%d[] = {\n", tag, p);  // arrays end in an unused entry
     s += b;
     for (const DevOp &o : ops) put_op(s, o);
-    std::snprintf(b, sizeof b, "{}};\nconstexpr bool dyn%d[] = {", p);
+    std::snprintf(b, sizeof b, "{}};\nconstexpr bool dyn%s%d[] = {", tag, p);
     s += b;
     for (int d : dyn) s += d ? "1," : "0,";
-    std::snprintf(b, sizeof b, "0};\nconstexpr float pool%d[] = {\n", p);
+    std::snprintf(b, sizeof b, "0};\nconstexpr float pool%s%d[] = {\n", tag, p);
     s += b;
     for (size_t i = 0; i < pool.size(); ++i) {
         std::snprintf(b, sizeof b, "%af,%s", (double)pool[i], (i % 8 == 7) ? "\n" : "");
         s += b;
     }
     std::snprintf(b, sizeof b,
-                  "0.f};\nstruct P%d {\n    static constexpr int R = %d, LW = %d;\n"
-                  "    static constexpr const qsv::DevPart &part = part%d;\n"
-                  "    static constexpr const qsv::DevStage *stages = stages%d;\n"
-                  "    static constexpr const qsv::DevOp *ops = ops%d;\n"
-                  "    static constexpr const bool *dyn = dyn%d;\n"
-                  "    static constexpr const float *pool = pool%d;\n};\n}  // namespace qsv_gen\n",
-                  p, plan.R, plan.LW, p, p, p, p, p);
+                  "0.f};\nstruct P%s%d {\n    static constexpr int R = %d, LW = %d;\n"
+                  "    static constexpr const qsv::DevPart &part = part%s%d;\n"
+                  "    static constexpr const qsv::DevStage *stages = stages%s%d;\n"
+                  "    static constexpr const qsv::DevOp *ops = ops%s%d;\n"
+                  "    static constexpr const bool *dyn = dyn%s%d;\n"
+                  "    static constexpr const float *pool = pool%s%d;\n};\n}  // namespace qsv_gen\n",
+                  tag, p, plan.R, plan.LW, tag, p, tag, p, tag, p, tag, p, tag, p);
     s += b;
 }
 
@@ -139,6 +158,7 @@ std::set<int32_t> dynamic_matrices(const Plan &plan)
 {
     std::set<int32_t> dyn_mats;  // pool entries written from theta at apply time
     for (const ParamGate &g : plan.pgates) dyn_mats.insert(g.mat);
+    for (const ParamDiag &d : plan.pdiags) dyn_mats.insert(d.mat);  // (member matrices are pgates' own)
     return dyn_mats;
 }
 
@@ -152,8 +172,14 @@ std::string specialise_source(const Plan &plan, int p0, int p1, bool with_revers
     // straight-line code: the gate bodies' plain arithmetic (see gates.cuh)
     std::string s = "#define QSV_PLAIN_ARITH 1\n#include \"spec.cuh\"\n";
     char b[1024];
+    std::map<int32_t, const ParamDiag *> pdiag_of;  // folded RZ diagonals, by pool offset
+    for (const ParamDiag &d : plan.pdiags) pdiag_of.emplace(d.mat, &d);
     for (int p = p0; p < p1; ++p) {
-        put_tables(s, plan, p, dyn_mats);
+        // the forward kernel applies folded RZ diagonals as their members' own
+        // rotations; the reverse walk keeps the folded form (fewer ops on psi
+        // and lambda)
+        put_tables(s, plan, p, dyn_mats, &pdiag_of);
+        if (with_reverse) put_tables(s, plan, p, dyn_mats, nullptr, "r");
         std::snprintf(b, sizeof b,
                       "extern \"C\" __global__ __launch_bounds__(%d) void qsv_spec_%d(float2 *__restrict__ psi, "
                       "float2 *__restrict__ ckpt, const float *__restrict__ pool)\n"
@@ -165,7 +191,7 @@ std::string specialise_source(const Plan &plan, int p0, int p1, bool with_revers
                           "extern \"C\" __global__ __launch_bounds__(%d) void qsv_rspec_%d(const float2 *__restrict__ "
                           "psi, float2 *__restrict__ lam, const float *__restrict__ pool, double *__restrict__ gpart, "
                           "int64_t slot_stride)\n"
-                          "{\n    qsv::spec_reverse<qsv_gen::P%d>(psi, lam, pool, gpart, slot_stride);\n}\n",
+                          "{\n    qsv::spec_reverse<qsv_gen::Pr%d>(psi, lam, pool, gpart, slot_stride);\n}\n",
                           1 << plan.LW, p, p);
             s += b;
         }
@@ -185,7 +211,9 @@ std::string specialise_batched_source(const Plan &plan)
     std::vector<int> reps;
     for (const CircuitPlan &C : plan.circ)
         if (C.shares < 0) reps.push_back(C.part_begin);
-    for (int p : reps) put_tables(s, plan, p, dyn_mats);
+    std::map<int32_t, const ParamDiag *> pdiag_of;  // folded RZ diagonals, by pool offset
+    for (const ParamDiag &d : plan.pdiags) pdiag_of.emplace(d.mat, &d);
+    for (int p : reps) put_tables(s, plan, p, dyn_mats, &pdiag_of);
     char b[512];
     s += "struct SpecWalk {\n"
          "    static __device__ __forceinline__ void forward(int pidx, const qsv::DevPart *, float2 *lds,\n"

@@ -60,6 +60,37 @@ __global__ void materialize_kernel(const ParamGate *__restrict__ pg, int n, cons
     }
 }
 
+// Register diagonals folded from parameterised RZ rotations: entry u of
+// diagonal i is exp(i/2 sum_m (2 u_{slot m} - 1) theta_m).  One thread per
+// diagonal: each member's e^{-i theta/2} from cos/sin in float64, the entries
+// as products of those factors and their conjugates (float64), rounded to
+// float32.
+__global__ void materialize_diag_kernel(const ParamDiag *__restrict__ pd, int n, int na,
+                                        const double *__restrict__ theta, float *__restrict__ pool)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const ParamDiag d = pd[i];
+    double zr[MAX_R], zi[MAX_R];  // e^{-i theta_m / 2}
+    for (int m = 0; m < d.n; ++m) {
+        double s, c;
+        sincos(0.5 * theta[d.theta[m]], &s, &c);
+        zr[m] = c;
+        zi[m] = -s;
+    }
+    float2 *out = reinterpret_cast<float2 *>(pool + d.mat);
+    for (int u = 0; u < na; ++u) {
+        double er = 1.0, ei = 0.0;
+        for (int m = 0; m < d.n; ++m) {
+            const double fi = ((u >> d.slot[m]) & 1) ? -zi[m] : zi[m];  // bit set: the conjugate
+            const double r = er * zr[m] - ei * fi;
+            ei = er * fi + ei * zr[m];
+            er = r;
+        }
+        out[u] = float2{(float)er, (float)ei};
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
@@ -104,13 +135,22 @@ hipError_t launch_sweep(const Plan &plan, int R, int LW, int pidx, float2 *psi, 
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_materialize(const Plan &plan, const double *theta, hipStream_t s)
+hipError_t launch_materialize(const Plan &plan, const double *theta, hipStream_t s, bool diags)
 {
     const int n = (int)plan.pgates.size();
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(materialize_kernel, dim3((n + 255) / 256), dim3(256), 0, s, plan.d_pgates, n, theta,
-                       plan.d_pool);
-    return hipGetLastError();
+    if (n > 0) {
+        hipLaunchKernelGGL(materialize_kernel, dim3((n + 255) / 256), dim3(256), 0, s, plan.d_pgates, n, theta,
+                           plan.d_pool);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const int nd = (int)plan.pdiags.size(), na = 1 << plan.R;
+    if (nd > 0 && diags) {
+        hipLaunchKernelGGL(materialize_diag_kernel, dim3((uint32_t)((nd + 255) / 256)), dim3(256), 0, s,
+                           plan.d_pdiags, nd, na, theta, plan.d_pool);
+        return hipGetLastError();
+    }
+    return hipSuccess;
 }
 
 }  // namespace qsv

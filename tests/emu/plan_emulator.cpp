@@ -103,6 +103,24 @@ extern "C" int emu_run_dist(int n, const qsv_gate *gates, int ng, const double *
         else if (g.kind == QSV_RZ) { m[0] = (float)c; m[1] = (float)-s; m[6] = (float)c; m[7] = (float)s; }
         else { m[0] = (float)c; m[1] = (float)-s; m[2] = (float)c; m[3] = (float)s; m[4] = (float)c; m[5] = (float)s; m[6] = (float)c; m[7] = (float)-s; }
     }
+    for (const ParamDiag &d : P.pdiags) {  // folded RZ rotations, as the device forms them
+        double zr[MAX_R], zi[MAX_R];
+        for (int m = 0; m < d.n; ++m) {
+            zr[m] = std::cos(0.5 * theta[d.theta[m]]);
+            zi[m] = -std::sin(0.5 * theta[d.theta[m]]);
+        }
+        for (int u = 0; u < (1 << P.R); ++u) {
+            double er = 1.0, ei = 0.0;
+            for (int m = 0; m < d.n; ++m) {
+                const double fi = ((u >> d.slot[m]) & 1) ? -zi[m] : zi[m];
+                const double r = er * zr[m] - ei * fi;
+                ei = er * fi + ei * zr[m];
+                er = r;
+            }
+            pool[d.mat + 2 * u] = (float)er;
+            pool[d.mat + 2 * u + 1] = (float)ei;
+        }
+    }
     for (const DevOp &o : P.ops) g_kind_counts[o.kind & 31]++;
     std::vector<float2> psi(size_t(1) << n);
     std::memcpy(psi.data(), state, psi.size() * sizeof(float2));
