@@ -165,3 +165,19 @@ def test_parameterised_rotations_large_angles(emu, R, LW):
     assert np.max(np.abs(out - ref)) < 1e-5
     back = emu(n, gates, 8, R, LW, theta, inverse=True, state=out)
     assert abs(back[0] - 1) < 1e-5 and np.max(np.abs(back[1:])) < 1e-5
+
+
+def test_parameterised_rz_rotations_fold_into_register_diagonals(emu):
+    """The ansatz's RZ rotations on register slots fold into register
+    diagonals formed from theta (OP_DREG ops, fewer than the RZ gates), and
+    the plan still gives the oracle's state for random angles."""
+    n, layers = 12, 3
+    gates, npar = W.ansatz(n, layers)
+    theta = np.random.default_rng(8).uniform(-np.pi, np.pi, size=npar)
+    emu.kind_counts(reset=True)
+    out = emu(n, gates, n, 4, 8, theta)
+    counts = emu.kind_counts(reset=True)
+    n_rz = n * layers
+    assert counts[OP_KINDS["DREG"]] > 0
+    assert counts[OP_KINDS["D1"]] + counts[OP_KINDS["D1_T"]] < n_rz
+    assert np.max(np.abs(out - oracle.apply(n, gates, theta))) < 1e-5
