@@ -62,20 +62,23 @@ __device__ __forceinline__ T uniform(const T &x)
 
 // One launch covers every pass: workgroup (x, pass, b) walks tiles x, x +
 // gridDim.x, ... of state b with the pass's tile qubits.  A thread holds 8
-// amplitude pairs of the tile (positions 2 tid + j + 1024 it, j < 2, it < 4),
-// read as 16-byte pairs (qubit 0 is always a tile qubit).  Partner amplitudes
+// amplitudes of the tile (positions 2 tid + j + 1024 it, j < 2, it < 4), read
+// as 16-byte pairs (qubit 0 is always a tile qubit).  Partner amplitudes
 // of the pass's X/Y groups come from the LDS copy of the tile, those of wide
 // groups (masks that do not fit a tile with the low qubits) from HBM.  The
 // pass's group and term tables are copied to LDS first when they fit: on a
 // small state a workgroup sees one tile, and reading them from memory group by
 // group would put one memory latency per group on its critical path.
 // partials[(b * n_passes + pass) * gridDim.x + block]
+//
+// Registers are capped at 128 per lane (4 waves per SIMD): two workgroups per
+// compute unit, so one workgroup's tile load overlaps the other's arithmetic;
+// at 3 waves per SIMD (one workgroup) the large-state pass lost a third of its
+// bandwidth.
 template <bool SMALL>
-__global__ __launch_bounds__(EXPECT_THREADS) void expect_kernel(const DevPass *__restrict__ passes, int p0,
-                                                              int n_passes, const DevGroup *__restrict__ groups,
-                                                              const DevTerm *__restrict__ terms, int n,
-                                                              const float2 *__restrict__ psi,
-                                                              double *__restrict__ partials)
+__global__ __launch_bounds__(EXPECT_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void expect_kernel(
+    const DevPass *__restrict__ passes, int p0, int n_passes, const DevGroup *__restrict__ groups,
+    const DevTerm *__restrict__ terms, int n, const float2 *__restrict__ psi, double *__restrict__ partials)
 {
     typedef float nf4 __attribute__((ext_vector_type(4)));  // a vector type the builtin accepts
     __shared__ float4 lds4[(1 << EXPECT_TILE_QUBITS) / 2];
@@ -196,26 +199,53 @@ __global__ __launch_bounds__(EXPECT_THREADS) void expect_kernel(const DevPass *_
                         acc += p0v * w[2 * it] + p1v * w[2 * it + 1];
                     }
                 } else if (G.xt >= 0) {
-                    // partners in the LDS tile: the pairs (p0, p1 = p0 ^ xt) of tile
-                    // positions with bit lb of p0 clear, k = tid + 512 i enumerating
-                    // them; per term, with z = conj(psi_p1) psi_p0 and signs from
-                    // the term's Z mask on the tile (zt) and outside it (base):
-                    //   s0 Re[c z] + s1 Re[c conj(z)]
+                    // partners in the tile: the pairs (p0, p1 = p0 ^ xt) of tile
+                    // positions with bit lb of p0 clear; per term, with
+                    // z = conj(psi_p1) psi_p0 and signs from the term's Z mask on the
+                    // tile (zt) and outside it (base):  s0 Re[c z] + s1 Re[c conj(z)]
                     const uint32_t xt = (uint32_t)G.xt;
                     const int lb = __builtin_ctz(xt);
                     const uint32_t below = (1u << lb) - 1;
+                    // f(p0, psi_p0, psi_p1) for every pair of the tile, in a fixed order
+                    auto for_pairs = [&](auto &&f) __attribute__((always_inline)) {
+                        if (xt == 1u) {
+                            // X on position 0 alone: the partner is the other half of the
+                            // thread's own 16-byte pair
+#pragma unroll
+                            for (int it = 0; it < EXPECT_PAIRS; ++it)
+                                if (2 * tid + ROW * it < tdim)
+                                    f(2 * tid + ROW * it, float2{v[it].x, v[it].y}, float2{v[it].z, v[it].w});
+                        } else if (lb >= 1) {
+                            // pairs k and k + 1 (k even) are the adjacent positions p0 and
+                            // p0 + 1 and their partners: one 16-byte LDS read for each side
+#pragma unroll
+                            for (int i = 0; i < EXPECT_PAIRS / 2; ++i) {
+                                const uint32_t k = 2u * (tid + (uint32_t)EXPECT_THREADS * i);
+                                if (k >= (tdim >> 1)) continue;
+                                const uint32_t q0 = ((k >> lb) << (lb + 1)) | (k & below);
+                                const float4 a4 = lds4[q0 >> 1], c4 = lds4[(q0 ^ xt) >> 1];
+                                f(q0, float2{a4.x, a4.y}, float2{c4.x, c4.y});
+                                f(q0 | 1u, float2{a4.z, a4.w}, float2{c4.z, c4.w});
+                            }
+                        } else {
+#pragma unroll
+                            for (int i = 0; i < EXPECT_PAIRS; ++i) {
+                                const uint32_t k = tid + (uint32_t)EXPECT_THREADS * i;
+                                if (k >= (tdim >> 1)) continue;
+                                const uint32_t q0 = ((k >> lb) << (lb + 1)) | (k & below);
+                                f(q0, lds[q0], lds[q0 ^ xt]);
+                            }
+                        }
+                    };
                     const DevTerm T0 = uniform(TP[G.term_begin - tb]);
+                    // a single real X string (the common case) takes the 16-byte
+                    // reads; any other group reads pair by pair, k = tid + 512 i
                     if (G.term_end - G.term_begin == 1 && T0.z_mask == 0 && T0.cim == 0.0) {
                         // one real X string: 2 c Re z summed over the pairs
                         double gz = 0.0;
-#pragma unroll
-                        for (int i = 0; i < EXPECT_PAIRS; ++i) {
-                            const uint32_t k = tid + (uint32_t)EXPECT_THREADS * i;
-                            if (k >= (tdim >> 1)) continue;
-                            const uint32_t q0 = ((k >> lb) << (lb + 1)) | (k & below);
-                            const float2 a = lds[q0], c = lds[q0 ^ xt];
+                        for_pairs([&](uint32_t, float2 a, float2 c) __attribute__((always_inline)) {
                             gz += (double)c.x * a.x + (double)c.y * a.y;
-                        }
+                        });
                         acc += 2.0 * T0.cre * gz;
                         continue;
                     }
