@@ -608,30 +608,16 @@ __device__ __forceinline__ void apply_op_dag2(float2 (&a)[1 << R], float2 (&l)[1
 
 // ---------------------------------------------------------------------------
 // Adjoint helpers: Im <lambda|P|psi> for the generator P of a rotation
-// exp(-i a P / 2), over one thread's amplitudes, in float64.
-// float -> double conversion ordered after acc has been computed (keeps the
-// converted values of later terms from all being live at once)
-__device__ __forceinline__ double cvt_after(float f, double acc)
-{
-#if defined(__HIP_DEVICE_COMPILE__)
-    double d;
-    asm("v_cvt_f64_f32 %0, %1" : "=v"(d) : "v"(f), "v"(acc));
-    return d;
-#else
-    (void)acc;
-    return (double)f;
-#endif
-}
-// acc + Im(conj(l) a), acc + Re(conj(l) a): exact products in float64
+// exp(-i a P / 2), over one thread's amplitudes: each amplitude's product in
+// float32 (one multiply and one fused multiply-add, relative error 2^-23 of
+// its terms, below the float32 state's own rounding), the sum in float64.
 __device__ __forceinline__ double acc_im(double acc, float2 l, float2 a)
 {
-    acc = __builtin_fma(cvt_after(l.x, acc), cvt_after(a.y, acc), acc);
-    return __builtin_fma(-cvt_after(l.y, acc), cvt_after(a.x, acc), acc);
+    return acc + (double)__builtin_fmaf(l.x, a.y, -(l.y * a.x));  // acc + Im(conj(l) a)
 }
 __device__ __forceinline__ double acc_re(double acc, float2 l, float2 a)
 {
-    acc = __builtin_fma(cvt_after(l.x, acc), cvt_after(a.x, acc), acc);
-    return __builtin_fma(cvt_after(l.y, acc), cvt_after(a.y, acc), acc);
+    return acc + (double)__builtin_fmaf(l.x, a.x, l.y * a.y);  // acc + Re(conj(l) a)
 }
 
 template <int R, int J, bool Y>
@@ -748,6 +734,100 @@ __device__ __forceinline__ double wave_sum(double v)
 #endif
 }
 
+#if defined(__HIP_DEVICE_COMPILE__)
+// Lane exchange between two float64 registers: with H32, lanes 32-63 of x
+// trade places with lanes 0-31 of y (v_permlane32_swap); otherwise the odd
+// 16-lane rows of x with the even rows of y (v_permlane16_swap).
+template <bool H32>
+__device__ __forceinline__ void lane_swap(double &x, double &y)
+{
+    const uint64_t bx = __builtin_bit_cast(uint64_t, x), by = __builtin_bit_cast(uint64_t, y);
+    const uint32_t xl = (uint32_t)bx, xh = (uint32_t)(bx >> 32), yl = (uint32_t)by, yh = (uint32_t)(by >> 32);
+    uint32_t lo0, lo1, hi0, hi1;
+    if constexpr (H32) {
+        const auto lo = __builtin_amdgcn_permlane32_swap(xl, yl, false, false);
+        const auto hi = __builtin_amdgcn_permlane32_swap(xh, yh, false, false);
+        lo0 = lo[0], lo1 = lo[1], hi0 = hi[0], hi1 = hi[1];
+    } else {
+        const auto lo = __builtin_amdgcn_permlane16_swap(xl, yl, false, false);
+        const auto hi = __builtin_amdgcn_permlane16_swap(xh, yh, false, false);
+        lo0 = lo[0], lo1 = lo[1], hi0 = hi[0], hi1 = hi[1];
+    }
+    x = __builtin_bit_cast(double, ((uint64_t)hi0 << 32) | lo0);
+    y = __builtin_bit_cast(double, ((uint64_t)hi1 << 32) | lo1);
+}
+#endif
+
+// Four wave sums at once (float64, a fixed order; the results are uniform).
+// Two rounds of lane swaps leave, in each 16-lane row, one value's partials
+// over the four rows (row 0: v0, row 1: v2, row 2: v1, row 3: v3); a
+// reduction within rows finishes all four together: 6 swaps, 7 additions and
+// 4 row steps instead of 4 x 6 exchange steps.
+__device__ __forceinline__ void wave_sum4(double (&v)[4])
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    lane_swap<true>(v[0], v[1]);
+    double p = v[0] + v[1];  // lanes 0-31: v0's two halves, lanes 32-63: v1's
+    lane_swap<true>(v[2], v[3]);
+    double q = v[2] + v[3];  // the same for v2 and v3
+    lane_swap<false>(p, q);
+    double r = p + q;        // rows: v0, v2, v1, v3, each over the four rows
+    r += dpp_f64<0xB1, 0xF>(r);   // quad_perm [1, 0, 3, 2]
+    r += dpp_f64<0x4E, 0xF>(r);   // quad_perm [2, 3, 0, 1]
+    r += dpp_f64<0x141, 0xF>(r);  // row_half_mirror
+    r += dpp_f64<0x140, 0xF>(r);  // row_mirror: every lane of a row holds its total
+    const uint64_t b = __builtin_bit_cast(uint64_t, r);
+    const int lanes[4] = {0, 32, 16, 48};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lanes[j]);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lanes[j]);
+        v[j] = __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+    }
+#else
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = wave_sum(v[j]);
+#endif
+}
+
+// Im <lambda|Z_j|psi> summed over the wave for the register slots j of mask
+// (at least two of them): out[j], uniform; slots outside mask get 0.  Each
+// amplitude's product is formed once and added, with the slot's sign, to
+// every slot's float64 sum.
+template <int R>
+__device__ __forceinline__ void grad_z_members(const float2 (&a)[1 << R], const float2 (&l)[1 << R], uint32_t mask,
+                                               double (&out)[R])
+{
+#pragma unroll
+    for (int j = 0; j < R; ++j) out[j] = 0.0;
+#pragma unroll
+    for (int i = 0; i < (1 << R); ++i) {
+        const double m = (double)__builtin_fmaf(l[i].x, a[i].y, -(l[i].y * a[i].x));  // Im(conj(l) a)
+#pragma unroll
+        for (int j = 0; j < R; ++j) out[j] += ((i >> j) & 1) ? -m : m;
+    }
+#pragma unroll
+    for (int j0 = 0; j0 < R; j0 += 4) {
+        double v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = (j0 + k < R && ((mask >> (j0 + k)) & 1u)) ? out[j0 + k] : 0.0;
+        const uint32_t cm = (mask >> j0) & 15u;
+        if (__builtin_popcount(cm) == 1) {  // one slot in this group of four
+            double x = 0.0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) x = ((cm >> k) & 1u) ? v[k] : x;
+            x = wave_sum(x);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = ((cm >> k) & 1u) ? x : 0.0;
+        } else if (cm) {
+            wave_sum4(v);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (j0 + k < R) out[j0 + k] = v[k];
+    }
+}
+
 // The gradient partials of op o (float64, summed over the wave): the one of
 // its rotation, or, for a register diagonal folded from parameterised RZ
 // rotations (OP_DREG with a gradient slot), one per member: the members are
@@ -759,6 +839,14 @@ __device__ __forceinline__ void grad_partials(const float2 (&a)[1 << R], const f
 {
     if (o.kind == OP_DREG) {
         uint32_t mask = (uint32_t)o.a;
+        if (__builtin_popcount(mask) >= 2) {
+            double v[R];
+            grad_z_members<R>(a, l, mask, v);
+#pragma unroll
+            for (int j = 0, m = 0; j < R; ++j)
+                if ((mask >> j) & 1u) emit(o.grad_slot + m++, v[j]);
+            return;
+        }
         for (int m = 0; mask; ++m, mask &= mask - 1) {
             double acc = 0.0;
             on_slot<R>(opaque(mask & (~mask + 1)), [&](auto J) __attribute__((always_inline)) {

@@ -188,11 +188,15 @@ __device__ __forceinline__ void spec_reverse_stage(float2 *lds_psi, float2 *lds_
             // a register diagonal folded from parameterised RZ rotations: one
             // partial per member slot (slots grad_slot + m in slot order)
             constexpr uint32_t mask = (uint32_t)T::ops[K].a;
+            double vm[R];
+            if constexpr (__builtin_popcount(mask) >= 2) grad_z_members<R>(a, l, mask, vm);
             static_for<0, R>([&](auto J) __attribute__((always_inline)) {
                 constexpr int j = std::decay_t<decltype(J)>::value;
                 if constexpr ((mask >> j) & 1u) {
                     constexpr int m = __builtin_popcount(mask & ((1u << j) - 1u));
-                    const double v = wave_sum(grad_z_reg<R, j>(a, l));
+                    double v;
+                    if constexpr (__builtin_popcount(mask) >= 2) v = vm[j];
+                    else v = wave_sum(grad_z_reg<R, j>(a, l));
                     if ((tid & 63) == 0) gpart[(int64_t)(T::ops[K].grad_slot + m) * slot_stride + part_index] = v;
                 }
             });
