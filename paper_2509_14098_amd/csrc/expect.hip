@@ -206,16 +206,19 @@ __global__ __launch_bounds__(EXPECT_THREADS) __attribute__((amdgpu_waves_per_eu(
                     const uint32_t xt = (uint32_t)G.xt;
                     const int lb = __builtin_ctz(xt);
                     const uint32_t below = (1u << lb) - 1;
-                    // f(p0, psi_p0, psi_p1) for every pair of the tile, in a fixed order
+                    // f(p0, psi_p0, psi_p1) for every pair of the tile, in a fixed order;
+                    // the 16-byte reads only on cached states, where the LDS reads
+                    // weigh (a streamed state is bound by HBM, and the extra registers
+                    // slowed its loads)
                     auto for_pairs = [&](auto &&f) __attribute__((always_inline)) {
-                        if (xt == 1u) {
+                        if (SMALL && xt == 1u) {
                             // X on position 0 alone: the partner is the other half of the
                             // thread's own 16-byte pair
 #pragma unroll
                             for (int it = 0; it < EXPECT_PAIRS; ++it)
                                 if (2 * tid + ROW * it < tdim)
                                     f(2 * tid + ROW * it, float2{v[it].x, v[it].y}, float2{v[it].z, v[it].w});
-                        } else if (lb >= 1) {
+                        } else if (SMALL && lb >= 1) {
                             // pairs k and k + 1 (k even) are the adjacent positions p0 and
                             // p0 + 1 and their partners: one 16-byte LDS read for each side
 #pragma unroll
