@@ -56,42 +56,82 @@ __device__ __forceinline__ void remap(float2 (&v)[1 << R], float2 *lds, bool act
     }
 }
 
+// f(integral_constant<int, i>) for i = B, B + S, ... below E, unrolled.
+template <int B, int E, int S, typename F>
+__device__ __forceinline__ void chunk_for(F &&f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        chunk_for<B + S, E, S>(static_cast<F &&>(f));
+    }
+}
+
 // psi (a) and lambda = H psi (l) in the register layout (toff, roff), psi read
 // from the LDS tile (positions are the qubits in order); the circuit's energy
 // <psi|H|psi> (float64, waves in order) goes to *energy_out.
+//
+// Amplitude x_i of the thread has position tpos ^ rpos_i (thread part, and the
+// uniform register part of slot i); swz is linear and its own inverse on
+// these slots, so the partner x_i ^ X of a Pauli group sits at slot
+// swz(tpos) ^ swz(rpos_i ^ X), and a term's sign (-1)^{|(x_i ^ X) & Z|} is the
+// thread's parity of tpos & Z times the uniform parity of (rpos_i ^ X) & Z.
+// The amplitudes are taken four at a time, each group and term record loaded
+// once per four (not once per amplitude), with float64 sums per amplitude.  At
+// 1024 threads this leaves a few per-circuit values spilled (outside the op
+// loop); the gradient from final states still ran 1.8 % faster.
 template <int R, int LW>
 __device__ __forceinline__ void batch_energy(const float2 *lds, bool active, uint32_t toff,
                                              const uint32_t (&roff)[1 << R], const DevGroup *__restrict__ groups,
                                              const DevTerm *__restrict__ terms, int n_groups, float2 (&a)[1 << R],
                                              float2 (&l)[1 << R], double *s_red, double *energy_out, uint32_t tid)
 {
-    constexpr int NA = 1 << R, WAVES = (1 << LW) / 64;
-    double e_part = 0.0;
+    constexpr int NA = 1 << R, WAVES = (1 << LW) / 64, C = NA < 4 ? NA : 4;
+    const uint32_t tslot = toff >> 3, tpos = swz(tslot);
+    uint32_t rpos[NA];
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
-        a[i] = float2{0.f, 0.f};
+        rpos[i] = swz(roff[i] >> 3);
+        a[i] = active ? lds[tslot ^ (roff[i] >> 3)] : float2{0.f, 0.f};
         l[i] = float2{0.f, 0.f};
-        if (active) {
-            const uint32_t sx = (toff ^ roff[i]) >> 3;  // swizzled slot of amplitude x
-            const uint32_t x = swz(sx);          // swz is an involution here: recovers x
-            a[i] = lds[sx];
-            double lr = 0.0, li = 0.0;
+    }
+    double e_part = 0.0;
+    if (active) {
+        chunk_for<0, NA, C>([&](auto c0c) __attribute__((always_inline)) {
+            constexpr int c0 = decltype(c0c)::value;
+            double lr[C], li[C];
+#pragma unroll
+            for (int j = 0; j < C; ++j) lr[j] = li[j] = 0.0;
             for (int g = 0; g < n_groups; ++g) {
                 const DevGroup G = groups[g];
-                const uint32_t y = x ^ (uint32_t)G.x_mask;
-                const float2 py = lds[swz(y)];
-                double wr = 0.0, wi = 0.0;
+                const uint32_t xm = (uint32_t)G.x_mask;
+                double wr[C], wi[C];
+#pragma unroll
+                for (int j = 0; j < C; ++j) wr[j] = wi[j] = 0.0;
                 for (int k = G.term_begin; k < G.term_end; ++k) {
-                    const double sg = (__popcll(y & terms[k].z_mask) & 1) ? -1.0 : 1.0;
-                    wr += sg * terms[k].cre;
-                    wi += sg * terms[k].cim;
+                    const DevTerm T = terms[k];
+                    const uint32_t z = (uint32_t)T.z_mask;
+                    const uint32_t tp = __popc(tpos & z) & 1u;
+#pragma unroll
+                    for (int j = 0; j < C; ++j) {
+                        const uint32_t s = tp ^ (__popc((rpos[c0 + j] ^ xm) & z) & 1u);
+                        wr[j] += s ? -T.cre : T.cre;
+                        wi[j] += s ? -T.cim : T.cim;
+                    }
                 }
-                lr += wr * py.x - wi * py.y;
-                li += wr * py.y + wi * py.x;
+#pragma unroll
+                for (int j = 0; j < C; ++j) {
+                    // (also for X = 0: a select between this read and a[] would put a[] in memory)
+                    const float2 py = lds[tslot ^ swz(rpos[c0 + j] ^ xm)];
+                    lr[j] += wr[j] * py.x - wi[j] * py.y;
+                    li[j] += wr[j] * py.y + wi[j] * py.x;
+                }
             }
-            l[i] = float2{(float)lr, (float)li};
-            e_part += (double)a[i].x * lr + (double)a[i].y * li;
-        }
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                l[c0 + j] = float2{(float)lr[j], (float)li[j]};
+                e_part += (double)a[c0 + j].x * lr[j] + (double)a[c0 + j].y * li[j];
+            }
+        });
     }
     e_part = wave_sum(e_part);
     if ((tid & 63) == 0) s_red[tid >> 6] = e_part;
