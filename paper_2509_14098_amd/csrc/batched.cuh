@@ -84,9 +84,10 @@ __device__ __forceinline__ void chunk_for(F &&f)
 // thread's parity of tpos & Z times the uniform parity of (rpos_i ^ X) & Z.
 // The amplitudes are taken four at a time, each group and term record loaded
 // once per four (not once per amplitude), with float64 sums per amplitude; a
-// group of one term puts its sign on the partner amplitude.  At 1024 threads
-// this leaves a few per-circuit values spilled (outside the op loop); the
-// gradient from final states still ran 3 % faster.
+// group of one term puts its sign on the partner amplitude, a longer group sums
+// its terms per sign pattern over the four.  At 1024 threads this leaves a few
+// per-circuit values spilled (outside the op loop); the gradient from final
+// states still ran 4 % faster.
 template <int R, int LW>
 __device__ __forceinline__ void batch_energy(const float2 *lds, bool active, uint32_t toff,
                                              const uint32_t (&roff)[1 << R], const DevGroup *__restrict__ groups,
@@ -132,18 +133,59 @@ __device__ __forceinline__ void batch_energy(const float2 *lds, bool active, uin
                 double wr[C], wi[C];
 #pragma unroll
                 for (int j = 0; j < C; ++j) wr[j] = wi[j] = 0.0;
-                for (int k = G.term_begin; k < G.term_end; ++k) {
-                    const DevTerm T = terms[k];
-                    const uint32_t z = (uint32_t)T.z_mask;
-                    // the sign as a float64 sign bit: the thread's part, then the
-                    // uniform part of each amplitude (scalar registers)
-                    const uint32_t tsb = (uint32_t)__popc(tpos & z) << 31;
-#pragma unroll
-                    for (int j = 0; j < C; ++j) {
+                if constexpr (C == 4) {
+                    // The chunk's amplitudes differ in register bits 0 and 1 (position
+                    // masks r1, r2), so a term's signs over the chunk are its sign at
+                    // amplitude c0 times chi_p(j) = (-1)^{|j & p|}, p = the term's Z
+                    // bits at r1 and r2 (uniform).  The terms are summed per pattern p
+                    // (b[p]), then w_j = sum_p chi_p(j) b[p].
+                    const uint32_t r1 = rpos[c0 + 1] ^ rpos[c0], r2 = rpos[c0 + 2] ^ rpos[c0];
+                    double br[4] = {0.0, 0.0, 0.0, 0.0}, bi[4] = {0.0, 0.0, 0.0, 0.0};
+                    for (int k = G.term_begin; k < G.term_end; ++k) {
+                        const DevTerm T = terms[k];
+                        const uint32_t z = (uint32_t)T.z_mask;
+                        // the sign at amplitude c0 as a float64 sign bit: the thread's
+                        // part, then the uniform part
                         const uint32_t sb =
-                            tsb ^ (uint32_t)__builtin_amdgcn_readfirstlane((int)((uint32_t)__popc((rpos[c0 + j] ^ xm) & z) << 31));
-                        wr[j] += flip_sign(T.cre, sb);
-                        if (T.cim != 0.0) wi[j] += flip_sign(T.cim, sb);
+                            ((uint32_t)__popc(tpos & z) << 31) ^
+                            (uint32_t)__builtin_amdgcn_readfirstlane((int)((uint32_t)__popc((rpos[c0] ^ xm) & z) << 31));
+                        const int pat = __builtin_amdgcn_readfirstlane((int)(((z & r1) ? 1u : 0u) | ((z & r2) ? 2u : 0u)));
+                        const double ar = flip_sign(T.cre, sb);
+                        if (pat == 0) br[0] += ar;
+                        else if (pat == 1) br[1] += ar;
+                        else if (pat == 2) br[2] += ar;
+                        else br[3] += ar;
+                        if (T.cim != 0.0) {
+                            const double ai = flip_sign(T.cim, sb);
+                            if (pat == 0) bi[0] += ai;
+                            else if (pat == 1) bi[1] += ai;
+                            else if (pat == 2) bi[2] += ai;
+                            else bi[3] += ai;
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const bool neg = __builtin_popcount(j & q) & 1;
+                            wr[j] += neg ? -br[q] : br[q];
+                            wi[j] += neg ? -bi[q] : bi[q];
+                        }
+                    }
+                } else {
+                    for (int k = G.term_begin; k < G.term_end; ++k) {
+                        const DevTerm T = terms[k];
+                        const uint32_t z = (uint32_t)T.z_mask;
+                        // the sign as a float64 sign bit: the thread's part, then the
+                        // uniform part of each amplitude (scalar registers)
+                        const uint32_t tsb = (uint32_t)__popc(tpos & z) << 31;
+#pragma unroll
+                        for (int j = 0; j < C; ++j) {
+                            const uint32_t sb = tsb ^ (uint32_t)__builtin_amdgcn_readfirstlane(
+                                                          (int)((uint32_t)__popc((rpos[c0 + j] ^ xm) & z) << 31));
+                            wr[j] += flip_sign(T.cre, sb);
+                            if (T.cim != 0.0) wi[j] += flip_sign(T.cim, sb);
+                        }
                     }
                 }
 #pragma unroll
