@@ -367,6 +367,98 @@ __global__ __launch_bounds__(RED_THREADS) void apply_h_kernel(const DevGroup *__
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
+// c with its sign bit flipped where bit 31 of sb is set.
+__device__ __forceinline__ float flipf(float c, uint32_t sb) { return __uint_as_float(__float_as_uint(c) ^ sb); }
+__device__ __forceinline__ double flipd(double c, uint32_t sb)
+{
+    return __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, c) ^ ((uint64_t)sb << 32));
+}
+
+// lam = H psi as apply_h_kernel, four amplitudes per thread (n >= 2): the four
+// values x0 + j of qubits 0 and 1, read and written as two 16-byte words.  For
+// a group with X mask m the partners are the four amplitudes at x0 ^ (m & ~3),
+// in the order j ^ (m & 3); a term's sign at amplitude j is its sign at x0
+// times (-1)^{|j & Z|}, so one term costs one parity per four amplitudes.  A
+// group of one term puts its sign on the partner amplitudes; a longer group
+// sums its terms per pattern Z & 3 first.  Group and term records are loaded
+// once per four amplitudes.
+__global__ __launch_bounds__(RED_THREADS) void apply_h4_kernel(const DevGroup *__restrict__ groups, int n_groups,
+                                                                const DevTerm *__restrict__ terms, int n,
+                                                                const float2 *__restrict__ psi,
+                                                                float2 *__restrict__ lam,
+                                                                double *__restrict__ partials)
+{
+    __shared__ double sh[RED_THREADS];
+    const uint64_t nc = 1ull << (n - 2);
+    const uint64_t stride = (uint64_t)gridDim.x * RED_THREADS;
+    const float4 *__restrict__ psi4 = reinterpret_cast<const float4 *>(psi);
+    float4 *__restrict__ lam4 = reinterpret_cast<float4 *>(lam);
+    double acc = 0.0;
+    for (uint64_t c = (uint64_t)blockIdx.x * RED_THREADS + threadIdx.x; c < nc; c += stride) {
+        const uint64_t x0 = c << 2;
+        const float4 pa = psi4[2 * c], pb = psi4[2 * c + 1];
+        const float2 p[4] = {{pa.x, pa.y}, {pa.z, pa.w}, {pb.x, pb.y}, {pb.z, pb.w}};
+        double lr[4] = {0.0, 0.0, 0.0, 0.0}, li[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int g = 0; g < n_groups; ++g) {
+            const DevGroup G = groups[g];
+            const uint64_t xm = G.x_mask;
+            const uint64_t y0 = x0 ^ (xm & ~3ull);
+            const float4 qa = psi4[y0 >> 1], qb = psi4[(y0 >> 1) + 1];
+            float2 r[4] = {{qa.x, qa.y}, {qa.z, qa.w}, {qb.x, qb.y}, {qb.z, qb.w}};
+            if (xm & 1) {  // r[j] = partner of amplitude j = q[j ^ (m & 3)]
+                float2 t = r[0]; r[0] = r[1]; r[1] = t;
+                t = r[2]; r[2] = r[3]; r[3] = t;
+            }
+            if (xm & 2) {
+                float2 t = r[0]; r[0] = r[2]; r[2] = t;
+                t = r[1]; r[1] = r[3]; r[3] = t;
+            }
+            if (G.term_end - G.term_begin == 1) {
+                const DevTerm T = terms[G.term_begin];
+                const uint32_t sb0 = (uint32_t)(__popcll((x0 ^ xm) & T.z_mask) & 1) << 31;
+                const uint32_t zl = (uint32_t)T.z_mask & 3u;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t sb = sb0 ^ ((uint32_t)(__popc((uint32_t)j & zl) & 1) << 31);
+                    const double qx = (double)flipf(r[j].x, sb), qy = (double)flipf(r[j].y, sb);
+                    lr[j] += T.cre * qx - T.cim * qy;
+                    li[j] += T.cre * qy + T.cim * qx;
+                }
+                continue;
+            }
+            double br[4] = {0.0, 0.0, 0.0, 0.0}, bi[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int k = G.term_begin; k < G.term_end; ++k) {
+                const DevTerm T = terms[k];
+                const uint32_t sb = (uint32_t)(__popcll((x0 ^ xm) & T.z_mask) & 1) << 31;
+                const int pat = (int)(T.z_mask & 3u);
+                const double ar = flipd(T.cre, sb), ai = flipd(T.cim, sb);
+                if (pat == 0) br[0] += ar, bi[0] += ai;
+                else if (pat == 1) br[1] += ar, bi[1] += ai;
+                else if (pat == 2) br[2] += ar, bi[2] += ai;
+                else br[3] += ar, bi[3] += ai;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                double wr = 0.0, wi = 0.0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const bool neg = __builtin_popcount(j & q) & 1;
+                    wr += neg ? -br[q] : br[q];
+                    wi += neg ? -bi[q] : bi[q];
+                }
+                lr[j] += wr * r[j].x - wi * r[j].y;
+                li[j] += wr * r[j].y + wi * r[j].x;
+            }
+        }
+        lam4[2 * c] = float4{(float)lr[0], (float)li[0], (float)lr[1], (float)li[1]};
+        lam4[2 * c + 1] = float4{(float)lr[2], (float)li[2], (float)lr[3], (float)li[3]};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc += (double)p[j].x * lr[j] + (double)p[j].y * li[j];
+    }
+    const double tot = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
 int expect_blocks(int n)
 {
     const int t = std::min(n, EXPECT_TILE_QUBITS);
@@ -487,9 +579,9 @@ hipError_t launch_expect(const DevPass *passes, int n_passes, const DevGroup *gr
 
 int apply_h_blocks(int n, int cap)
 {
-    // one amplitude per thread: each amplitude walks every Pauli group with a
-    // dependent table load and gather, so many waves are needed to cover them
-    const uint64_t b = std::max<uint64_t>(1, (1ull << n) / RED_THREADS);
+    // four amplitudes per thread (one below n = 2)
+    const uint64_t per_thread = n >= 2 ? 4 : 1;
+    const uint64_t b = std::max<uint64_t>(1, (1ull << n) / (per_thread * RED_THREADS));
     return (int)std::min<uint64_t>(b, (uint64_t)std::max(cap, 1));
 }
 
@@ -497,8 +589,12 @@ hipError_t launch_apply_h(const DevGroup *groups, int n_groups, const DevTerm *t
                           float2 *lam, double *partials, int n_blocks, double *energy, hipStream_t s)
 {
     const int nb = apply_h_blocks(n, n_blocks);
-    hipLaunchKernelGGL(apply_h_kernel, dim3(nb), dim3(RED_THREADS), 0, s, groups, n_groups, terms, n, psi, lam,
-                       partials);
+    if (n >= 2)
+        hipLaunchKernelGGL(apply_h4_kernel, dim3(nb), dim3(RED_THREADS), 0, s, groups, n_groups, terms, n, psi, lam,
+                           partials);
+    else
+        hipLaunchKernelGGL(apply_h_kernel, dim3(nb), dim3(RED_THREADS), 0, s, groups, n_groups, terms, n, psi, lam,
+                           partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(RED_THREADS), 0, s, partials, nb, energy);
