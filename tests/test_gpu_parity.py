@@ -361,7 +361,8 @@ def random_pauli_sum(n, rng, n_terms=9):
 
 
 @pytest.mark.parametrize("hkind", ["zz+x", "xyz"])
-@pytest.mark.parametrize("n,ng,seed", [(2, 30, 1), (5, 80, 2), (9, 150, 3), (14, 200, 4), (16, 200, 5)])
+@pytest.mark.parametrize("n,ng,seed", [(1, 12, 6), (2, 30, 1), (3, 40, 7), (5, 80, 2), (9, 150, 3), (14, 200, 4),
+                                       (16, 200, 5)])
 def test_adjoint_vs_oracle(sim, n, ng, seed, hkind):
     npar = 6
     rng = np.random.default_rng(seed)
